@@ -1,0 +1,198 @@
+"""Analytic Jacobian and vector-Jacobian product of (hrr, w_1..w_Ns) w.r.t. (T, Y_1..Y_Ns) (oracle).
+
+The paper's integrator needs derivatives of the chemistry source in every Newton
+and Krylov iteration; it approximates J v by difference quotients (Section 2).
+The oracle differentiates the production rates of kinetics.py exactly, by the
+chain rule, with plain loops over reactions:
+
+* rows:    0 = hrr, 1..Ns = w_k;  columns: 0 = T, 1..Ns = Y_j (p fixed, every Y_j
+  independent, no renormalisation);
+* dC_m/dY_j = delta_mj rho / W_m - C_m Wbar / W_j   and   dC_m/dT = -C_m / T;
+* d ln k/dT = (b + theta/T) / T for an Arrhenius constant;
+* d(g/RT)/dT = -(h/RT) / T, hence d ln K_c/dT = (sum_k dnu_k h_k/(RT) - dnu) / T;
+* Troe: closed-form derivatives of F through P_r and F_cent;
+* d hrr/dx = -sum_k h_k dw_k/dx, plus -sum_k cp_k w_k for x = T (dh_k/dT = cp_k).
+
+Pinned by: complex-step differentiation of the forward oracle (exact to rounding),
+central finite differences, and the dot-product identity of the VJP.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .kinetics import production_rates
+from .thermo import mixture_state, nasa7
+
+LN10 = np.log(10.0)
+
+
+def _dlnk_dT(b, theta, T):
+    return (b + theta / T) / T
+
+
+def _troe_parts(T, M, lnA, b, theta, troe):
+    """Returns (kf, dkf/dT at fixed M, dkf/dM at fixed T) for one falloff reaction."""
+    lnA0, b0, th0, alpha, T3, T1, T2 = troe
+    kinf = np.exp(lnA) * T ** b * np.exp(-theta / T)
+    k0 = np.exp(lnA0) * T ** b0 * np.exp(-th0 / T)
+    Pr = k0 * M / kinf
+    Fcent = (1.0 - alpha) * np.exp(-T / T3) + alpha * np.exp(-T / T1) + np.exp(-T2 / T)
+    dFcent = -(1.0 - alpha) / T3 * np.exp(-T / T3) - alpha / T1 * np.exp(-T / T1) \
+        + T2 / T ** 2 * np.exp(-T2 / T)
+    lFc = np.log10(Fcent)
+    c = -0.4 - 0.67 * lFc
+    n = 0.75 - 1.27 * lFc
+    d = 0.14
+    ell = np.log10(Pr)
+    u = ell + c
+    den = n - d * u
+    f1 = u / den
+    logF = lFc / (1.0 + f1 ** 2)
+    F = 10.0 ** logF
+    kf = kinf * Pr / (1.0 + Pr) * F
+    # partial derivatives of log10 F
+    df1_dell = n / den ** 2
+    df1_dlFc = (-0.67 * den - u * (-1.27 + 0.67 * d)) / den ** 2
+    dlogF_dell = -lFc * 2.0 * f1 * df1_dell / (1.0 + f1 ** 2) ** 2
+    dlogF_dlFc = 1.0 / (1.0 + f1 ** 2) - lFc * 2.0 * f1 * df1_dlFc / (1.0 + f1 ** 2) ** 2
+    # temperature at fixed [M]
+    dlnkinf = _dlnk_dT(b, theta, T)
+    dlnk0 = _dlnk_dT(b0, th0, T)
+    dlnPr = dlnk0 - dlnkinf
+    dlFc_dT = dFcent / (Fcent * LN10)
+    dlnF_dT = LN10 * (dlogF_dell * dlnPr / LN10 + dlogF_dlFc * dlFc_dT)
+    dkf_dT = kf * (dlnkinf + dlnPr / (1.0 + Pr) + dlnF_dT)
+    # [M] at fixed T:  d ln kf / d ln Pr = 1/(1+Pr) + dlog10F/dell ;  kf/M = k0 F / (1+Pr)
+    dkf_dM = k0 * F / (1.0 + Pr) * (1.0 / (1.0 + Pr) + dlogF_dell)
+    return kf, dkf_dT, dkf_dM
+
+
+def jacobian(m, T, p, Y):
+    """J [n, Ns+1, Ns+1]: rows (hrr, w_1..Ns), columns (T, Y_1..Ns)."""
+    T = np.asarray(T)
+    p = np.asarray(p)
+    Y = np.asarray(Y)
+    n, ns = Y.shape
+    Wbar, rho, X, C = mixture_state(m, T, p, Y)
+    cpR, hRT, _, gRT = nasa7(m, T)
+    dnu = m.nu_r - m.nu_f
+    lnp0RT = np.log(m.p0 / (m.R * T))
+    dtype = np.result_type(T, Y, p, float)
+    JC = np.zeros((n, ns, ns), dtype=dtype)      # d w_k / d C_j
+    JTC = np.zeros((n, ns), dtype=dtype)         # d w_k / d T at fixed C
+    for i in range(m.n_reactions):
+        M = C @ m.eff[i]
+        if m.kind[i] == "troe":
+            kf, dkf_dT, dkf_dM = _troe_parts(T, M, m.lnA[i], m.b[i], m.theta[i], m.troe[i])
+        else:
+            kf = np.exp(m.lnA[i]) * T ** m.b[i] * np.exp(-m.theta[i] / T)
+            dkf_dT = kf * _dlnk_dT(m.b[i], m.theta[i], T)
+            dkf_dM = np.zeros_like(kf)
+        lnKc = -(gRT * dnu[i][None, :]).sum(axis=1) + dnu[i].sum() * lnp0RT
+        dlnKc_dT = ((hRT * dnu[i][None, :]).sum(axis=1) - dnu[i].sum()) / T
+        invKc = np.exp(-lnKc)
+        reac = np.nonzero(m.nu_f[i])[0]
+        prod = np.nonzero(m.nu_r[i])[0]
+        pf = np.ones(n, dtype=dtype)
+        pr = np.ones(n, dtype=dtype)
+        for k in reac:
+            pf = pf * C[:, k] ** int(m.nu_f[i, k])
+        for k in prod:
+            pr = pr * C[:, k] ** int(m.nu_r[i, k])
+
+        def dprod(species, nu):
+            """d(prod_k C_k^nu_k)/dC_j for each j in `species` (no division by C)."""
+            out = {}
+            for j in species:
+                v = nu[j] * C[:, j] ** int(nu[j] - 1)
+                for k in species:
+                    if k != j:
+                        v = v * C[:, k] ** int(nu[k])
+                out[j] = v
+            return out
+
+        dpf = dprod(reac, m.nu_f[i])
+        dpr = dprod(prod, m.nu_r[i])
+        bracket = pf - invKc * pr                # q = fac * kf * bracket
+        fac = M if m.kind[i] == "threebody" else np.ones_like(M)
+        dq_dC = np.zeros((n, ns), dtype=dtype)
+        for j, v in dpf.items():
+            dq_dC[:, j] += fac * kf * v
+        for j, v in dpr.items():
+            dq_dC[:, j] -= fac * kf * invKc * v
+        if m.kind[i] == "threebody":
+            dq_dC += (kf * bracket)[:, None] * m.eff[i][None, :]
+        elif m.kind[i] == "troe":
+            dq_dC += (dkf_dM * bracket)[:, None] * m.eff[i][None, :]
+        dq_dT = fac * (dkf_dT * bracket + kf * invKc * pr * dlnKc_dT)
+        JC += dnu[i][None, :, None] * dq_dC[:, None, :]
+        JTC += dnu[i][None, :] * dq_dT[:, None]
+    # chain rule to (T, Y)
+    dC_dY = rho[:, None, None] * np.eye(ns)[None] / m.W[None, :, None] \
+        - C[:, :, None] * (Wbar[:, None] / m.W[None, :])[:, None, :]          # [n, m, j]
+    JY = np.einsum("nkm,nmj->nkj", JC, dC_dY)
+    JT = JTC - np.einsum("nkm,nm->nk", JC, C) / T[:, None]
+    w = production_rates(m, T, p, Y)["wdot"]
+    h = m.R * T[:, None] * hRT
+    cp = m.R * cpR
+    J = np.zeros((n, ns + 1, ns + 1), dtype=dtype)
+    J[:, 1:, 0] = JT
+    J[:, 1:, 1:] = JY
+    J[:, 0, 0] = -(h * JT).sum(axis=1) - (cp * w).sum(axis=1)
+    J[:, 0, 1:] = -np.einsum("nk,nkj->nj", h, JY)
+    return J
+
+
+def vjp(m, T, p, Y, u, u_hrr=None):
+    """(gT [n], gY [n, Ns]) = u^T J with u [n, Ns] the cotangent of w and u_hrr [n] of hrr."""
+    J = jacobian(m, T, p, Y)
+    n = J.shape[0]
+    uu = np.concatenate([np.zeros((n, 1)) if u_hrr is None else np.asarray(u_hrr)[:, None],
+                         np.asarray(u)], axis=1)
+    g = np.einsum("nr,nrc->nc", uu, J)
+    return g[:, 0], g[:, 1:]
+
+
+def _forward_vector(m, T, p, Y):
+    r = production_rates(m, T, p, Y)
+    return np.concatenate([r["hrr"][:, None], r["wdot"]], axis=1)
+
+
+def complex_step_jacobian(m, T, p, Y, h=1e-30):
+    """Jacobian by complex-step differentiation of the forward oracle (exact to rounding)."""
+    T = np.asarray(T, dtype=float)
+    Y = np.asarray(Y, dtype=float)
+    n, ns = Y.shape
+    J = np.zeros((n, ns + 1, ns + 1))
+    for c in range(ns + 1):
+        Tc = T.astype(complex)
+        Yc = Y.astype(complex)
+        if c == 0:
+            step = h * T
+            Tc = Tc + 1j * step
+        else:
+            step = np.full(n, h)
+            Yc[:, c - 1] = Yc[:, c - 1] + 1j * step
+        J[:, :, c] = _forward_vector(m, Tc, p, Yc).imag / step[:, None]
+    return J
+
+
+def central_fd_jacobian(m, T, p, Y, rel=1e-6, y_floor=1e-10):
+    """Central finite differences, h_T = rel*T, h_j = rel*max(Y_j, y_floor)."""
+    T = np.asarray(T, dtype=float)
+    Y = np.asarray(Y, dtype=float)
+    n, ns = Y.shape
+    J = np.zeros((n, ns + 1, ns + 1))
+    for c in range(ns + 1):
+        if c == 0:
+            hh = rel * T
+            fp = _forward_vector(m, T + hh, p, Y)
+            fm = _forward_vector(m, T - hh, p, Y)
+        else:
+            hh = rel * np.maximum(Y[:, c - 1], y_floor)
+            Yp = Y.copy(); Yp[:, c - 1] += hh
+            Ym = Y.copy(); Ym[:, c - 1] -= hh
+            fp = _forward_vector(m, T, p, Yp)
+            fm = _forward_vector(m, T, p, Ym)
+        J[:, :, c] = (fp - fm) / (2.0 * hh[:, None])
+    return J
