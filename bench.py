@@ -1,0 +1,145 @@
+"""Benchmark: production rates + dense Jacobian, 53 species, FP64 and mixed precision, on one MI355X.
+
+Workload: the 53-species / 325-reaction mechanism (40 three-body, 25 Troe falloff),
+2^18 points (the first 2^18 rows of the 2^20-point state: T ~ U[300, 2500] K with
+10 % near-equilibrium points, p in {1, 10} atm, Y ~ Dirichlet(0.3)), synthetic.
+One step = one fused crf_wdot_jac call (state, thermo, rate constants, falloff,
+equilibrium constants, rates of progress, production rates and the dense Jacobian)
+over the whole batch.  The rest of the per-point path (thermo, transport, VJP) is
+timed in the same run and reported under "path".
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import tempfile
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def jac_bytes_per_point(ns, prec):
+    """Algorithmic HBM bytes per point of crf_wdot_jac: read T, p, Y; write J and w."""
+    n1 = ns + 1
+    return 8 * (2 + ns) + (8 if prec == "fp64" else 4) * n1 * n1 + 8 * ns
+
+
+def timed(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps      # ms per call
+
+
+def cpu_baseline(mech_path, st, n_sample):
+    """The FP64 numpy oracle (production rates + analytic Jacobian) on a bounded sample."""
+    import numpy as np
+
+    import oracle
+    om = oracle.read_mechanism(mech_path)
+    T, p, Y = st["T"][:n_sample], st["p"][:n_sample], np.ascontiguousarray(st["Y"][:, :n_sample].T)
+    c0, w0 = time.process_time(), time.perf_counter()
+    oracle.production_rates(om, T, p, Y)
+    oracle.jacobian(om, T, p, Y)
+    wall = time.perf_counter() - w0
+    cpu = time.process_time() - c0
+    return {"value": n_sample / wall / 1e6, "unit": "Mpoints/s", "cores": max(1, round(cpu / wall)),
+            "kind": "oracle",
+            "sample": f"{n_sample} points of the same state (production rates + analytic Jacobian, FP64 numpy), "
+                      f"{wall:.1f} s wall on {os.cpu_count()} host CPUs"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--points", type=int, default=1 << 18)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--only", choices=["fp64", "mixed"], default=None, help="time one precision only")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the per-point chemistry shards trivially by points; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2409_06404_amd as crf
+
+    dev = torch.device("cuda", 0)
+    n = args.points
+    with tempfile.TemporaryDirectory() as d:
+        mech_path = synth.write_mechanism(synth.MECH_C1, os.path.join(d, "c1.mech"))
+        m = crf.Mechanism(mech_path, device=0)
+        ns = m.n_species
+        full = synth.state_c1(ns, n=1 << 20, seed=1)
+        st = {"T": full["T"][:n], "p": full["p"][:n], "Y": np.ascontiguousarray(full["Y"][:, :n])}
+        T = torch.from_numpy(st["T"]).to(dev)
+        p = torch.from_numpy(st["p"]).to(dev)
+        Y = torch.from_numpy(st["Y"]).to(dev).t()
+        u = torch.randn((ns, n), dtype=torch.float64, device=dev).t()
+        stream = torch.cuda.current_stream(dev)
+        res = {}
+        precs = [args.only] if args.only else ["fp64", "mixed"]
+        for prec in precs:
+            J = torch.empty((n, ns + 1, ns + 1), dtype=torch.float64 if prec == "fp64" else torch.float32,
+                            device=dev)
+            ms = timed(lambda: crf.wdot_jac(m, T, p, Y, prec, out=J), args.steps, args.warmup, stream)
+            bpp = jac_bytes_per_point(ns, prec)
+            achieved = bpp * n / (ms * 1e-3) / 1e9
+            res[prec] = {"value": n / (ms * 1e-3) / 1e6, "ms_per_step": ms,
+                         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                                      "bytes_per_point": bpp, "kernel": "k_jac<%s>" % ("false" if prec == "fp64" else "true")}}
+            del J
+            torch.cuda.empty_cache()
+        path = {}
+        for prec in precs:
+            path[prec] = {
+                "wdot": n / (timed(lambda: crf.wdot(m, T, p, Y, prec, hrr=True), args.steps, 1, stream) * 1e-3) / 1e6,
+                "transport": n / (timed(lambda: crf.transport(m, T, p, Y, prec), max(2, args.steps // 4), 1, stream) * 1e-3) / 1e6,
+                "vjp": n / (timed(lambda: crf.wdot_vjp(m, T, p, Y, u, None, prec), args.steps, 1, stream) * 1e-3) / 1e6,
+            }
+        path["fp64"]["thermo"] = n / (timed(lambda: crf.thermo(m, T, p, Y), args.steps, 1, stream) * 1e-3) / 1e6
+        m.close()
+        head = "fp64" if "fp64" in res else precs[0]
+        out = {
+            "metric": "Mpoints/s wdot+Jacobian (53 sp), FP64 vs mixed precision, % of roofline",
+            "value": res[head]["value"], "unit": "Mpoints/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": res[head]["ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64" if head == "fp64" else "f32+f64",
+            "data": "synthetic",
+            "config": {"workload": "wdot + dense Jacobian (fused), 53 species / 325 reactions (40 three-body, "
+                                   "25 Troe), 2^18 points, inputs resident in HBM",
+                       "n_points": n, "species": ns, "reactions": 325, "precision": head},
+            "roofline": res[head]["roofline"],
+        }
+        if "mixed" in res and head != "mixed":
+            out["mixed"] = dict(res["mixed"], dtype="f32+f64")
+        out["path_mpoints_per_s"] = path
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(mech_path, st, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

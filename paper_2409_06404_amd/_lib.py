@@ -1,0 +1,68 @@
+"""ctypes declarations of the C ABI in include/crf.h (argument marshalling only)."""
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcrf.so")
+
+EXPORTED = (
+    "crf_load_mech", "crf_free_mech", "crf_n_species", "crf_n_reactions", "crf_device",
+    "crf_last_error", "crf_status_str", "crf_thermo", "crf_wdot", "crf_transport",
+    "crf_wdot_vjp", "crf_wdot_jac",
+)
+
+CRF_OK, CRF_E_ARG, CRF_E_PARSE, CRF_E_MECH, CRF_E_NOMEM, CRF_E_DEVICE, CRF_E_UNSUPPORTED = range(7)
+CRF_FP64, CRF_MIXED = 0, 1
+
+_lib = None
+
+
+class CrfError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{status_name(status)}: {message}")
+        self.status = status
+
+
+def status_name(s):
+    return ["CRF_OK", "CRF_E_ARG", "CRF_E_PARSE", "CRF_E_MECH", "CRF_E_NOMEM", "CRF_E_DEVICE",
+            "CRF_E_UNSUPPORTED"][s] if 0 <= s < 7 else f"status {s}"
+
+
+def lib():
+    """The loaded library; raises if libcrf.so has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I64, I, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
+    L.crf_load_mech.argtypes = [ctypes.c_char_p, I, ctypes.POINTER(ctypes.c_void_p)]
+    L.crf_load_mech.restype = I
+    L.crf_free_mech.argtypes = [P]
+    L.crf_free_mech.restype = None
+    for f in ("crf_n_species", "crf_n_reactions", "crf_device"):
+        getattr(L, f).argtypes = [P]
+        getattr(L, f).restype = I
+    L.crf_last_error.argtypes = []
+    L.crf_last_error.restype = ctypes.c_char_p
+    L.crf_status_str.argtypes = [I]
+    L.crf_status_str.restype = ctypes.c_char_p
+    state = [P, I64, D, D, I64, D, I64]
+    L.crf_thermo.argtypes = state + [D] * 8 + [P]
+    L.crf_thermo.restype = I
+    L.crf_wdot.argtypes = [P, I, I64, D, D, I64, D, I64, D, D, D, P]
+    L.crf_wdot.restype = I
+    L.crf_transport.argtypes = [P, I, I64, D, D, I64, D, I64, D, D, D, P]
+    L.crf_transport.restype = I
+    L.crf_wdot_vjp.argtypes = [P, I, I64, D, D, I64, D, I64, D, D, D, D, P]
+    L.crf_wdot_vjp.restype = I
+    L.crf_wdot_jac.argtypes = [P, I, I64, D, D, I64, D, I64, D, D, P]
+    L.crf_wdot_jac.restype = I
+    _lib = L
+    return L
+
+
+def check(status):
+    if status != CRF_OK:
+        raise CrfError(status, lib().crf_last_error().decode())

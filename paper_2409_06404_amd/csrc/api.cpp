@@ -1,0 +1,171 @@
+// C ABI entry points: host-side argument validation, then kernel launch.
+
+#include <string>
+
+#include "crf_internal.h"
+
+namespace crf {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+crf_status fail(crf_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+namespace {
+
+// Validation of the state arguments common to every compute call.
+crf_status check_state(const crf_mech *m, int64_t n, const double *T, const double *p, int64_t ps,
+                       const double *Y, int64_t ld, const char *fn) {
+    std::string f(fn);
+    if (!m) return fail(CRF_E_ARG, f + ": mechanism is NULL");
+    if (n < 0) return fail(CRF_E_ARG, f + ": n must be >= 0");
+    if (n > ((int64_t)1 << 40)) return fail(CRF_E_ARG, f + ": n too large");
+    if (ps != 0 && ps != 1) return fail(CRF_E_ARG, f + ": p_stride must be 0 or 1");
+    if (ld < n) return fail(CRF_E_ARG, f + ": ld must be >= n");
+    if (n > 0 && (!T || !p || !Y)) return fail(CRF_E_ARG, f + ": T, p and Y must not be NULL");
+    if (m->device < 0 || !m->dev_buf) return fail(CRF_E_DEVICE, f + ": mechanism was loaded without a device");
+    return CRF_OK;
+}
+
+crf_status check_prec(crf_precision prec, const char *fn) {
+    if (prec != CRF_FP64 && prec != CRF_MIXED) return fail(CRF_E_ARG, std::string(fn) + ": invalid precision");
+    return CRF_OK;
+}
+
+// Runs `launch` with the mechanism's device current; restores the caller's device.
+template <class F>
+crf_status on_device(const crf_mech *m, const char *fn, F &&launch) {
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) return fail(CRF_E_DEVICE, std::string(fn) + ": hipGetDevice failed");
+    if (prev != m->device && hipSetDevice(m->device) != hipSuccess)
+        return fail(CRF_E_DEVICE, std::string(fn) + ": hipSetDevice failed");
+    hipError_t e = launch();
+    if (prev != m->device) hipSetDevice(prev);
+    if (e != hipSuccess) return fail(CRF_E_DEVICE, std::string(fn) + ": launch failed: " + hipGetErrorString(e));
+    return CRF_OK;
+}
+
+}  // namespace
+}  // namespace crf
+
+using namespace crf;
+
+extern "C" {
+
+crf_status crf_load_mech(const char *path, int device, crf_mech **out) {
+    if (!out) return fail(CRF_E_ARG, "crf_load_mech: out is NULL");
+    *out = nullptr;
+    if (device < -1) return fail(CRF_E_ARG, "crf_load_mech: device must be >= -1");
+    crf_mech *m = new (std::nothrow) crf_mech();
+    if (!m) return fail(CRF_E_NOMEM, "crf_load_mech: out of host memory");
+    crf_status s = parse_mechanism(path, m->host);
+    if (s == CRF_OK && device >= 0) s = upload_mechanism(m, device);
+    if (s != CRF_OK) { delete m; return s; }
+    *out = m;
+    return CRF_OK;
+}
+
+void crf_free_mech(crf_mech *m) {
+    if (!m) return;
+    if (m->dev_buf) {
+        int prev = -1;
+        hipGetDevice(&prev);
+        hipSetDevice(m->device);
+        hipFree(m->dev_buf);
+        if (prev >= 0) hipSetDevice(prev);
+    }
+    delete m;
+}
+
+int crf_n_species(const crf_mech *m) { return m ? m->host.ns() : -1; }
+int crf_n_reactions(const crf_mech *m) { return m ? m->host.nr() : -1; }
+int crf_device(const crf_mech *m) { return m ? m->device : -1; }
+
+const char *crf_last_error(void) { return crf::g_last_error.c_str(); }
+
+const char *crf_status_str(crf_status s) {
+    switch (s) {
+        case CRF_OK: return "CRF_OK";
+        case CRF_E_ARG: return "CRF_E_ARG";
+        case CRF_E_PARSE: return "CRF_E_PARSE";
+        case CRF_E_MECH: return "CRF_E_MECH";
+        case CRF_E_NOMEM: return "CRF_E_NOMEM";
+        case CRF_E_DEVICE: return "CRF_E_DEVICE";
+        case CRF_E_UNSUPPORTED: return "CRF_E_UNSUPPORTED";
+    }
+    return "CRF_UNKNOWN_STATUS";
+}
+
+crf_status crf_thermo(const crf_mech *m, int64_t n, const double *T, const double *p, int64_t ps,
+                      const double *Y, int64_t ld, double *cp_k, double *h_k, double *s_k, double *g_k,
+                      double *cp_mass, double *h_mass, double *rho, double *Wbar, crf_stream stream) {
+    crf_status s = check_state(m, n, T, p, ps, Y, ld, "crf_thermo");
+    if (s != CRF_OK) return s;
+    if (n == 0) return CRF_OK;
+    return on_device(m, "crf_thermo", [&] {
+        return launch_thermo(m->dev, n, T, p, ps, Y, ld, cp_k, h_k, s_k, g_k, cp_mass, h_mass, rho, Wbar,
+                             (hipStream_t)stream);
+    });
+}
+
+crf_status crf_wdot(const crf_mech *m, crf_precision prec, int64_t n, const double *T, const double *p,
+                    int64_t ps, const double *Y, int64_t ld, double *wdot, double *hrr, double *mass_resid,
+                    crf_stream stream) {
+    crf_status s = check_state(m, n, T, p, ps, Y, ld, "crf_wdot");
+    if (s == CRF_OK) s = check_prec(prec, "crf_wdot");
+    if (s != CRF_OK) return s;
+    if (n > 0 && !wdot) return fail(CRF_E_ARG, "crf_wdot: wdot must not be NULL");
+    if (n == 0) return CRF_OK;
+    return on_device(m, "crf_wdot", [&] {
+        return launch_wdot(m->dev, prec == CRF_MIXED, n, T, p, ps, Y, ld, wdot, hrr, mass_resid,
+                           (hipStream_t)stream);
+    });
+}
+
+crf_status crf_transport(const crf_mech *m, crf_precision prec, int64_t n, const double *T,
+                         const double *p, int64_t ps, const double *Y, int64_t ld, double *mu,
+                         double *lambda, double *Dmix, crf_stream stream) {
+    crf_status s = check_state(m, n, T, p, ps, Y, ld, "crf_transport");
+    if (s == CRF_OK) s = check_prec(prec, "crf_transport");
+    if (s != CRF_OK) return s;
+    if (n == 0 || (!mu && !lambda && !Dmix)) return CRF_OK;
+    return on_device(m, "crf_transport", [&] {
+        return launch_transport(m->dev, prec == CRF_MIXED, n, T, p, ps, Y, ld, mu, lambda, Dmix,
+                                (hipStream_t)stream);
+    });
+}
+
+crf_status crf_wdot_vjp(const crf_mech *m, crf_precision prec, int64_t n, const double *T,
+                        const double *p, int64_t ps, const double *Y, int64_t ld, const double *u,
+                        const double *u_hrr, double *gT, double *gY, crf_stream stream) {
+    crf_status s = check_state(m, n, T, p, ps, Y, ld, "crf_wdot_vjp");
+    if (s == CRF_OK) s = check_prec(prec, "crf_wdot_vjp");
+    if (s != CRF_OK) return s;
+    if (n > 0 && (!u || !gT || !gY)) return fail(CRF_E_ARG, "crf_wdot_vjp: u, gT and gY must not be NULL");
+    if (n == 0) return CRF_OK;
+    return on_device(m, "crf_wdot_vjp", [&] {
+        return launch_vjp(m->dev, prec == CRF_MIXED, n, T, p, ps, Y, ld, u, u_hrr, gT, gY,
+                          (hipStream_t)stream);
+    });
+}
+
+crf_status crf_wdot_jac(const crf_mech *m, crf_precision prec, int64_t n, const double *T,
+                        const double *p, int64_t ps, const double *Y, int64_t ld, void *J, double *wdot,
+                        crf_stream stream) {
+    crf_status s = check_state(m, n, T, p, ps, Y, ld, "crf_wdot_jac");
+    if (s == CRF_OK) s = check_prec(prec, "crf_wdot_jac");
+    if (s != CRF_OK) return s;
+    if (n > 0 && !J) return fail(CRF_E_ARG, "crf_wdot_jac: J must not be NULL");
+    if (n == 0) return CRF_OK;
+    return on_device(m, "crf_wdot_jac", [&] {
+        return launch_jac(m->dev, prec == CRF_MIXED, n, T, p, ps, Y, ld, J, wdot, (hipStream_t)stream);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+// Internal definitions shared by the loader, the C ABI and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "crf.h"
+
+namespace crf {
+
+// Reaction kinds (bits 0-1 of the packed reaction info word).
+enum : int { RXN_ELEMENTARY = 0, RXN_THREEBODY = 1, RXN_TROE = 2 };
+
+// Slots per reaction: up to 3 distinct reactant species (slots 0-2) and up to 3
+// distinct product species (slots 3-5).  Packed info word:
+//   bits 0-1  kind
+//   bits 2-3  number of reactant slots used
+//   bits 4-5  number of product slots used
+//   bits 6+2s coefficient (1..3) of slot s, s = 0..5
+constexpr int MAX_SIDE = 3;
+constexpr int SLOTS = 6;
+
+__host__ __device__ inline int info_kind(int w) { return w & 3; }
+__host__ __device__ inline int info_nreac(int w) { return (w >> 2) & 3; }
+__host__ __device__ inline int info_nprod(int w) { return (w >> 4) & 3; }
+__host__ __device__ inline int info_nu(int w, int s) { return (w >> (6 + 2 * s)) & 3; }
+
+// Per-reaction integer record, 8 ints (two 16-byte loads):
+//   [0..5] species of slots 0..5 (-1 unused)
+//   [6]    first third-body efficiency exception (index into eff_sp / eff_m1)
+//   [7]    number of exceptions (bits 0-7) | troe index << 8
+struct alignas(16) RxnInts { int v[8]; };
+
+// Device tables of one mechanism; pointers into a single device allocation.
+struct DevMech {
+    int ns, nr, n_troe, n_exc, n_pairs;
+    double R, p0;
+    // species
+    const double *W, *invW;
+    const double *nasa;       // [ns][16]: Tmid, a_lo[7], a_hi[7], pad
+    const double *mu_fit;     // [ns][4]
+    const double *lam_fit;    // [ns][4]
+    const double *w4;         // W^(1/4)
+    const double *iw4;        // W^(-1/4)
+    const double *wilke_c;    // [j][k]: (1/sqrt 8) (1 + W_k/W_j)^(-1/2)
+    const double *dif_fit;    // [pair][4], pairs j<k in lexicographic order
+    const int *pair_jk;       // [pair]: j | k << 16
+    // reactions
+    const double *lnA, *b, *theta;
+    const int *info;          // packed info word
+    const int *dnu_sum;       // sum_k (nu''_k - nu'_k)
+    const RxnInts *ri;
+    const double *troe;       // [n_troe][8]: lnA0, b0, theta0, alpha, 1/T3, 1/T1, T2, 0
+    const int *eff_sp;        // [n_exc]
+    const double *eff_m1;     // [n_exc] eps - 1
+};
+
+// Host copy of a parsed mechanism.
+struct HostMech {
+    double R = 0, p0 = 0;
+    std::vector<std::string> elements;
+    std::vector<double> aw;
+    std::vector<std::string> names;
+    std::vector<int> comp;               // [ns][ne]
+    std::vector<double> W;
+    std::vector<double> nasa;            // [ns][16]
+    std::vector<double> mu_fit, lam_fit; // [ns][4]
+    std::vector<double> dif_full;        // [ns][ns][4], symmetric
+    std::vector<char> dif_seen;          // [ns][ns]
+    std::vector<double> lnA, b, theta;
+    std::vector<int> info, dnu_sum;
+    std::vector<RxnInts> ri;
+    std::vector<double> troe;            // [n_troe][8]
+    std::vector<int> eff_sp;
+    std::vector<double> eff_m1;
+    int ns() const { return (int)names.size(); }
+    int nr() const { return (int)lnA.size(); }
+};
+
+}  // namespace crf
+
+struct crf_mech {
+    crf::HostMech host;
+    crf::DevMech dev{};
+    int device = -1;
+    void *dev_buf = nullptr;
+};
+
+namespace crf {
+
+// Error reporting (thread-local message of the last failure).
+crf_status fail(crf_status s, const std::string &msg);
+void clear_error();
+
+// Parsing / validation / upload (mech.cpp).
+crf_status parse_mechanism(const char *path, HostMech &out);
+crf_status upload_mechanism(crf_mech *m, int device);
+
+// Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.
+hipError_t launch_thermo(const DevMech &m, int64_t n, const double *T, const double *p, int64_t ps,
+                         const double *Y, int64_t ld, double *cp_k, double *h_k, double *s_k,
+                         double *g_k, double *cp_mass, double *h_mass, double *rho, double *Wbar,
+                         hipStream_t st);
+hipError_t launch_wdot(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
+                       int64_t ps, const double *Y, int64_t ld, double *wdot, double *hrr,
+                       double *rmass, hipStream_t st);
+hipError_t launch_transport(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
+                            int64_t ps, const double *Y, int64_t ld, double *mu, double *lam,
+                            double *Dmix, hipStream_t st);
+hipError_t launch_vjp(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
+                      int64_t ps, const double *Y, int64_t ld, const double *u, const double *uh,
+                      double *gT, double *gY, hipStream_t st);
+hipError_t launch_jac(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
+                      int64_t ps, const double *Y, int64_t ld, void *J, double *wdot, hipStream_t st);
+
+}  // namespace crf

@@ -1,0 +1,711 @@
+// HIP kernels for gfx950 (CDNA4): per-point thermochemistry, production rates,
+// transport, vector-Jacobian product and dense Jacobian.
+//
+// Work decomposition.  A mechanism has tens to thousands of reactions and tens
+// to hundreds of species, and the chemistry of every grid point is independent.
+// Each 64-wide wavefront therefore owns one grid point (or a few) at a time:
+//   * state phase:    lanes = species (mixture state, NASA-7 polynomials);
+//   * reaction phase: lanes = reactions (rate constants, falloff, equilibrium
+//                     constants, rates of progress and their derivatives);
+//   * output phase:   lanes = species / Jacobian columns.
+// Per-point species arrays live in LDS ([species] per point, a few KB per wave),
+// reaction constants are read from the mechanism tables (the same addresses for
+// every wave, so they stay in L1/L2), and the sparse stoichiometric reductions
+// (w_k = sum_i dnu_ki q_i and the Jacobian assembly) are scatters into LDS with
+// native ds_add_f64 / ds_add_f32.  Every LDS address is owned by one wave, so the
+// order of additions is fixed by the program and results are reproducible.
+//
+// Thermodynamics (crf_thermo) is point-parallel instead: lane = point, species
+// loop uniform, coefficients via scalar loads, fully coalesced stores.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <type_traits>
+
+#include "crf_internal.h"
+
+namespace crf {
+
+namespace {
+
+constexpr int WAVE = 64;
+constexpr double LN10 = 2.302585092994045684;
+constexpr double INV_LN10 = 0.4342944819032518277;
+
+// ------------------------------------------------------------------ helpers
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;   // butterfly: every lane holds the same (commutative) sum
+}
+
+// Makes LDS writes of all lanes of this wave visible to all its lanes.
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ inline double ipow(double x, int n) {   // n in 0..3
+    return n == 1 ? x : n == 2 ? x * x : n == 3 ? x * x * x : 1.0;
+}
+__device__ inline double ipow_m1(double x, int n) {   // n * x^(n-1), n in 1..3
+    return n == 1 ? 1.0 : n == 2 ? 2.0 * x : 3.0 * x * x;
+}
+
+template <class R> __device__ inline R exp_r(R x);
+template <> __device__ inline double exp_r<double>(double x) { return exp(x); }
+template <> __device__ inline float exp_r<float>(float x) { return __expf(x); }
+template <class R> __device__ inline R log_r(R x);
+template <> __device__ inline double log_r<double>(double x) { return log(x); }
+template <> __device__ inline float log_r<float>(float x) { return __logf(x); }
+
+// e^x with FP64 range reduction (x = k ln2 + f, |f| <= ln2/2) and an FP32 core:
+// relative error ~2^-23 independent of |x|.  Used for the equilibrium factor in
+// the mixed mode, where ln K_c itself is formed in FP64.
+__device__ inline double exp_split(double x) {
+    const double k = rint(x * 1.4426950408889634074);
+    double f = fma(-k, 6.93147180369123816490e-01, x);
+    f = fma(-k, 1.90821492927058770002e-10, f);
+    const float e = __expf((float)f);
+    return ldexp((double)e, (int)fmax(fmin(k, 2000.0), -2000.0));
+}
+
+struct PointState {
+    double T, lnT, invT, lnp0RT, rho, Wbar, Ctot, p;
+    bool valid;
+};
+
+// NASA-7 evaluation for one species: cp/R, h/RT, s/R (g/RT = h/RT - s/R).
+__device__ inline void nasa7(const double *c16, double T, double lnT, double invT, double &cpR,
+                             double &hRT, double &sR) {
+    const double *a = (T <= c16[0]) ? c16 + 1 : c16 + 8;
+    const double a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3], a4 = a[4], a5 = a[5], a6 = a[6];
+    cpR = a0 + T * (a1 + T * (a2 + T * (a3 + T * a4)));
+    hRT = a0 + T * (a1 * 0.5 + T * (a2 * (1.0 / 3.0) + T * (a3 * 0.25 + T * (a4 * 0.2)))) + a5 * invT;
+    sR = a0 * lnT + T * (a1 + T * (a2 * 0.5 + T * (a3 * (1.0 / 3.0) + T * (a4 * 0.25)))) + a6;
+}
+
+// Loads T, p and the mixture state of point i; lanes = species write the
+// per-species LDS arrays.  Returns the point scalars (identical in every lane).
+template <bool NEED_H, bool NEED_CP>
+__device__ inline PointState load_point(const DevMech &m, int64_t i, int64_t n, const double *T,
+                                        const double *p, int64_t ps, const double *Y, int64_t ld,
+                                        double *C, double *gRT, double *hRT, double *cpR) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    PointState s;
+    s.valid = i < n;
+    const int64_t ii = s.valid ? i : 0;
+    s.T = T[ii];
+    s.p = p[ii * ps];
+    s.lnT = log(s.T);
+    s.invT = 1.0 / s.T;
+    s.lnp0RT = log(m.p0 / (m.R * s.T));
+    double sy = 0.0;
+    for (int k = lane; k < m.ns; k += WAVE) sy += Y[(int64_t)k * ld + ii] * m.invW[k];
+    sy = wave_sum(sy);
+    s.Wbar = 1.0 / sy;
+    s.rho = s.p * s.Wbar / (m.R * s.T);
+    double ct = 0.0;
+    for (int k = lane; k < m.ns; k += WAVE) {
+        const double c = s.rho * Y[(int64_t)k * ld + ii] * m.invW[k];
+        double cp, h, sr;
+        nasa7(m.nasa + 16 * k, s.T, s.lnT, s.invT, cp, h, sr);
+        C[k] = c;
+        gRT[k] = h - sr;
+        if (NEED_H) hRT[k] = h;
+        if (NEED_CP) cpR[k] = cp;
+        ct += c;
+    }
+    s.Ctot = wave_sum(ct);
+    return s;
+}
+
+// Everything one reaction contributes at one point.
+struct RxnEval {
+    double q;            // net rate of progress (incl. [M] for three-body)
+    double d[SLOTS];     // dq/dC of the slot species (mass-action part)
+    double mfac;         // dq/d[M] (three-body and falloff), else 0
+    double t;            // dq/dT at fixed concentrations
+    double sigma;        // sum_j C_j dq/dC_j over all species (incl. efficiency part)
+};
+
+// Rate of progress of reaction `r` (and, with DERIV, its derivatives).
+// MIXED: Arrhenius exponentials and Troe blending in FP32; everything else FP64.
+template <bool MIXED, bool DERIV>
+__device__ inline void eval_reaction(const DevMech &m, int r, const PointState &ps, const double *C,
+                                     const double *gRT, const double *hRT, int info, const RxnInts &ri,
+                                     double lnA, double bb, double th, int dnu_sum, RxnEval &o) {
+    using Rt = typename std::conditional<MIXED, float, double>::type;
+    const int kind = info_kind(info);
+    const int nre = info_nreac(info), npr = info_nprod(info);
+    // third-body concentration [M] = Ctot + sum_exc (eps - 1) C_k
+    double M = 0.0;
+    const int n_exc = ri.v[7] & 255;
+    if (kind != RXN_ELEMENTARY) {
+        M = ps.Ctot;
+        for (int e = 0; e < n_exc; ++e) M += m.eff_m1[ri.v[6] + e] * C[m.eff_sp[ri.v[6] + e]];
+    }
+    // forward rate constant
+    const Rt lnT = (Rt)ps.lnT, invT = (Rt)ps.invT, T = (Rt)ps.T;
+    const Rt lnkinf = (Rt)lnA + (Rt)bb * lnT - (Rt)th * invT;
+    const Rt kinf = exp_r<Rt>(lnkinf);
+    const Rt dlnkinf = ((Rt)bb + (Rt)th * invT) * invT;
+    Rt kf = kinf, dkf_dT = kinf * dlnkinf, dkf_dM = 0;
+    if (kind == RXN_TROE) {
+        const double *tp = m.troe + 8 * (ri.v[7] >> 8);
+        const Rt lnA0 = (Rt)tp[0], b0 = (Rt)tp[1], th0 = (Rt)tp[2], alpha = (Rt)tp[3];
+        const Rt iT3 = (Rt)tp[4], iT1 = (Rt)tp[5], T2 = (Rt)tp[6];
+        const Rt lnk0 = lnA0 + b0 * lnT - th0 * invT;
+        const Rt lnM = log_r<Rt>((Rt)M);
+        const Rt lnPr = lnk0 - lnkinf + lnM;
+        const Rt Pr = exp_r<Rt>(lnPr);
+        const Rt e3 = exp_r<Rt>(-T * iT3), e1 = exp_r<Rt>(-T * iT1), e2 = exp_r<Rt>(-T2 * invT);
+        const Rt Fc = ((Rt)1 - alpha) * e3 + alpha * e1 + e2;
+        const Rt tiny = MIXED ? (Rt)1e-37 : (Rt)1e-300;
+        const Rt lFc = log_r<Rt>(Fc > tiny ? Fc : tiny) * (Rt)INV_LN10;
+        const Rt c = (Rt)-0.4 - (Rt)0.67 * lFc;
+        const Rt nn = (Rt)0.75 - (Rt)1.27 * lFc;
+        const Rt lnfloor = MIXED ? (Rt)-85.19 : (Rt)-690.7755278982137;
+        const Rt ell = (lnPr > lnfloor ? lnPr : lnfloor) * (Rt)INV_LN10;
+        const Rt u = ell + c;
+        const Rt den = nn - (Rt)0.14 * u;
+        const Rt f1 = u / den;
+        const Rt g = (Rt)1 / ((Rt)1 + f1 * f1);
+        const Rt F = exp_r<Rt>(lFc * g * (Rt)LN10);
+        const Rt Prp = (Rt)1 / ((Rt)1 + (Rt)1 / Pr);     // Pr/(1+Pr), safe for Pr -> 0, inf
+        kf = kinf * Prp * F;
+        if (DERIV) {
+            const Rt idd = (Rt)1 / (den * den);
+            const Rt df1_dell = nn * idd;
+            const Rt df1_dlFc = ((Rt)-0.67 * den - u * ((Rt)-1.27 + (Rt)0.67 * (Rt)0.14)) * idd;
+            const Rt dlogF_dell = -lFc * (Rt)2 * f1 * df1_dell * g * g;
+            const Rt dlogF_dlFc = g - lFc * (Rt)2 * f1 * df1_dlFc * g * g;
+            const Rt dlnk0 = (b0 + th0 * invT) * invT;
+            const Rt dlnPr = dlnk0 - dlnkinf;
+            const Rt dFc = -((Rt)1 - alpha) * iT3 * e3 - alpha * iT1 * e1 + T2 * invT * invT * e2;
+            const Rt dlFc = dFc / (Fc * (Rt)LN10);
+            const Rt dlnF = dlogF_dell * dlnPr + (Rt)LN10 * dlogF_dlFc * dlFc;
+            const Rt ip1 = (Rt)1 / ((Rt)1 + Pr);
+            dkf_dT = kf * (dlnkinf + dlnPr * ip1 + dlnF);
+            const Rt k0 = exp_r<Rt>(lnk0);
+            dkf_dM = k0 * F * ip1 * (ip1 + dlogF_dell);
+        }
+    }
+    // equilibrium constant: ln K_c = -sum dnu_k g_k/RT + dnu ln(p0/RT)   (always FP64)
+    double lnKc = (double)dnu_sum * ps.lnp0RT;
+    double dlnKc = -(double)dnu_sum;
+    double pf = 1.0, pr = 1.0;
+    double Cs[SLOTS], Ps[SLOTS];
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        const bool used = s < MAX_SIDE ? s < nre : (s - MAX_SIDE) < npr;
+        const int k = used ? ri.v[s] : 0;
+        const int nu = used ? info_nu(info, s) : 0;
+        const double sgn = s < MAX_SIDE ? -1.0 : 1.0;
+        const double c = used ? C[k] : 1.0;
+        Cs[s] = c;
+        Ps[s] = ipow(c, nu);
+        if (used) {
+            lnKc -= sgn * nu * gRT[k];
+            if (DERIV) dlnKc += sgn * nu * hRT[k];
+        }
+        if (s < MAX_SIDE) pf *= Ps[s]; else pr *= Ps[s];
+    }
+    const double invKc = MIXED ? exp_split(-lnKc) : exp(-lnKc);
+    const double kfd = (double)kf;
+    const double fac = kind == RXN_THREEBODY ? M : 1.0;
+    const double krd = kfd * invKc;
+    o.q = fac * (kfd * pf - krd * pr);
+    if (DERIV) {
+        dlnKc *= ps.invT;
+        const double bracket = pf - invKc * pr;
+        o.t = fac * ((double)dkf_dT * bracket + krd * pr * dlnKc);
+        o.mfac = kind == RXN_THREEBODY ? kfd * bracket : kind == RXN_TROE ? (double)dkf_dM * bracket : 0.0;
+        double sig = 0.0;
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const bool used = s < MAX_SIDE ? s < nre : (s - MAX_SIDE) < npr;
+            const int nu = used ? info_nu(info, s) : 1;
+            // d(prod)/dC_s = nu C_s^(nu-1) * product of the other slots of the same side
+            double other = 1.0;
+            const int lo = s < MAX_SIDE ? 0 : MAX_SIDE;
+#pragma unroll
+            for (int t = 0; t < MAX_SIDE; ++t)
+                if (lo + t != s) other *= Ps[lo + t];
+            const double dp = ipow_m1(Cs[s], nu) * other;
+            const double d = used ? (s < MAX_SIDE ? fac * kfd * dp : -fac * krd * dp) : 0.0;
+            o.d[s] = d;
+            sig += d * Cs[s];
+        }
+        // efficiency part of sum_j C_j dq/dC_j: mfac * sum_j eps_j C_j = mfac * [M]
+        o.sigma = sig + o.mfac * M;
+    }
+}
+
+// ------------------------------------------------------------------ thermo
+__global__ __launch_bounds__(256) void k_thermo(DevMech m, int64_t n, const double *__restrict__ T,
+                                                const double *__restrict__ p, int64_t ps,
+                                                const double *__restrict__ Y, int64_t ld,
+                                                double *__restrict__ cp_k, double *__restrict__ h_k,
+                                                double *__restrict__ s_k, double *__restrict__ g_k,
+                                                double *__restrict__ cp_mass, double *__restrict__ h_mass,
+                                                double *__restrict__ rho, double *__restrict__ Wbar) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double t = T[i], lnT = log(t), invT = 1.0 / t;
+        double sy = 0.0;
+        for (int k = 0; k < m.ns; ++k) sy += Y[(int64_t)k * ld + i] * m.invW[k];
+        const double wbar = 1.0 / sy;
+        double cpm = 0.0, hm = 0.0;
+        for (int k = 0; k < m.ns; ++k) {
+            double cp, h, sr;
+            nasa7(m.nasa + 16 * k, t, lnT, invT, cp, h, sr);
+            const double cpv = m.R * cp, hv = m.R * t * h, sv = m.R * sr;
+            const int64_t o = (int64_t)k * ld + i;
+            if (cp_k) cp_k[o] = cpv;
+            if (h_k) h_k[o] = hv;
+            if (s_k) s_k[o] = sv;
+            if (g_k) g_k[o] = hv - t * sv;
+            const double yw = Y[o] * m.invW[k];
+            cpm += yw * cpv;
+            hm += yw * hv;
+        }
+        if (cp_mass) cp_mass[i] = cpm;
+        if (h_mass) h_mass[i] = hm;
+        if (rho) rho[i] = p[i * ps] * wbar / (m.R * t);
+        if (Wbar) Wbar[i] = wbar;
+    }
+}
+
+// ------------------------------------------------------------------ wdot
+// LDS per wave: PPW points x {C, g/RT, h/RT, w} x nsp doubles.
+template <bool MIXED, int PPW>
+__global__ __launch_bounds__(256) void k_wdot(DevMech m, int64_t n, const double *__restrict__ T,
+                                              const double *__restrict__ p, int64_t ps,
+                                              const double *__restrict__ Y, int64_t ld,
+                                              double *__restrict__ wdot, double *__restrict__ hrr,
+                                              double *__restrict__ rmass, int nsp) {
+    extern __shared__ double lds[];
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    const int wpb = blockDim.x / WAVE;
+    double *base = lds + (size_t)wave * PPW * 4 * nsp;
+    const int64_t n_groups = (n + PPW - 1) / PPW;
+    for (int64_t g = (int64_t)blockIdx.x * wpb + wave; g < n_groups; g += (int64_t)gridDim.x * wpb) {
+        PointState st[PPW];
+        wave_lds_sync();
+#pragma unroll
+        for (int q = 0; q < PPW; ++q) {
+            double *C = base + (4 * q + 0) * nsp, *G = base + (4 * q + 1) * nsp, *H = base + (4 * q + 2) * nsp,
+                   *Wd = base + (4 * q + 3) * nsp;
+            st[q] = load_point<true, false>(m, g * PPW + q, n, T, p, ps, Y, ld, C, G, H, nullptr);
+            for (int k = lane; k < m.ns; k += WAVE) Wd[k] = 0.0;
+        }
+        wave_lds_sync();
+        for (int r = lane; r < m.nr; r += WAVE) {
+            const int info = m.info[r];
+            const RxnInts ri = m.ri[r];
+            const double lnA = m.lnA[r], bb = m.b[r], th = m.theta[r];
+            const int dsum = m.dnu_sum[r];
+            const int nre = info_nreac(info), npr = info_nprod(info);
+#pragma unroll
+            for (int q = 0; q < PPW; ++q) {
+                double *C = base + (4 * q + 0) * nsp, *G = base + (4 * q + 1) * nsp,
+                       *Wd = base + (4 * q + 3) * nsp;
+                RxnEval o;
+                eval_reaction<MIXED, false>(m, r, st[q], C, G, nullptr, info, ri, lnA, bb, th, dsum, o);
+                for (int s = 0; s < nre; ++s) atomicAdd(&Wd[ri.v[s]], -(double)info_nu(info, s) * o.q);
+                for (int s = 0; s < npr; ++s)
+                    atomicAdd(&Wd[ri.v[MAX_SIDE + s]], (double)info_nu(info, MAX_SIDE + s) * o.q);
+            }
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int q = 0; q < PPW; ++q) {
+            if (!st[q].valid) continue;
+            const int64_t i = g * PPW + q;
+            const double *H = base + (4 * q + 2) * nsp, *Wd = base + (4 * q + 3) * nsp;
+            double hs = 0.0, ms = 0.0;
+            for (int k = lane; k < m.ns; k += WAVE) {
+                const double w = Wd[k];
+                wdot[(int64_t)k * ld + i] = w;
+                hs += H[k] * w;
+                ms += m.W[k] * w;
+            }
+            hs = wave_sum(hs);
+            ms = wave_sum(ms);
+            if (lane == 0) {
+                if (hrr) hrr[i] = -m.R * st[q].T * hs;
+                if (rmass) rmass[i] = ms;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ VJP
+// LDS per wave: {C, g/RT, h/RT, cp/R, u, gC, w} x nsp doubles (one point at a time).
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_vjp(DevMech m, int64_t n, const double *__restrict__ T,
+                                             const double *__restrict__ p, int64_t ps,
+                                             const double *__restrict__ Y, int64_t ld,
+                                             const double *__restrict__ u, const double *__restrict__ uh,
+                                             double *__restrict__ gT, double *__restrict__ gY, int nsp) {
+    extern __shared__ double lds[];
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    const int wpb = blockDim.x / WAVE;
+    double *C = lds + (size_t)wave * 7 * nsp, *G = C + nsp, *H = G + nsp, *CP = H + nsp, *U = CP + nsp,
+           *GC = U + nsp, *Wd = GC + nsp;
+    for (int64_t i = (int64_t)blockIdx.x * wpb + wave; i < n; i += (int64_t)gridDim.x * wpb) {
+        wave_lds_sync();
+        const PointState st = load_point<true, true>(m, i, n, T, p, ps, Y, ld, C, G, H, CP);
+        const double uhr = uh ? uh[i] : 0.0;
+        for (int k = lane; k < m.ns; k += WAVE) {
+            U[k] = u[(int64_t)k * ld + i];
+            GC[k] = 0.0;
+            Wd[k] = 0.0;
+        }
+        wave_lds_sync();
+        double a_tau = 0.0, a_t = 0.0, a_sig = 0.0;
+        const double RT = m.R * st.T;
+        for (int r = lane; r < m.nr; r += WAVE) {
+            const int info = m.info[r];
+            const RxnInts ri = m.ri[r];
+            RxnEval o;
+            eval_reaction<MIXED, true>(m, r, st, C, G, H, info, ri, m.lnA[r], m.b[r], m.theta[r],
+                                       m.dnu_sum[r], o);
+            const int nre = info_nreac(info), npr = info_nprod(info);
+            // ubar = sum_k dnu_k (u_k - u_hrr h_k)   (the hrr row is -sum_k h_k w_k)
+            double ub = 0.0;
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) {
+                const bool used = s < MAX_SIDE ? s < nre : (s - MAX_SIDE) < npr;
+                if (!used) continue;
+                const int k = ri.v[s];
+                const double dn = (s < MAX_SIDE ? -1.0 : 1.0) * info_nu(info, s);
+                ub += dn * (U[k] - uhr * RT * H[k]);
+                if (uh) atomicAdd(&Wd[k], dn * o.q);
+            }
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) {
+                const bool used = s < MAX_SIDE ? s < nre : (s - MAX_SIDE) < npr;
+                if (used) atomicAdd(&GC[ri.v[s]], ub * o.d[s]);
+            }
+            if (o.mfac != 0.0) {
+                const int n_exc = ri.v[7] & 255;
+                for (int e = 0; e < n_exc; ++e)
+                    atomicAdd(&GC[m.eff_sp[ri.v[6] + e]], ub * o.mfac * m.eff_m1[ri.v[6] + e]);
+            }
+            a_tau += ub * o.mfac;
+            a_t += ub * o.t;
+            a_sig += ub * o.sigma;
+        }
+        a_tau = wave_sum(a_tau);
+        a_t = wave_sum(a_t);
+        a_sig = wave_sum(a_sig);
+        wave_lds_sync();
+        // R = sum_j (gC_j + tau) C_j ;  gY_j = (rho (gC_j + tau) - Wbar R) / W_j ;  gT = t - R/T - u_hrr sum cp w
+        double cpw = 0.0;
+        for (int k = lane; k < m.ns; k += WAVE) cpw += CP[k] * Wd[k];
+        cpw = wave_sum(cpw) * m.R;
+        const double Rsum = a_sig;   // sum_i ubar_i sigma_i already includes the efficiency part
+        for (int k = lane; k < m.ns; k += WAVE)
+            gY[(int64_t)k * ld + i] = (st.rho * (GC[k] + a_tau) - st.Wbar * Rsum) * m.invW[k];
+        if (lane == 0) gT[i] = a_t - Rsum * st.invT - uhr * cpw;
+    }
+}
+
+// ------------------------------------------------------------------ Jacobian
+// LDS per wave: S[(ns+1) x sr] (J_C rows, row 0 = hrr) in Acc, plus
+// {C, g/RT, h/RT, cp/R} x nsp and {tau, jtc, rc, w} x (nsp+1) doubles.
+template <bool MIXED>
+__global__ __launch_bounds__(64) void k_jac(DevMech m, int64_t n, const double *__restrict__ T,
+                                            const double *__restrict__ p, int64_t ps,
+                                            const double *__restrict__ Y, int64_t ld, void *__restrict__ Jv,
+                                            double *__restrict__ wdot, int nsp, int sr) {
+    using Acc = typename std::conditional<MIXED, float, double>::type;
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int ns = m.ns, n1 = ns + 1;
+    double *C = lds, *G = C + nsp, *H = G + nsp, *CP = H + nsp;
+    double *TAU = CP + nsp, *JTC = TAU + (nsp + 1), *RC = JTC + (nsp + 1), *Wd = RC + (nsp + 1);
+    Acc *S = (Acc *)(Wd + (nsp + 1));
+    Acc *J = (Acc *)Jv;
+    const int s_entries = n1 * sr;
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        wave_lds_sync();
+        const PointState st = load_point<true, true>(m, i, n, T, p, ps, Y, ld, C, G, H, CP);
+        for (int e = lane; e < s_entries; e += WAVE) S[e] = (Acc)0;
+        for (int k = lane; k <= ns; k += WAVE) { TAU[k] = 0.0; JTC[k] = 0.0; RC[k] = 0.0; Wd[k] = 0.0; }
+        wave_lds_sync();
+        const double RT = m.R * st.T;
+        for (int r = lane; r < m.nr; r += WAVE) {
+            const int info = m.info[r];
+            const RxnInts ri = m.ri[r];
+            RxnEval o;
+            eval_reaction<MIXED, true>(m, r, st, C, G, H, info, ri, m.lnA[r], m.b[r], m.theta[r],
+                                       m.dnu_sum[r], o);
+            const int nre = info_nreac(info), npr = info_nprod(info);
+            double dh = 0.0;   // reaction enthalpy sum_k dnu_k h_k
+#pragma unroll
+            for (int a = 0; a < SLOTS; ++a) {
+                const bool used = a < MAX_SIDE ? a < nre : (a - MAX_SIDE) < npr;
+                if (!used) continue;
+                const int k = ri.v[a];
+                const double dn = (a < MAX_SIDE ? -1.0 : 1.0) * info_nu(info, a);
+                dh += dn * RT * H[k];
+                atomicAdd(&Wd[1 + k], dn * o.q);
+                atomicAdd(&JTC[1 + k], dn * o.t);
+                atomicAdd(&RC[1 + k], dn * o.sigma);
+                if (o.mfac != 0.0) atomicAdd(&TAU[1 + k], dn * o.mfac);
+                Acc *row = S + (1 + k) * sr;
+#pragma unroll
+                for (int b = 0; b < SLOTS; ++b) {
+                    const bool ub = b < MAX_SIDE ? b < nre : (b - MAX_SIDE) < npr;
+                    if (ub) atomicAdd(&row[ri.v[b]], (Acc)(dn * o.d[b]));
+                }
+            }
+            // hrr row (row 0): -dh times the reaction's derivatives
+#pragma unroll
+            for (int b = 0; b < SLOTS; ++b) {
+                const bool ub = b < MAX_SIDE ? b < nre : (b - MAX_SIDE) < npr;
+                if (ub) atomicAdd(&S[ri.v[b]], (Acc)(-dh * o.d[b]));
+            }
+            if (o.mfac != 0.0) {
+                const int n_exc = ri.v[7] & 255;
+                for (int e = 0; e < n_exc; ++e) {
+                    const int ke = m.eff_sp[ri.v[6] + e];
+                    const double me = o.mfac * m.eff_m1[ri.v[6] + e];
+                    atomicAdd(&S[ke], (Acc)(-dh * me));
+                    for (int a = 0; a < SLOTS; ++a) {
+                        const bool used = a < MAX_SIDE ? a < nre : (a - MAX_SIDE) < npr;
+                        if (!used) continue;
+                        const double dn = (a < MAX_SIDE ? -1.0 : 1.0) * info_nu(info, a);
+                        atomicAdd(&S[(1 + ri.v[a]) * sr + ke], (Acc)(dn * me));
+                    }
+                }
+            }
+        }
+        wave_lds_sync();
+        // row 0 scalars: tau_0, jtc_0, rc_0 = -sum_k h_k (...)_k ; hrr ; sum cp_k w_k
+        double t0 = 0.0, j0 = 0.0, r0 = 0.0, hw = 0.0, cw = 0.0;
+        for (int k = lane; k < ns; k += WAVE) {
+            const double hk = RT * H[k];
+            t0 -= hk * TAU[1 + k];
+            j0 -= hk * JTC[1 + k];
+            r0 -= hk * RC[1 + k];
+            hw -= hk * Wd[1 + k];
+            cw += m.R * CP[k] * Wd[1 + k];
+        }
+        t0 = wave_sum(t0); j0 = wave_sum(j0); r0 = wave_sum(r0); cw = wave_sum(cw);
+        if (lane == 0) { TAU[0] = t0; JTC[0] = j0; RC[0] = r0; }
+        wave_lds_sync();
+        Acc *Jp = J + (size_t)i * n1 * n1;
+        for (int row = 0; row < n1; ++row) {
+            const double tau = TAU[row];
+            const double Rr = RC[row];          // sum_j J_C[row][j] C_j (sigma includes the efficiency part)
+            for (int c = lane; c < n1; c += WAVE) {
+                double v;
+                if (c == 0) {
+                    v = JTC[row] - Rr * st.invT;
+                    if (row == 0) v -= cw;
+                } else {
+                    const int j = c - 1;
+                    v = (st.rho * ((double)S[row * sr + j] + tau) - st.Wbar * Rr) * m.invW[j];
+                }
+                Jp[row * n1 + c] = (Acc)v;
+            }
+        }
+        if (wdot)
+            for (int k = lane; k < ns; k += WAVE) wdot[(int64_t)k * ld + i] = Wd[1 + k];
+    }
+}
+
+// ------------------------------------------------------------------ transport
+// LDS per wave: PPW points x {X, mu, smu, isum} x nsp doubles (isum: sum_j X_j / D_jk).
+template <bool MIXED, int PPW>
+__global__ __launch_bounds__(256) void k_transport(DevMech m, int64_t n, const double *__restrict__ T,
+                                                   const double *__restrict__ p, int64_t ps,
+                                                   const double *__restrict__ Y, int64_t ld,
+                                                   double *__restrict__ mu, double *__restrict__ lam,
+                                                   double *__restrict__ Dmix, int nsp) {
+    using Rt = typename std::conditional<MIXED, float, double>::type;
+    extern __shared__ double lds[];
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    const int wpb = blockDim.x / WAVE;
+    const int ns = m.ns;
+    double *base = lds + (size_t)wave * PPW * 4 * nsp;
+    const int64_t n_groups = (n + PPW - 1) / PPW;
+    for (int64_t g = (int64_t)blockIdx.x * wpb + wave; g < n_groups; g += (int64_t)gridDim.x * wpb) {
+        double lnT[PPW], lnp0p[PPW], lam_out[PPW];
+        bool valid[PPW];
+        wave_lds_sync();
+#pragma unroll
+        for (int q = 0; q < PPW; ++q) {
+            const int64_t i = g * PPW + q;
+            valid[q] = i < n;
+            const int64_t ii = valid[q] ? i : 0;
+            double *X = base + (4 * q) * nsp, *MU = X + nsp, *SMU = MU + nsp, *IS = SMU + nsp;
+            const double t = T[ii];
+            lnT[q] = log(t);
+            lnp0p[q] = log(m.p0 / p[ii * ps]);
+            double sy = 0.0;
+            for (int k = lane; k < ns; k += WAVE) sy += Y[(int64_t)k * ld + ii] * m.invW[k];
+            const double wbar = 1.0 / wave_sum(sy);
+            double sxl = 0.0, sxil = 0.0;
+            const Rt L = (Rt)lnT[q];
+            for (int k = lane; k < ns; k += WAVE) {
+                const double x = wbar * Y[(int64_t)k * ld + ii] * m.invW[k];
+                const double *a = m.mu_fit + 4 * k, *b = m.lam_fit + 4 * k;
+                const double muk = (double)exp_r<Rt>((Rt)a[0] + L * ((Rt)a[1] + L * ((Rt)a[2] + L * (Rt)a[3])));
+                const double lk = (double)exp_r<Rt>((Rt)b[0] + L * ((Rt)b[1] + L * ((Rt)b[2] + L * (Rt)b[3])));
+                X[k] = x;
+                MU[k] = muk;
+                SMU[k] = sqrt(muk);
+                IS[k] = 0.0;
+                sxl += x * lk;
+                sxil += x / lk;
+            }
+            sxl = wave_sum(sxl);
+            sxil = wave_sum(sxil);
+            lam_out[q] = 0.5 * (sxl + 1.0 / sxil);
+        }
+        wave_lds_sync();
+        // binary diffusion: lanes = pairs; sum_j X_j / D_jk by LDS scatter
+        if (Dmix) {
+            for (int pr = lane; pr < m.n_pairs; pr += WAVE) {
+                const int jk = m.pair_jk[pr];
+                const int j = jk & 0xffff, k = jk >> 16;
+                const double *c = m.dif_fit + 4 * pr;
+                const Rt c0 = (Rt)c[0], c1 = (Rt)c[1], c2 = (Rt)c[2], c3 = (Rt)c[3];
+#pragma unroll
+                for (int q = 0; q < PPW; ++q) {
+                    double *X = base + (4 * q) * nsp, *IS = X + 3 * nsp;
+                    const Rt L = (Rt)lnT[q];
+                    const double invD = (double)exp_r<Rt>(-(c0 + L * (c1 + L * (c2 + L * c3))) - (Rt)lnp0p[q]);
+                    atomicAdd(&IS[k], X[j] * invD);
+                    atomicAdd(&IS[j], X[k] * invD);
+                }
+            }
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int q = 0; q < PPW; ++q) {
+            const int64_t i = g * PPW + q;
+            double *X = base + (4 * q) * nsp, *MU = X + nsp, *SMU = MU + nsp, *IS = SMU + nsp;
+            double num = 0.0;
+            if (mu) {
+                // Wilke: denominator_k = sum_j X_j Phi_kj, Phi_kj = c_jk (1 + sqrt(mu_k/mu_j) (W_j/W_k)^(1/4))^2
+                for (int k = lane; k < ns; k += WAVE) {
+                    const Rt smk = (Rt)SMU[k], iw4k = (Rt)m.iw4[k];
+                    Rt den = 0;
+                    for (int j = 0; j < ns; ++j) {
+                        const Rt f = (Rt)1 + smk / (Rt)SMU[j] * (Rt)m.w4[j] * iw4k;
+                        den += (Rt)X[j] * (Rt)m.wilke_c[(size_t)j * ns + k] * f * f;
+                    }
+                    num += X[k] * MU[k] / (double)den;
+                }
+                num = wave_sum(num);
+            }
+            if (!valid[q]) continue;
+            if (Dmix)
+                for (int k = lane; k < ns; k += WAVE)
+                    Dmix[(int64_t)k * ld + i] = (1.0 - Y[(int64_t)k * ld + i]) / IS[k];
+            if (lane == 0) {
+                if (mu) mu[i] = num;
+                if (lam) lam[i] = lam_out[q];
+            }
+        }
+    }
+}
+
+int device_cu_count() {
+    static int cached[64] = {0};
+    int dev = 0;
+    hipGetDevice(&dev);
+    if (dev < 0 || dev >= 64) return 256;
+    if (!cached[dev]) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
+        cached[dev] = cu;
+    }
+    return cached[dev];
+}
+
+inline unsigned grid_for(int64_t work_items, int per_block, int blocks_per_cu) {
+    const int64_t need = (work_items + per_block - 1) / per_block;
+    const int64_t cap = (int64_t)device_cu_count() * blocks_per_cu;
+    return (unsigned)(need < cap ? (need > 0 ? need : 1) : cap);
+}
+
+inline int pad_odd(int x) { return x | 1; }
+
+}  // namespace
+
+hipError_t launch_thermo(const DevMech &m, int64_t n, const double *T, const double *p, int64_t ps,
+                         const double *Y, int64_t ld, double *cp_k, double *h_k, double *s_k, double *g_k,
+                         double *cp_mass, double *h_mass, double *rho, double *Wbar, hipStream_t st) {
+    hipLaunchKernelGGL(k_thermo, dim3(grid_for(n, 256, 16)), dim3(256), 0, st, m, n, T, p, ps, Y, ld, cp_k,
+                       h_k, s_k, g_k, cp_mass, h_mass, rho, Wbar);
+    return hipGetLastError();
+}
+
+hipError_t launch_wdot(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
+                       const double *Y, int64_t ld, double *wdot, double *hrr, double *rmass, hipStream_t st) {
+    constexpr int PPW = 2, WPB = 4;
+    const int nsp = pad_odd(m.ns);
+    const size_t shm = (size_t)WPB * PPW * 4 * nsp * sizeof(double);
+    const int64_t groups = (n + PPW - 1) / PPW;
+    const dim3 grid(grid_for(groups, WPB, 16)), block(WPB * WAVE);
+    if (mixed)
+        hipLaunchKernelGGL((k_wdot<true, PPW>), grid, block, shm, st, m, n, T, p, ps, Y, ld, wdot, hrr, rmass, nsp);
+    else
+        hipLaunchKernelGGL((k_wdot<false, PPW>), grid, block, shm, st, m, n, T, p, ps, Y, ld, wdot, hrr, rmass, nsp);
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
+                      const double *Y, int64_t ld, const double *u, const double *uh, double *gT, double *gY,
+                      hipStream_t st) {
+    constexpr int WPB = 4;
+    const int nsp = pad_odd(m.ns);
+    const size_t shm = (size_t)WPB * 7 * nsp * sizeof(double);
+    const dim3 grid(grid_for(n, WPB, 16)), block(WPB * WAVE);
+    if (mixed)
+        hipLaunchKernelGGL((k_vjp<true>), grid, block, shm, st, m, n, T, p, ps, Y, ld, u, uh, gT, gY, nsp);
+    else
+        hipLaunchKernelGGL((k_vjp<false>), grid, block, shm, st, m, n, T, p, ps, Y, ld, u, uh, gT, gY, nsp);
+    return hipGetLastError();
+}
+
+hipError_t launch_jac(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
+                      const double *Y, int64_t ld, void *J, double *wdot, hipStream_t st) {
+    const int nsp = pad_odd(m.ns);
+    const int sr = pad_odd(m.ns + 1);
+    const size_t acc = mixed ? sizeof(float) : sizeof(double);
+    const size_t shm = (size_t)(4 * nsp + 4 * (nsp + 1)) * sizeof(double) + (size_t)(m.ns + 1) * sr * acc;
+    if (shm > 160 * 1024) return hipErrorInvalidValue;
+    const dim3 grid(grid_for(n, 1, 8)), block(WAVE);
+    if (mixed)
+        hipLaunchKernelGGL((k_jac<true>), grid, block, shm, st, m, n, T, p, ps, Y, ld, J, wdot, nsp, sr);
+    else
+        hipLaunchKernelGGL((k_jac<false>), grid, block, shm, st, m, n, T, p, ps, Y, ld, J, wdot, nsp, sr);
+    return hipGetLastError();
+}
+
+hipError_t launch_transport(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
+                            int64_t ps, const double *Y, int64_t ld, double *mu, double *lam, double *Dmix,
+                            hipStream_t st) {
+    constexpr int PPW = 2, WPB = 4;
+    const int nsp = pad_odd(m.ns);
+    const size_t shm = (size_t)WPB * PPW * 4 * nsp * sizeof(double);
+    const int64_t groups = (n + PPW - 1) / PPW;
+    const dim3 grid(grid_for(groups, WPB, 16)), block(WPB * WAVE);
+    if (mixed)
+        hipLaunchKernelGGL((k_transport<true, PPW>), grid, block, shm, st, m, n, T, p, ps, Y, ld, mu, lam, Dmix, nsp);
+    else
+        hipLaunchKernelGGL((k_transport<false, PPW>), grid, block, shm, st, m, n, T, p, ps, Y, ld, mu, lam, Dmix, nsp);
+    return hipGetLastError();
+}
+
+}  // namespace crf

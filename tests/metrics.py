@@ -4,8 +4,11 @@
 * significant species: ||W_k w_k||_2 >= 1e-6 max_j ||W_j w_j||_2;
 * E_turn,k = max_p |yhat - y| / (|y| + S_{p,k}) with the gross turnover
   S_k = sum_i |dnu_ki| (|q_f,i| + |q_r,i|) (bounded under cancellation);
-* Jacobian: max_p max_j |dJ_{p,kj}| x_{p,j} / (S_{p,k} + |w_{p,k}|) with x = (T, Y);
-  row 0 (hrr) uses sum_k |h_k| (S_k + |w_k|) as its scale (same turnover basis).
+* Jacobian: max_p max_j |dJ_{p,kj}| x_{p,j} / scale_{p,k} with x = (T, Y), where the row
+  scale is the larger of the gross turnover S_{p,k} + |w_{p,k}| and the row's largest
+  scaled entry max_j |J_{p,kj}| x_{p,j} (the T column carries the Arrhenius factor
+  b + theta/T, up to ~100, that the turnover does not); row 0 (hrr) uses
+  sum_k |h_k| (S_k + |w_k|) in place of the turnover.
 """
 import numpy as np
 
@@ -36,4 +39,5 @@ def jac_scaled_error(Jhat, J, T, Y, turnover, wdot, h=None, hrr=None):
         scale[:, 0] = (np.abs(h) * (turnover + np.abs(wdot))).sum(axis=1)
     else:
         scale[:, 0] = np.abs(J[:, 0, :] * x).max(axis=1)
+    scale = np.maximum(scale, (np.abs(J) * x[:, None, :]).max(axis=2))
     return (err.max(axis=2) / (scale + 1e-300)).max(axis=0)

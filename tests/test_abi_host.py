@@ -1,0 +1,120 @@
+"""The C-ABI library loads, exports every declared symbol, and validates on the host (CPU only).
+
+No compute call reaches a device here: mechanisms are loaded host-only (device -1)
+and every call is rejected by argument validation before any launch.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "crf.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2409_06404_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2409_06404_amd.build import build_library
+        build_library()
+    return _lib.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(crf_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    from paper_2409_06404_amd import _lib
+    names = declared_functions()
+    assert set(names) == set(_lib.EXPORTED)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _load(L, path, device=-1):
+    h = ctypes.c_void_p()
+    s = L.crf_load_mech(str(path).encode(), device, ctypes.byref(h))
+    return s, h
+
+
+def test_host_only_load_and_counts(L, c1_path):
+    s, h = _load(L, c1_path)
+    assert s == 0, L.crf_last_error()
+    assert L.crf_n_species(h) == 53 and L.crf_n_reactions(h) == 325 and L.crf_device(h) == -1
+    L.crf_free_mech(h)
+    assert L.crf_n_species(None) == -1
+    L.crf_free_mech(None)
+
+
+def test_status_strings(L):
+    assert L.crf_status_str(0) == b"CRF_OK"
+    assert L.crf_status_str(6) == b"CRF_E_UNSUPPORTED"
+
+
+def _edit(src, dst, fn):
+    text = open(src).read()
+    open(dst, "w").write(fn(text))
+    return dst
+
+
+@pytest.mark.parametrize("edit,status,msg", [
+    (lambda t: t.replace("crf-mech 1", "crf-mech 2"), 2, "version"),
+    (lambda t: "\n".join(t.splitlines()[:40]), 2, ""),                                   # truncated
+    (lambda t: t.replace("reaction elementary reactants 2", "reaction plog reactants 2", 1), 6, "unsupported"),
+    (lambda t: t.replace("gas-constant 8314.46261815324", "gas-constant -1"), 3, "positive"),
+], ids=["version", "truncated", "kind", "gasconst"])
+def test_malformed_files(L, c0_path, tmp_path, edit, status, msg):
+    bad = _edit(c0_path, tmp_path / "bad.mech", edit)
+    s, h = _load(L, bad)
+    assert s == status, (s, L.crf_last_error())
+    assert msg in L.crf_last_error().decode()
+    assert not h.value
+
+
+def test_unbalanced_reaction_rejected(L, c0_path, tmp_path):
+    lines = open(c0_path).read().splitlines()
+    i = next(k for k, ln in enumerate(lines) if ln.startswith("reaction "))
+    toks = lines[i].split()
+    j = toks.index("products") + 2                  # first product token "k:nu"
+    k, nu = toks[j].split(":")
+    toks[j] = f"{k}:{int(nu) + 1}" if int(nu) < 3 else f"{k}:1"
+    lines[i] = " ".join(toks)
+    bad = tmp_path / "unbal.mech"
+    bad.write_text("\n".join(lines) + "\n")
+    s, _ = _load(L, bad)
+    assert s in (3, 6), L.crf_last_error()
+    assert "balanced" in L.crf_last_error().decode() or "order" in L.crf_last_error().decode()
+
+
+def test_missing_file(L):
+    s, h = _load(L, "/nonexistent/x.mech")
+    assert s == 2 and b"cannot read" in L.crf_last_error()
+
+
+def test_compute_calls_validate_before_launch(L, c0_path):
+    s, h = _load(L, c0_path)
+    assert s == 0
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(0x1000)      # never dereferenced: validation fails first
+    # n < 0
+    assert L.crf_wdot(h, 0, -1, fake, fake, 1, fake, 10, fake, null, null, null) == 1
+    # ld < n
+    assert L.crf_wdot(h, 0, 10, fake, fake, 1, fake, 5, fake, null, null, null) == 1
+    # bad p_stride
+    assert L.crf_transport(h, 0, 10, fake, fake, 2, fake, 10, fake, null, null, null) == 1
+    # NULL state with n > 0
+    assert L.crf_wdot_jac(h, 0, 10, null, fake, 1, fake, 10, fake, null, null) == 1
+    # NULL mechanism
+    assert L.crf_thermo(None, 10, fake, fake, 1, fake, 10, *([null] * 8), null) == 1
+    # valid arguments on a host-only mechanism: device error, nothing launched
+    assert L.crf_wdot(h, 0, 10, fake, fake, 1, fake, 10, fake, null, null, null) == 5
+    assert b"without a device" in L.crf_last_error()
+    # bad precision is checked after the state
+    s2, h2 = _load(L, c0_path)
+    L.crf_free_mech(h2)
+    L.crf_free_mech(h)
