@@ -31,6 +31,29 @@ def jac_bytes_per_point(ns, prec):
     return 8 * (2 + ns) + (8 if prec == "fp64" else 4) * n1 * n1 + 8 * ns
 
 
+def kernel_source_hash():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2409_06404_amd", "csrc", "kernels.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def recorded_traffic(prec):
+    """HBM bytes per launch of k_jac from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"k_jac_{prec}_c3_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if line.startswith("RESULT "):
+            for tok in line.split()[1:]:
+                k, v = tok.split("=")
+                rec[k] = v
+    if rec.get("kernel_sha") != kernel_source_hash():
+        return None
+    return float(rec["bytes_per_launch"])
+
+
 def timed(fn, steps, warmup, stream):
     import torch
     for _ in range(warmup):
@@ -73,6 +96,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None, help="time one precision only")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (the reference for HBM byte counters)")
+    ap.add_argument("--no-path", action="store_true", help="time the fused wdot+Jacobian call only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -98,6 +124,13 @@ def main():
         Y = torch.from_numpy(st["Y"]).to(dev).t()
         u = torch.randn((ns, n), dtype=torch.float64, device=dev).t()
         stream = torch.cuda.current_stream(dev)
+        if args.calib_copy:
+            a = torch.ones(1 << 27, dtype=torch.float64, device=dev)     # 1 GiB
+            b = torch.empty_like(a)
+            b.copy_(a)
+            torch.cuda.synchronize()
+            del a, b
+            torch.cuda.empty_cache()
         res = {}
         precs = [args.only] if args.only else ["fp64", "mixed"]
         for prec in precs:
@@ -108,18 +141,19 @@ def main():
             achieved = bpp * n / (ms * 1e-3) / 1e9
             res[prec] = {"value": n / (ms * 1e-3) / 1e6, "ms_per_step": ms,
                          "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(prec),
                                       "bytes_per_point": bpp, "kernel": "k_jac<%s>" % ("false" if prec == "fp64" else "true")}}
             del J
             torch.cuda.empty_cache()
         path = {}
-        for prec in precs:
+        for prec in ([] if args.no_path else precs):
             path[prec] = {
                 "wdot": n / (timed(lambda: crf.wdot(m, T, p, Y, prec, hrr=True), args.steps, 1, stream) * 1e-3) / 1e6,
                 "transport": n / (timed(lambda: crf.transport(m, T, p, Y, prec), max(2, args.steps // 4), 1, stream) * 1e-3) / 1e6,
                 "vjp": n / (timed(lambda: crf.wdot_vjp(m, T, p, Y, u, None, prec), args.steps, 1, stream) * 1e-3) / 1e6,
             }
-        path["fp64"]["thermo"] = n / (timed(lambda: crf.thermo(m, T, p, Y), args.steps, 1, stream) * 1e-3) / 1e6
+        if "fp64" in path:
+            path["fp64"]["thermo"] = n / (timed(lambda: crf.thermo(m, T, p, Y), args.steps, 1, stream) * 1e-3) / 1e6
         m.close()
         head = "fp64" if "fp64" in res else precs[0]
         out = {

@@ -315,9 +315,11 @@ __global__ __launch_bounds__(256) void k_wdot(DevMech m, int64_t n, const double
                        *Wd = base + (4 * q + 3) * nsp;
                 RxnEval o;
                 eval_reaction<MIXED, false>(m, r, st[q], C, G, nullptr, info, ri, lnA, bb, th, dsum, o);
-                for (int s = 0; s < nre; ++s) atomicAdd(&Wd[ri.v[s]], -(double)info_nu(info, s) * o.q);
-                for (int s = 0; s < npr; ++s)
-                    atomicAdd(&Wd[ri.v[MAX_SIDE + s]], (double)info_nu(info, MAX_SIDE + s) * o.q);
+#pragma unroll
+                for (int s = 0; s < SLOTS; ++s) {
+                    const bool used = s < MAX_SIDE ? s < nre : (s - MAX_SIDE) < npr;
+                    if (used) atomicAdd(&Wd[ri.v[s]], (s < MAX_SIDE ? -1.0 : 1.0) * info_nu(info, s) * o.q);
+                }
             }
         }
         wave_lds_sync();
@@ -416,13 +418,22 @@ __global__ __launch_bounds__(256) void k_vjp(DevMech m, int64_t n, const double 
 }
 
 // ------------------------------------------------------------------ Jacobian
-// LDS per wave: S[(ns+1) x sr] (J_C rows, row 0 = hrr) in Acc, plus
-// {C, g/RT, h/RT, cp/R} x nsp and {tau, jtc, rc, w} x (nsp+1) doubles.
+// Rows 0..Ns of the Jacobian (row 0 = hrr) are assembled in blocks of `rb` rows:
+// S[(row - r0) * sr + j] = sum_i dnu_row,i dq_i/dC_j (mass-action and efficiency
+// exceptions; row 0 uses -sum_k h_k dnu_ki), then
+//   J[row][T]   = jtc[row] - R[row]/T (- sum_k cp_k w_k for row 0)
+//   J[row][Y_j] = (rho (S[row][j] + tau[row]) - Wbar R[row]) / W_j
+// with tau = sum_i dnu_i dq_i/d[M] (the efficiency-1 part of every column),
+// R = sum_i dnu_i sum_j C_j dq_i/dC_j, jtc = sum_i dnu_i dq_i/dT at fixed C.
+// With 53 species the whole matrix is one block; larger mechanisms repeat the
+// reaction pass per block instead of exceeding one wavefront's LDS.
+// LDS per wave: {C, g/RT, h/RT, cp/R} x nsp and {tau, jtc, R, w} x (nsp+1)
+// doubles, plus rb x sr accumulators (FP64, or FP32 in the mixed mode).
 template <bool MIXED>
 __global__ __launch_bounds__(64) void k_jac(DevMech m, int64_t n, const double *__restrict__ T,
                                             const double *__restrict__ p, int64_t ps,
                                             const double *__restrict__ Y, int64_t ld, void *__restrict__ Jv,
-                                            double *__restrict__ wdot, int nsp, int sr) {
+                                            double *__restrict__ wdot, int nsp, int sr, int rb) {
     using Acc = typename std::conditional<MIXED, float, double>::type;
     extern __shared__ double lds[];
     const int lane = threadIdx.x & (WAVE - 1);
@@ -431,90 +442,124 @@ __global__ __launch_bounds__(64) void k_jac(DevMech m, int64_t n, const double *
     double *TAU = CP + nsp, *JTC = TAU + (nsp + 1), *RC = JTC + (nsp + 1), *Wd = RC + (nsp + 1);
     Acc *S = (Acc *)(Wd + (nsp + 1));
     Acc *J = (Acc *)Jv;
-    const int s_entries = n1 * sr;
+    const float inv_n1 = 1.0f / (float)n1;
     for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
         wave_lds_sync();
         const PointState st = load_point<true, true>(m, i, n, T, p, ps, Y, ld, C, G, H, CP);
-        for (int e = lane; e < s_entries; e += WAVE) S[e] = (Acc)0;
         for (int k = lane; k <= ns; k += WAVE) { TAU[k] = 0.0; JTC[k] = 0.0; RC[k] = 0.0; Wd[k] = 0.0; }
-        wave_lds_sync();
         const double RT = m.R * st.T;
-        for (int r = lane; r < m.nr; r += WAVE) {
-            const int info = m.info[r];
-            const RxnInts ri = m.ri[r];
-            RxnEval o;
-            eval_reaction<MIXED, true>(m, r, st, C, G, H, info, ri, m.lnA[r], m.b[r], m.theta[r],
-                                       m.dnu_sum[r], o);
-            const int nre = info_nreac(info), npr = info_nprod(info);
-            double dh = 0.0;   // reaction enthalpy sum_k dnu_k h_k
+        double cw = 0.0;
+        Acc *Jp = J + (size_t)i * n1 * n1;
+        for (int r0 = 0; r0 < n1; r0 += rb) {
+            const int r1 = r0 + rb < n1 ? r0 + rb : n1;
+            const bool first = r0 == 0;
+            for (int e = lane; e < (r1 - r0) * sr; e += WAVE) S[e] = (Acc)0;
+            wave_lds_sync();
+            for (int r = lane; r < m.nr; r += WAVE) {
+                const int info = m.info[r];
+                const RxnInts ri = m.ri[r];
+                RxnEval o;
+                eval_reaction<MIXED, true>(m, r, st, C, G, H, info, ri, m.lnA[r], m.b[r], m.theta[r],
+                                           m.dnu_sum[r], o);
+                const int nre = info_nreac(info), npr = info_nprod(info);
+                double dh = 0.0;   // reaction enthalpy sum_k dnu_k h_k
 #pragma unroll
-            for (int a = 0; a < SLOTS; ++a) {
-                const bool used = a < MAX_SIDE ? a < nre : (a - MAX_SIDE) < npr;
-                if (!used) continue;
-                const int k = ri.v[a];
-                const double dn = (a < MAX_SIDE ? -1.0 : 1.0) * info_nu(info, a);
-                dh += dn * RT * H[k];
-                atomicAdd(&Wd[1 + k], dn * o.q);
-                atomicAdd(&JTC[1 + k], dn * o.t);
-                atomicAdd(&RC[1 + k], dn * o.sigma);
-                if (o.mfac != 0.0) atomicAdd(&TAU[1 + k], dn * o.mfac);
-                Acc *row = S + (1 + k) * sr;
+                for (int a = 0; a < SLOTS; ++a) {
+                    const bool used = a < MAX_SIDE ? a < nre : (a - MAX_SIDE) < npr;
+                    if (!used) continue;
+                    const int k = ri.v[a];
+                    const double dn = (a < MAX_SIDE ? -1.0 : 1.0) * info_nu(info, a);
+                    dh += dn * RT * H[k];
+                    if (first) {
+                        atomicAdd(&Wd[1 + k], dn * o.q);
+                        atomicAdd(&JTC[1 + k], dn * o.t);
+                        atomicAdd(&RC[1 + k], dn * o.sigma);
+                        if (o.mfac != 0.0) atomicAdd(&TAU[1 + k], dn * o.mfac);
+                    }
+                    const int row = 1 + k;
+                    if (row >= r0 && row < r1) {
+                        Acc *Srow = S + (row - r0) * sr;
 #pragma unroll
-                for (int b = 0; b < SLOTS; ++b) {
-                    const bool ub = b < MAX_SIDE ? b < nre : (b - MAX_SIDE) < npr;
-                    if (ub) atomicAdd(&row[ri.v[b]], (Acc)(dn * o.d[b]));
+                        for (int b = 0; b < SLOTS; ++b) {
+                            const bool ub = b < MAX_SIDE ? b < nre : (b - MAX_SIDE) < npr;
+                            if (ub) atomicAdd(&Srow[ri.v[b]], (Acc)(dn * o.d[b]));
+                        }
+                    }
                 }
-            }
-            // hrr row (row 0): -dh times the reaction's derivatives
+                if (first) {   // hrr row: -dh times the reaction's derivatives
 #pragma unroll
-            for (int b = 0; b < SLOTS; ++b) {
-                const bool ub = b < MAX_SIDE ? b < nre : (b - MAX_SIDE) < npr;
-                if (ub) atomicAdd(&S[ri.v[b]], (Acc)(-dh * o.d[b]));
-            }
-            if (o.mfac != 0.0) {
-                const int n_exc = ri.v[7] & 255;
-                for (int e = 0; e < n_exc; ++e) {
-                    const int ke = m.eff_sp[ri.v[6] + e];
-                    const double me = o.mfac * m.eff_m1[ri.v[6] + e];
-                    atomicAdd(&S[ke], (Acc)(-dh * me));
-                    for (int a = 0; a < SLOTS; ++a) {
-                        const bool used = a < MAX_SIDE ? a < nre : (a - MAX_SIDE) < npr;
-                        if (!used) continue;
-                        const double dn = (a < MAX_SIDE ? -1.0 : 1.0) * info_nu(info, a);
-                        atomicAdd(&S[(1 + ri.v[a]) * sr + ke], (Acc)(dn * me));
+                    for (int b = 0; b < SLOTS; ++b) {
+                        const bool ub = b < MAX_SIDE ? b < nre : (b - MAX_SIDE) < npr;
+                        if (ub) atomicAdd(&S[ri.v[b]], (Acc)(-dh * o.d[b]));
+                    }
+                }
+                if (o.mfac != 0.0) {
+                    const int n_exc = ri.v[7] & 255;
+                    for (int e = 0; e < n_exc; ++e) {
+                        const int ke = m.eff_sp[ri.v[6] + e];
+                        const double me = o.mfac * m.eff_m1[ri.v[6] + e];
+                        if (first) atomicAdd(&S[ke], (Acc)(-dh * me));
+                        for (int a = 0; a < SLOTS; ++a) {
+                            const bool used = a < MAX_SIDE ? a < nre : (a - MAX_SIDE) < npr;
+                            const int row = used ? 1 + ri.v[a] : -1;
+                            if (row < r0 || row >= r1) continue;
+                            const double dn = (a < MAX_SIDE ? -1.0 : 1.0) * info_nu(info, a);
+                            atomicAdd(&S[(row - r0) * sr + ke], (Acc)(dn * me));
+                        }
                     }
                 }
             }
-        }
-        wave_lds_sync();
-        // row 0 scalars: tau_0, jtc_0, rc_0 = -sum_k h_k (...)_k ; hrr ; sum cp_k w_k
-        double t0 = 0.0, j0 = 0.0, r0 = 0.0, hw = 0.0, cw = 0.0;
-        for (int k = lane; k < ns; k += WAVE) {
-            const double hk = RT * H[k];
-            t0 -= hk * TAU[1 + k];
-            j0 -= hk * JTC[1 + k];
-            r0 -= hk * RC[1 + k];
-            hw -= hk * Wd[1 + k];
-            cw += m.R * CP[k] * Wd[1 + k];
-        }
-        t0 = wave_sum(t0); j0 = wave_sum(j0); r0 = wave_sum(r0); cw = wave_sum(cw);
-        if (lane == 0) { TAU[0] = t0; JTC[0] = j0; RC[0] = r0; }
-        wave_lds_sync();
-        Acc *Jp = J + (size_t)i * n1 * n1;
-        for (int row = 0; row < n1; ++row) {
-            const double tau = TAU[row];
-            const double Rr = RC[row];          // sum_j J_C[row][j] C_j (sigma includes the efficiency part)
-            for (int c = lane; c < n1; c += WAVE) {
-                double v;
-                if (c == 0) {
-                    v = JTC[row] - Rr * st.invT;
-                    if (row == 0) v -= cw;
-                } else {
-                    const int j = c - 1;
-                    v = (st.rho * ((double)S[row * sr + j] + tau) - st.Wbar * Rr) * m.invW[j];
+            wave_lds_sync();
+            if (first) {
+                // row 0 scalars: tau_0, jtc_0, R_0 = -sum_k h_k (...)_k ; sum cp_k w_k
+                double t0 = 0.0, j0 = 0.0, q0 = 0.0;
+                for (int k = lane; k < ns; k += WAVE) {
+                    const double hk = RT * H[k];
+                    t0 -= hk * TAU[1 + k];
+                    j0 -= hk * JTC[1 + k];
+                    q0 -= hk * RC[1 + k];
+                    cw += m.R * CP[k] * Wd[1 + k];
                 }
-                Jp[row * n1 + c] = (Acc)v;
+                t0 = wave_sum(t0); j0 = wave_sum(j0); q0 = wave_sum(q0); cw = wave_sum(cw);
+                if (lane == 0) { TAU[0] = t0; JTC[0] = j0; RC[0] = q0; }
+                wave_lds_sync();
             }
+            // emission of rows r0..r1-1: two consecutive entries per lane, 128 per pass
+            const int e_lo = r0 * n1, e_hi = r1 * n1;
+            // paired stores need a 2-element-aligned address (e0 has the parity of e_lo)
+            const bool vec_ok = (((uintptr_t)(Jp + e_lo)) & (2 * sizeof(Acc) - 1)) == 0;
+            for (int e0 = e_lo + 2 * lane; e0 < e_hi; e0 += 2 * WAVE) {
+                Acc v[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int e = e0 + t;
+                    double x = 0.0;
+                    if (e < e_hi) {
+                        // row = e / n1 from a float estimate, corrected to the exact quotient
+                        int row = (int)(((float)e + 0.5f) * inv_n1);
+                        int c = e - row * n1;
+                        if (c < 0) { row -= 1; c += n1; }
+                        if (c >= n1) { row += 1; c -= n1; }
+                        const double Rr = RC[row];
+                        if (c == 0) {
+                            x = JTC[row] - Rr * st.invT;
+                            if (row == 0) x -= cw;
+                        } else {
+                            x = (st.rho * ((double)S[(row - r0) * sr + c - 1] + TAU[row]) - st.Wbar * Rr) * m.invW[c - 1];
+                        }
+                    }
+                    v[t] = (Acc)x;
+                }
+                if (vec_ok && e0 + 1 < e_hi) {
+                    typedef Acc Acc2 __attribute__((ext_vector_type(2)));
+                    Acc2 vv = {v[0], v[1]};
+                    *(Acc2 *)(Jp + e0) = vv;
+                } else {
+                    Jp[e0] = v[0];
+                    if (e0 + 1 < e_hi) Jp[e0 + 1] = v[1];
+                }
+            }
+            wave_lds_sync();
         }
         if (wdot)
             for (int k = lane; k < ns; k += WAVE) wdot[(int64_t)k * ld + i] = Wd[1 + k];
@@ -681,15 +726,21 @@ hipError_t launch_vjp(const DevMech &m, int mixed, int64_t n, const double *T, c
 hipError_t launch_jac(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
                       const double *Y, int64_t ld, void *J, double *wdot, hipStream_t st) {
     const int nsp = pad_odd(m.ns);
-    const int sr = pad_odd(m.ns + 1);
+    const int n1 = m.ns + 1;
+    const int sr = pad_odd(n1);
     const size_t acc = mixed ? sizeof(float) : sizeof(double);
-    const size_t shm = (size_t)(4 * nsp + 4 * (nsp + 1)) * sizeof(double) + (size_t)(m.ns + 1) * sr * acc;
-    if (shm > 160 * 1024) return hipErrorInvalidValue;
+    const size_t fixed = (size_t)(4 * nsp + 4 * (nsp + 1)) * sizeof(double);
+    // rows per block: the whole matrix when it fits in ~48 KB, else as many rows as fit
+    const size_t budget = 48 * 1024;
+    int rb = (int)((budget > fixed ? budget - fixed : 0) / ((size_t)sr * acc));
+    if (rb >= n1) rb = n1;
+    if (rb < 1) return hipErrorInvalidValue;
+    const size_t shm = fixed + (size_t)rb * sr * acc;
     const dim3 grid(grid_for(n, 1, 8)), block(WAVE);
     if (mixed)
-        hipLaunchKernelGGL((k_jac<true>), grid, block, shm, st, m, n, T, p, ps, Y, ld, J, wdot, nsp, sr);
+        hipLaunchKernelGGL((k_jac<true>), grid, block, shm, st, m, n, T, p, ps, Y, ld, J, wdot, nsp, sr, rb);
     else
-        hipLaunchKernelGGL((k_jac<false>), grid, block, shm, st, m, n, T, p, ps, Y, ld, J, wdot, nsp, sr);
+        hipLaunchKernelGGL((k_jac<false>), grid, block, shm, st, m, n, T, p, ps, Y, ld, J, wdot, nsp, sr, rb);
     return hipGetLastError();
 }
 

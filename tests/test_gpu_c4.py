@@ -1,0 +1,109 @@
+"""Parity on the 200-species / 1500-reaction mechanism (300 three-body, 150 Troe), on the GPU.
+
+States are spectral-element blocks of 8^3 Gauss-Lobatto points with tanh flame
+fronts at 40 atm.  The Jacobian of this mechanism is assembled in several row
+blocks (one wavefront's LDS does not hold all 201 x 201 accumulators).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+from metrics import e_norm, e_turn, jac_scaled_error, significant_species  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+R = 8314.46261815324
+
+
+@pytest.fixture(scope="module")
+def c4(mech_dir):
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2409_06404_amd as crf
+    path = synth.write_mechanism(synth.MECH_C4, str(mech_dir / "c4.mech"))
+    g = crf.Mechanism(path, device=0)
+    yield crf, g, oracle.read_mechanism(path)
+    g.close()
+
+
+def _dev(st):
+    dev = torch.device("cuda", 0)
+    return (torch.from_numpy(st["T"]).to(dev), torch.from_numpy(st["p"]).to(dev),
+            torch.from_numpy(np.ascontiguousarray(st["Y"])).to(dev).t())
+
+
+def _sub(st, idx):
+    return {"T": st["T"][idx], "p": st["p"][idx], "Y": np.ascontiguousarray(st["Y"][:, idx])}
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_c4_wdot(c4, prec, tol):
+    crf, g, om = c4
+    st = synth.state_c4_launch(200, 2, seed=4, launch=0)          # 1024 points
+    T, p, Y = _dev(st)
+    w, h, r = crf.wdot(g, T, p, Y, prec, hrr=True, mass_resid=True)
+    torch.cuda.synchronize()
+    idx = np.arange(0, 1024, 3)
+    s = _sub(st, idx)
+    ref = oracle.production_rates(om, s["T"], s["p"], s["Y"].T)
+    got = w.cpu().numpy()[idx]
+    sig = significant_species(ref["wdot"], om.W)
+    en = e_norm(got, ref["wdot"])
+    print(f"c4 wdot {prec}: E_norm max {en[sig].max():.2e}", flush=True)
+    assert en[sig].max() <= tol
+    if prec == "fp64":
+        assert e_turn(got, ref["wdot"], ref["turnover"]).max() <= 1e-12
+    assert np.max(np.abs(r.cpu().numpy()[idx]) / (ref["turnover"] @ om.W)) <= 1e-13
+
+
+@pytest.mark.parametrize("prec,tol,npts", [("fp64", 1e-12, 6), ("mixed", 1e-5, 10)])
+def test_c4_jacobian_row_blocks(c4, prec, tol, npts):
+    crf, g, om = c4
+    st = synth.state_c4_launch(200, 1, seed=4, launch=3)
+    idx = np.linspace(0, 511, npts).astype(int)
+    s = _sub(st, idx)
+    T, p, Y = _dev(s)
+    J, w = crf.wdot_jac(g, T, p, Y, prec)
+    torch.cuda.synchronize()
+    Jr = oracle.jacobian(om, s["T"], s["p"], s["Y"].T)
+    out = oracle.production_rates(om, s["T"], s["p"], s["Y"].T)
+    _, hRT, _, _ = oracle.nasa7(om, s["T"])
+    err = jac_scaled_error(J.double().cpu().numpy(), Jr, s["T"], s["Y"].T, out["turnover"], out["wdot"],
+                           R * s["T"][:, None] * hRT, out["hrr"])
+    print(f"c4 jac {prec}: {err.max():.2e}", flush=True)
+    assert err.max() <= tol
+    assert e_turn(w.cpu().numpy(), out["wdot"], out["turnover"]).max() <= (1e-12 if prec == "fp64" else 1e-5)
+
+
+def test_c4_vjp(c4):
+    crf, g, om = c4
+    st = synth.state_c4_launch(200, 1, seed=4, launch=5)
+    idx = np.linspace(0, 511, 8).astype(int)
+    s = _sub(st, idx)
+    T, p, Y = _dev(s)
+    rng = np.random.default_rng(9)
+    u = rng.standard_normal((200, len(idx)))
+    gT, gY = crf.wdot_vjp(g, T, p, Y, torch.from_numpy(u).cuda().t())
+    torch.cuda.synchronize()
+    Jr = oracle.jacobian(om, s["T"], s["p"], s["Y"].T)
+    uu = np.concatenate([np.zeros((len(idx), 1)), u.T], axis=1)
+    gref = np.einsum("nr,nrc->nc", uu, Jr)
+    scale = np.einsum("nr,nrc->nc", np.abs(uu), np.abs(Jr)) + 1e-300
+    got = np.concatenate([gT.cpu().numpy()[:, None], gY.cpu().numpy()], axis=1)
+    assert np.max(np.abs(got - gref) / scale) <= 1e-11
+
+
+def test_c4_transport(c4):
+    crf, g, om = c4
+    st = synth.state_c4_launch(200, 1, seed=4, launch=6)
+    idx = np.linspace(0, 511, 12).astype(int)
+    s = _sub(st, idx)
+    T, p, Y = _dev(s)
+    mu, lam, D = crf.transport(g, T, p, Y, "fp64")
+    torch.cuda.synchronize()
+    ref = oracle.transport_properties(om, s["T"], s["p"], s["Y"].T)
+    assert np.max(np.abs(mu.cpu().numpy() / ref["mu"] - 1)) <= 1e-12
+    assert np.max(np.abs(lam.cpu().numpy() / ref["lambda"] - 1)) <= 1e-12
+    assert np.max(np.abs(D.cpu().numpy() / ref["Dmix"] - 1)) <= 1e-12
