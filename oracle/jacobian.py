@@ -67,8 +67,15 @@ def _troe_parts(T, M, lnA, b, theta, troe):
     return kf, dkf_dT, dkf_dM
 
 
-def jacobian(m, T, p, Y):
-    """J [n, Ns+1, Ns+1]: rows (hrr, w_1..Ns), columns (T, Y_1..Ns)."""
+def jacobian(m, T, p, Y, return_gross=False):
+    """J [n, Ns+1, Ns+1]: rows (hrr, w_1..Ns), columns (T, Y_1..Ns).
+
+    With return_gross, also the gross magnitude G of every entry: the same chain
+    rule with every reaction's contribution taken in absolute value,
+    G_kx = sum_i |dnu_ki| |dq_i/dx| (each chain-rule term separately), row 0 =
+    sum_k |h_k| G_kx (+ sum_k |cp_k w_k| for x = T).  G bounds the rounding of any
+    summation order of J the way the gross turnover bounds that of w.
+    """
     T = np.asarray(T)
     p = np.asarray(p)
     Y = np.asarray(Y)
@@ -80,6 +87,9 @@ def jacobian(m, T, p, Y):
     dtype = np.result_type(T, Y, p, float)
     JC = np.zeros((n, ns, ns), dtype=dtype)      # d w_k / d C_j
     JTC = np.zeros((n, ns), dtype=dtype)         # d w_k / d T at fixed C
+    if return_gross:
+        GY = np.zeros((n, ns, ns))
+        GT = np.zeros((n, ns))
     for i in range(m.n_reactions):
         M = C @ m.eff[i]
         if m.kind[i] == "troe":
@@ -127,6 +137,22 @@ def jacobian(m, T, p, Y):
         dq_dT = fac * (dkf_dT * bracket + kf * invKc * pr * dlnKc_dT)
         JC += dnu[i][None, :, None] * dq_dC[:, None, :]
         JTC += dnu[i][None, :] * dq_dT[:, None]
+        if return_gross:
+            a = np.zeros((n, ns))
+            for j, v in dpf.items():
+                a[:, j] += np.abs(fac * kf * v)
+            for j, v in dpr.items():
+                a[:, j] += np.abs(fac * kf * invKc * v)
+            if m.kind[i] == "threebody":
+                a += np.abs(kf * bracket)[:, None] * m.eff[i][None, :]
+            elif m.kind[i] == "troe":
+                a += np.abs(dkf_dM * bracket)[:, None] * m.eff[i][None, :]
+            sig = (a * C).sum(axis=1)
+            tabs = np.abs(fac) * (np.abs(dkf_dT * pf) + np.abs(dkf_dT * invKc * pr)
+                                  + np.abs(kf * invKc * pr * dlnKc_dT))
+            gy = rho[:, None] * a / m.W[None, :] + (Wbar[:, None] / m.W[None, :]) * sig[:, None]
+            GY += np.abs(dnu[i])[None, :, None] * gy[:, None, :]
+            GT += np.abs(dnu[i])[None, :] * (tabs + sig / T)[:, None]
     # chain rule to (T, Y)
     dC_dY = rho[:, None, None] * np.eye(ns)[None] / m.W[None, :, None] \
         - C[:, :, None] * (Wbar[:, None] / m.W[None, :])[:, None, :]          # [n, m, j]
@@ -140,7 +166,14 @@ def jacobian(m, T, p, Y):
     J[:, 1:, 1:] = JY
     J[:, 0, 0] = -(h * JT).sum(axis=1) - (cp * w).sum(axis=1)
     J[:, 0, 1:] = -np.einsum("nk,nkj->nj", h, JY)
-    return J
+    if not return_gross:
+        return J
+    G = np.zeros((n, ns + 1, ns + 1))
+    G[:, 1:, 0] = GT
+    G[:, 1:, 1:] = GY
+    G[:, 0, 0] = (np.abs(h) * GT).sum(axis=1) + np.abs(cp * w).sum(axis=1)
+    G[:, 0, 1:] = np.einsum("nk,nkj->nj", np.abs(h), GY)
+    return J, G
 
 
 def vjp(m, T, p, Y, u, u_hrr=None):

@@ -56,7 +56,21 @@ struct DevMech {
     const double *troe;       // [n_troe][8]: lnA0, b0, theta0, alpha, 1/T3, 1/T1, T2, 0
     const int *eff_sp;        // [n_exc]
     const double *eff_m1;     // [n_exc] eps - 1
+    // Jacobian gather schedule (see build_jac_schedule in mech.cpp); js_len == 0 if absent
+    const int *dofs;          // [nr] first per-point derivative slot of reaction i
+    const unsigned *jsched;   // [js_len][js_threads] packed records (build_jac_schedule)
+    int js_len, js_threads;
+    int rd_size, rd_exc, rd_t, rd_q, rd_mf, rd_sig;   // per-point reaction-data layout
+    int js_sr;                // row stride of the accumulator matrix (>= ns + 4)
 };
+
+// Register-schedule Jacobian kernel: threads per workgroup (3 wavefronts), most
+// schedule records per thread, reactions per thread, species (one per lane of the
+// state wavefront).
+constexpr int JAC_THREADS = 192;
+constexpr int JAC_SCHED_MAX = 64;
+constexpr int JAC_RXN_PER_THREAD = 2;
+constexpr int JAC_MAX_SPECIES = 64;
 
 // Host copy of a parsed mechanism.
 struct HostMech {
@@ -76,6 +90,10 @@ struct HostMech {
     std::vector<double> troe;            // [n_troe][8]
     std::vector<int> eff_sp;
     std::vector<double> eff_m1;
+    // Jacobian gather schedule
+    std::vector<int> dofs;
+    std::vector<unsigned> jsched;
+    int js_len = 0, rd_size = 0, rd_exc = 0, rd_t = 0, rd_q = 0, rd_mf = 0, rd_sig = 0, js_sr = 0;
     int ns() const { return (int)names.size(); }
     int nr() const { return (int)lnA.size(); }
 };
@@ -97,6 +115,7 @@ void clear_error();
 
 // Parsing / validation / upload (mech.cpp).
 crf_status parse_mechanism(const char *path, HostMech &out);
+void build_jac_schedule(HostMech &h, int threads);
 crf_status upload_mechanism(crf_mech *m, int device);
 
 // Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.

@@ -428,20 +428,21 @@ __global__ __launch_bounds__(256) void k_vjp(DevMech m, int64_t n, const double 
 // With 53 species the whole matrix is one block; larger mechanisms repeat the
 // reaction pass per block instead of exceeding one wavefront's LDS.
 // LDS per wave: {C, g/RT, h/RT, cp/R} x nsp and {tau, jtc, R, w} x (nsp+1)
-// doubles, plus rb x sr accumulators (FP64, or FP32 in the mixed mode).
+// doubles, plus rb x sr FP64 accumulators (the mixed mode stores J in FP32).
 template <bool MIXED>
 __global__ __launch_bounds__(64) void k_jac(DevMech m, int64_t n, const double *__restrict__ T,
                                             const double *__restrict__ p, int64_t ps,
                                             const double *__restrict__ Y, int64_t ld, void *__restrict__ Jv,
                                             double *__restrict__ wdot, int nsp, int sr, int rb) {
-    using Acc = typename std::conditional<MIXED, float, double>::type;
+    using Out = typename std::conditional<MIXED, float, double>::type;
+    using Acc = double;     // accumulate in FP64 in both modes; the mixed mode stores FP32
     extern __shared__ double lds[];
     const int lane = threadIdx.x & (WAVE - 1);
     const int ns = m.ns, n1 = ns + 1;
     double *C = lds, *G = C + nsp, *H = G + nsp, *CP = H + nsp;
     double *TAU = CP + nsp, *JTC = TAU + (nsp + 1), *RC = JTC + (nsp + 1), *Wd = RC + (nsp + 1);
     Acc *S = (Acc *)(Wd + (nsp + 1));
-    Acc *J = (Acc *)Jv;
+    Out *J = (Out *)Jv;
     const float inv_n1 = 1.0f / (float)n1;
     for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
         wave_lds_sync();
@@ -449,7 +450,7 @@ __global__ __launch_bounds__(64) void k_jac(DevMech m, int64_t n, const double *
         for (int k = lane; k <= ns; k += WAVE) { TAU[k] = 0.0; JTC[k] = 0.0; RC[k] = 0.0; Wd[k] = 0.0; }
         const double RT = m.R * st.T;
         double cw = 0.0;
-        Acc *Jp = J + (size_t)i * n1 * n1;
+        Out *Jp = J + (size_t)i * n1 * n1;
         for (int r0 = 0; r0 < n1; r0 += rb) {
             const int r1 = r0 + rb < n1 ? r0 + rb : n1;
             const bool first = r0 == 0;
@@ -527,9 +528,9 @@ __global__ __launch_bounds__(64) void k_jac(DevMech m, int64_t n, const double *
             // emission of rows r0..r1-1: two consecutive entries per lane, 128 per pass
             const int e_lo = r0 * n1, e_hi = r1 * n1;
             // paired stores need a 2-element-aligned address (e0 has the parity of e_lo)
-            const bool vec_ok = (((uintptr_t)(Jp + e_lo)) & (2 * sizeof(Acc) - 1)) == 0;
+            const bool vec_ok = (((uintptr_t)(Jp + e_lo)) & (2 * sizeof(Out) - 1)) == 0;
             for (int e0 = e_lo + 2 * lane; e0 < e_hi; e0 += 2 * WAVE) {
-                Acc v[2];
+                Out v[2];
 #pragma unroll
                 for (int t = 0; t < 2; ++t) {
                     const int e = e0 + t;
@@ -548,12 +549,12 @@ __global__ __launch_bounds__(64) void k_jac(DevMech m, int64_t n, const double *
                             x = (st.rho * ((double)S[(row - r0) * sr + c - 1] + TAU[row]) - st.Wbar * Rr) * m.invW[c - 1];
                         }
                     }
-                    v[t] = (Acc)x;
+                    v[t] = (Out)x;
                 }
                 if (vec_ok && e0 + 1 < e_hi) {
-                    typedef Acc Acc2 __attribute__((ext_vector_type(2)));
-                    Acc2 vv = {v[0], v[1]};
-                    *(Acc2 *)(Jp + e0) = vv;
+                    typedef Out Out2 __attribute__((ext_vector_type(2)));
+                    Out2 vv = {v[0], v[1]};
+                    *(Out2 *)(Jp + e0) = vv;
                 } else {
                     Jp[e0] = v[0];
                     if (e0 + 1 < e_hi) Jp[e0 + 1] = v[1];
@@ -563,6 +564,201 @@ __global__ __launch_bounds__(64) void k_jac(DevMech m, int64_t n, const double *
         }
         if (wdot)
             for (int k = lane; k < ns; k += WAVE) wdot[(int64_t)k * ld + i] = Wd[1 + k];
+    }
+}
+
+// ------------------------------------------------------------------ Jacobian (register schedule)
+// One workgroup of JAC_THREADS threads (3 wavefronts) per point, persistent over a
+// strided sequence of points.  Each thread keeps its gather-schedule records
+// (<= JAC_SCHED_MAX words) in registers for the workgroup's lifetime, and the next
+// point's T, p and Y are prefetched while the current point is processed.
+// Phases, separated by workgroup barriers:
+//   A  state (wavefront 0, lane = species) from the prefetched registers; the other
+//      wavefronts clear the accumulators;
+//   B  threads = reactions: every derivative of every rate of progress into the
+//      per-point reaction data RD (layout in build_jac_schedule);
+//   C  threads run their schedule: A[(1+k) sr + c] = sum of (coef, RD[src]) records,
+//      each entry written once.  Columns: c < Ns  J_C[k][c] without the
+//      efficiency-1 part; Ns  dw_k/dT at fixed C; Ns+1  w_k; Ns+2  tau_k (the
+//      efficiency-1 part of every column); Ns+3  R_k = sum_j J_C[k][j] C_j;
+//   D  hrr row A0[c] = -sum_k h_k A[1+k][c] in FP64 (h_k times rates can exceed the
+//      FP32 range), summed over species by all three wavefronts;
+//   E  emission, each thread a fixed pair of columns over a strided set of rows:
+//        J[row][T]   = A[row][Ns] - R_row/T (- sum_k cp_k w_k on row 0)
+//        J[row][Y_j] = (rho A[row][j] + (rho tau_row - Wbar R_row)) / W_j
+// No LDS atomics: every LDS word has one writer per phase.
+template <bool MIXED>
+__global__ __launch_bounds__(JAC_THREADS) void k_jac_reg(DevMech m, int64_t n, const double *__restrict__ T,
+                                                        const double *__restrict__ p, int64_t ps,
+                                                        const double *__restrict__ Y, int64_t ld,
+                                                        void *__restrict__ Jv, double *__restrict__ wdot,
+                                                        int nsp) {
+    using Acc = typename std::conditional<MIXED, float, double>::type;
+    extern __shared__ double lds[];
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
+    constexpr int nthr = JAC_THREADS;
+    const int ns = m.ns, n1 = ns + 1, sr = m.js_sr, nc = ns + 4;
+    double *C = lds, *G = C + nsp, *H = G + nsp, *CP = H + nsp;
+    double *A0 = CP + nsp;                         // hrr row [nsp + 4]
+    double *P3 = A0 + (nsp + 4);                   // partial hrr sums [3][nsp + 4]
+    double *SC = P3 + 3 * (nsp + 4);               // point scalars [8]
+    double *RD = SC + 8;                           // [rd_size]
+    Acc *A = (Acc *)(RD + m.rd_size);              // [(ns + 1) * sr]
+    Acc *J = (Acc *)Jv;
+    const int a_entries = n1 * sr;
+    const int len = m.js_len;
+    // ---- per-workgroup constants in registers
+    unsigned sched[JAC_SCHED_MAX];
+#pragma unroll
+    for (int it = 0; it < JAC_SCHED_MAX; ++it) sched[it] = it < len ? m.jsched[it * nthr + tid] : (4u << 13);
+    // emission mapping: a pair of columns (c0, c0 + 1) and a row phase per thread
+    const int npair = (n1 + 1) / 2;
+    const int rphase = nthr / npair;                 // rows handled in parallel
+    const int pr_c0 = 2 * (tid % npair), pr_r0 = tid / npair;
+    const bool pr_on = pr_r0 < rphase;
+    const double iw0 = (pr_c0 >= 1 && pr_c0 - 1 < ns) ? m.invW[pr_c0 - 1] : 0.0;
+    const double iw1 = (pr_c0 < ns) ? m.invW[pr_c0] : 0.0;
+    // prefetch of the first point (wavefront 0; lane = species)
+    double pf_T = 0.0, pf_p = 0.0, pf_Y = 0.0;
+    if (wave == 0 && (int64_t)blockIdx.x < n) {
+        const int64_t i0 = blockIdx.x;
+        pf_T = T[i0];
+        pf_p = p[i0 * ps];
+        if (lane < ns) pf_Y = Y[(int64_t)lane * ld + i0];
+    }
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        __syncthreads();
+        // ---- A
+        if (wave == 0) {
+            PointState st;
+            st.T = pf_T; st.p = pf_p;
+            st.lnT = log(st.T);
+            st.invT = 1.0 / st.T;
+            st.lnp0RT = log(m.p0 / (m.R * st.T));
+            const bool has = lane < ns;
+            const double yv = has ? pf_Y : 0.0;
+            const double wbar = 1.0 / wave_sum(has ? yv * m.invW[lane] : 0.0);
+            const double rho = st.p * wbar / (m.R * st.T);
+            double c = 0.0;
+            if (has) {
+                c = rho * yv * m.invW[lane];
+                double cp, h, sr_;
+                nasa7(m.nasa + 16 * lane, st.T, st.lnT, st.invT, cp, h, sr_);
+                C[lane] = c; G[lane] = h - sr_; H[lane] = h; CP[lane] = cp;
+            }
+            const double ct = wave_sum(c);
+            if (lane == 0) {
+                SC[0] = st.T; SC[1] = st.lnT; SC[2] = st.invT; SC[3] = st.lnp0RT;
+                SC[4] = rho; SC[5] = wbar; SC[6] = ct; SC[7] = st.p;
+            }
+            const int64_t inext = i + gridDim.x;
+            if (inext < n) {
+                pf_T = T[inext];
+                pf_p = p[inext * ps];
+                if (has) pf_Y = Y[(int64_t)lane * ld + inext];
+            }
+        } else {
+            for (int e = tid - WAVE; e < a_entries; e += nthr - WAVE) A[e] = (Acc)0;
+        }
+        __syncthreads();
+        PointState st;
+        st.T = SC[0]; st.lnT = SC[1]; st.invT = SC[2]; st.lnp0RT = SC[3];
+        st.rho = SC[4]; st.Wbar = SC[5]; st.Ctot = SC[6]; st.p = SC[7]; st.valid = true;
+        // ---- B
+#pragma unroll 1
+        for (int q = 0; q < JAC_RXN_PER_THREAD; ++q) {
+            const int r = tid + q * nthr;
+            if (r >= m.nr) continue;
+            const int info = m.info[r];
+            const RxnInts ri = m.ri[r];
+            RxnEval o;
+            eval_reaction<MIXED, true>(m, r, st, C, G, H, info, ri, m.lnA[r], m.b[r], m.theta[r],
+                                       m.dnu_sum[r], o);
+            const int nre = info_nreac(info), npr = info_nprod(info);
+            double *dst = RD + m.dofs[r];
+            int rank = 0;
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) {
+                const bool used = s < MAX_SIDE ? s < nre : (s - MAX_SIDE) < npr;
+                if (used) dst[rank++] = o.d[s];
+            }
+            RD[m.rd_t + r] = o.t;
+            RD[m.rd_q + r] = o.q;
+            RD[m.rd_mf + r] = o.mfac;
+            RD[m.rd_sig + r] = o.sigma;
+            const int n_exc = ri.v[7] & 255;
+            for (int e = 0; e < n_exc; ++e) RD[m.rd_exc + ri.v[6] + e] = o.mfac * m.eff_m1[ri.v[6] + e];
+        }
+        __syncthreads();
+        // ---- C
+        {
+            double acc = 0.0;
+#pragma unroll
+            for (int it = 0; it < JAC_SCHED_MAX; ++it) {
+                if (it < len) {                   // uniform: skips the padding beyond the schedule
+                    unsigned d = sched[it];
+                    asm volatile("" : "+v"(d));   // decode here, not hoisted out of the point loop
+                    acc = fma((double)((int)((d >> 13) & 7u) - 4), RD[d & 0x1fffu], acc);
+                    if (d & (1u << 16)) {
+                        A[d >> 17] = (Acc)acc;
+                        acc = 0.0;
+                    }
+                }
+                if ((it & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        __syncthreads();
+        // ---- D: hrr row, species split over the three wavefronts (lane = column)
+        const double RT = m.R * st.T;
+        for (int c = lane; c < nc; c += WAVE) {
+            double s0 = 0.0;
+            for (int k = wave; k < ns; k += 3) s0 -= H[k] * (double)A[(1 + k) * sr + c];
+            P3[wave * (nsp + 4) + c] = RT * s0;
+        }
+        __syncthreads();
+        for (int c = tid; c < nc; c += nthr) A0[c] = P3[c] + P3[(nsp + 4) + c] + P3[2 * (nsp + 4) + c];
+        if (wave == 2) {
+            double cw = 0.0;
+            for (int k = lane; k < ns; k += WAVE) cw += CP[k] * (double)A[(1 + k) * sr + ns + 1];
+            cw = wave_sum(cw) * m.R;
+            if (lane == 0) SC[0] = cw;     // T is no longer read from SC for this point
+        }
+        __syncthreads();
+        const double cw = SC[0];
+        // ---- E: emission
+        Acc *Jp = J + (size_t)i * n1 * n1;
+        if (pr_on) {
+            for (int row = pr_r0; row < n1; row += rphase) {
+                double a0, a1, jtc, tau, R;
+                if (row == 0) {
+                    a0 = pr_c0 >= 1 ? A0[pr_c0 - 1] : 0.0;
+                    a1 = pr_c0 < ns ? A0[pr_c0] : 0.0;
+                    jtc = A0[ns] - cw; tau = A0[ns + 2]; R = A0[ns + 3];
+                } else {
+                    const Acc *Ar = A + row * sr;
+                    a0 = pr_c0 >= 1 ? (double)Ar[pr_c0 - 1] : 0.0;
+                    a1 = pr_c0 < ns ? (double)Ar[pr_c0] : 0.0;
+                    jtc = (double)Ar[ns]; tau = (double)Ar[ns + 2]; R = (double)Ar[ns + 3];
+                }
+                const double alpha = st.rho * tau - st.Wbar * R;
+                const Acc v0 = (Acc)(pr_c0 == 0 ? jtc - R * st.invT : (st.rho * a0 + alpha) * iw0);
+                const Acc v1 = (Acc)((st.rho * a1 + alpha) * iw1);
+                Acc *dst = Jp + row * n1 + pr_c0;
+                if (pr_c0 + 1 < n1) {
+                    if ((((uintptr_t)dst) & (2 * sizeof(Acc) - 1)) == 0) {
+                        typedef Acc Acc2 __attribute__((ext_vector_type(2)));
+                        *(Acc2 *)dst = Acc2{v0, v1};
+                    } else {
+                        dst[0] = v0;
+                        dst[1] = v1;
+                    }
+                } else {
+                    dst[0] = v0;
+                }
+            }
+        }
+        if (wdot)
+            for (int k = tid; k < ns; k += nthr) wdot[(int64_t)k * ld + i] = (double)A[(1 + k) * sr + ns + 1];
     }
 }
 
@@ -723,12 +919,30 @@ hipError_t launch_vjp(const DevMech &m, int mixed, int64_t n, const double *T, c
     return hipGetLastError();
 }
 
+// LDS bytes of k_jac_reg for this mechanism (0 if it has no register schedule).
+size_t jac_gather_lds(const DevMech &m, int mixed) {
+    if (m.js_len <= 0) return 0;
+    const int nsp = pad_odd(m.ns);
+    return (size_t)(4 * nsp + 4 * (nsp + 4) + 8 + m.rd_size) * sizeof(double) +
+           (size_t)(m.ns + 1) * m.js_sr * (mixed ? sizeof(float) : sizeof(double));
+}
+
 hipError_t launch_jac(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
                       const double *Y, int64_t ld, void *J, double *wdot, hipStream_t st) {
+    const size_t gl = jac_gather_lds(m, mixed);
+    if (gl > 0 && gl <= 64 * 1024) {
+        const int nsp = pad_odd(m.ns);
+        const dim3 grid(grid_for(n, 1, 8)), block(JAC_THREADS);
+        if (mixed)
+            hipLaunchKernelGGL((k_jac_reg<true>), grid, block, gl, st, m, n, T, p, ps, Y, ld, J, wdot, nsp);
+        else
+            hipLaunchKernelGGL((k_jac_reg<false>), grid, block, gl, st, m, n, T, p, ps, Y, ld, J, wdot, nsp);
+        return hipGetLastError();
+    }
     const int nsp = pad_odd(m.ns);
     const int n1 = m.ns + 1;
     const int sr = pad_odd(n1);
-    const size_t acc = mixed ? sizeof(float) : sizeof(double);
+    const size_t acc = sizeof(double);
     const size_t fixed = (size_t)(4 * nsp + 4 * (nsp + 1)) * sizeof(double);
     // rows per block: the whole matrix when it fits in ~48 KB, else as many rows as fit
     const size_t budget = 48 * 1024;

@@ -238,6 +238,100 @@ crf_status parse_mechanism(const char *path, HostMech &h) {
     return CRF_OK;
 }
 
+// ---------------------------------------------------------------------------- Jacobian schedule
+// The register-schedule Jacobian kernel first stores, per point, every reaction's
+// derivative data in LDS ("reaction data", RD):
+//   RD[dofs[i] + r]   dq_i/dC of the r-th used slot of reaction i (mass-action part)
+//   RD[rd_exc + x]    dq_i/d[M] (eps_x - 1) for efficiency exception x of reaction i
+//   RD[rd_t + i]      dq_i/dT at fixed concentrations
+//   RD[rd_q + i]      q_i
+//   RD[rd_mf + i]     dq_i/d[M]
+//   RD[rd_sig + i]    sum_j C_j dq_i/dC_j
+// and then assembles the accumulator matrix A[(1 + k) * sr + c] (species rows) as
+// plain sums over these values:
+//   c < Ns   : sum_i dnu_ki (dq_i/dC_c mass-action + exception terms)
+//   c = Ns   : sum_i dnu_ki dq_i/dT        c = Ns + 1 : sum_i dnu_ki q_i (= w_k)
+//   c = Ns+2 : sum_i dnu_ki dq_i/d[M]     (the efficiency-1 part of every column)
+//   c = Ns+3 : sum_i dnu_ki sum_j C_j dq_i/dC_j  (= sum_j J_C[k][j] C_j)
+// Every entry is computed by exactly one thread (no atomics): contributions are
+// grouped by target entry and the entries are dealt to `threads` threads, longest
+// first, onto the least-loaded thread; each thread's stream is padded to the common
+// length with no-op records.  A record is one 32-bit word, kept in registers:
+//   bits 0-12 src, bits 13-15 coef + 4 (coef = dnu_ki in -3..3), bit 16 closes an
+//   entry, bits 17-31 target.
+// When the mechanism does not fit these fields or the length limit, js_len = 0 and
+// the Jacobian falls back to the row-block kernel.
+void build_jac_schedule(HostMech &h, int threads) {
+    const int ns = h.ns(), nr = h.nr();
+    h.dofs.assign(nr, 0);
+    int nd = 0;
+    for (int i = 0; i < nr; ++i) {
+        h.dofs[i] = nd;
+        nd += info_nreac(h.info[i]) + info_nprod(h.info[i]);
+    }
+    h.rd_exc = nd;
+    h.rd_t = nd + (int)h.eff_sp.size();
+    h.rd_q = h.rd_t + nr;
+    h.rd_mf = h.rd_q + nr;
+    h.rd_sig = h.rd_mf + nr;
+    h.rd_size = h.rd_sig + nr;
+    h.js_sr = (ns + 4) | 1;
+    h.js_len = 0;
+    h.jsched.clear();
+    if (h.rd_size > (1 << 13) || (ns + 1) * h.js_sr > (1 << 15) || ns > JAC_MAX_SPECIES ||
+        nr > JAC_RXN_PER_THREAD * threads)
+        return;
+    std::map<int, std::vector<std::pair<int, int>>> by_target;   // target -> (src, coef)
+    for (int i = 0; i < nr; ++i) {
+        const int info = h.info[i];
+        const int nre = info_nreac(info), npr = info_nprod(info);
+        const RxnInts &r = h.ri[i];
+        int used[SLOTS], nused = 0;
+        for (int s = 0; s < SLOTS; ++s)
+            if (s < MAX_SIDE ? s < nre : (s - MAX_SIDE) < npr) used[nused++] = s;
+        for (int ua = 0; ua < nused; ++ua) {
+            const int a = used[ua];
+            const int k = r.v[a];
+            const int dn = (a < MAX_SIDE ? -1 : 1) * info_nu(info, a);
+            const int row = (1 + k) * h.js_sr;
+            by_target[row + ns].push_back({h.rd_t + i, dn});
+            by_target[row + ns + 1].push_back({h.rd_q + i, dn});
+            if (info_kind(info) != RXN_ELEMENTARY) by_target[row + ns + 2].push_back({h.rd_mf + i, dn});
+            by_target[row + ns + 3].push_back({h.rd_sig + i, dn});
+            for (int ub = 0; ub < nused; ++ub) by_target[row + r.v[used[ub]]].push_back({h.dofs[i] + ub, dn});
+            const int n_exc = r.v[7] & 255;
+            for (int e = 0; e < n_exc; ++e)
+                by_target[row + h.eff_sp[r.v[6] + e]].push_back({h.rd_exc + r.v[6] + e, dn});
+        }
+    }
+    // longest-processing-time assignment of entries to threads
+    std::vector<std::pair<int, int>> order;   // (count, target)
+    for (auto &kv : by_target) order.push_back({(int)kv.second.size(), kv.first});
+    std::sort(order.begin(), order.end(),
+              [](auto &x, auto &y) { return x.first > y.first || (x.first == y.first && x.second < y.second); });
+    std::vector<std::vector<unsigned>> stream(threads);
+    std::vector<int> load(threads, 0);
+    for (auto &ct : order) {
+        int t = 0;
+        for (int u = 1; u < threads; ++u)
+            if (load[u] < load[t]) t = u;
+        const auto &lst = by_target[ct.second];
+        for (size_t c = 0; c < lst.size(); ++c) {
+            const bool last = c + 1 == lst.size();
+            stream[t].push_back((unsigned)lst[c].first | ((unsigned)(lst[c].second + 4) << 13) |
+                                (last ? (1u << 16) | ((unsigned)ct.second << 17) : 0u));
+        }
+        load[t] += (int)lst.size();
+    }
+    int len = 0;
+    for (int t = 0; t < threads; ++t) len = std::max(len, load[t]);
+    if (len > JAC_SCHED_MAX) return;
+    h.js_len = len;
+    h.jsched.assign((size_t)len * threads, 4u << 13);      // padding: src 0, coef 0
+    for (int t = 0; t < threads; ++t)
+        for (int it = 0; it < load[t]; ++it) h.jsched[(size_t)it * threads + t] = stream[t][it];
+}
+
 // ---------------------------------------------------------------------------- upload
 namespace {
 
@@ -255,6 +349,7 @@ struct Packer {
 }  // namespace
 
 crf_status upload_mechanism(crf_mech *mm, int device) {
+    build_jac_schedule(mm->host, JAC_THREADS);
     const HostMech &h = mm->host;
     const int ns = h.ns(), nr = h.nr();
     // derived species tables
@@ -279,7 +374,7 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
            oLam = P.add(h.lam_fit), oW4 = P.add(w4), oIw4 = P.add(iw4), oWc = P.add(wc), oDif = P.add(dif),
            oPjk = P.add(pjk), oLnA = P.add(h.lnA), oB = P.add(h.b), oTh = P.add(h.theta), oInfo = P.add(h.info),
            oDs = P.add(h.dnu_sum), oRi = P.add(h.ri), oTroe = P.add(h.troe), oEs = P.add(h.eff_sp),
-           oEm = P.add(h.eff_m1);
+           oEm = P.add(h.eff_m1), oDofs = P.add(h.dofs), oJs = P.add(h.jsched);
     int prev = -1;
     if (hipGetDevice(&prev) != hipSuccess) return fail(CRF_E_DEVICE, "hipGetDevice failed (no HIP device?)");
     if (hipSetDevice(device) != hipSuccess) return fail(CRF_E_DEVICE, "hipSetDevice(" + std::to_string(device) + ") failed");
@@ -301,6 +396,9 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
     m.theta = (const double *)at(oTh); m.info = (const int *)at(oInfo); m.dnu_sum = (const int *)at(oDs);
     m.ri = (const RxnInts *)at(oRi); m.troe = (const double *)at(oTroe); m.eff_sp = (const int *)at(oEs);
     m.eff_m1 = (const double *)at(oEm);
+    m.dofs = (const int *)at(oDofs); m.jsched = (const unsigned *)at(oJs);
+    m.js_len = h.js_len; m.js_threads = JAC_THREADS; m.rd_size = h.rd_size; m.rd_exc = h.rd_exc;
+    m.rd_t = h.rd_t; m.rd_q = h.rd_q; m.rd_mf = h.rd_mf; m.rd_sig = h.rd_sig; m.js_sr = h.js_sr;
     mm->dev_buf = d;
     mm->device = device;
     return CRF_OK;

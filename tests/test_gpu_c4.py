@@ -11,7 +11,8 @@ torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
 import synth  # noqa: E402
-from metrics import e_norm, e_turn, jac_scaled_error, significant_species  # noqa: E402
+from metrics import (e_norm, e_turn, fp32_range_split, jac_scaled_error, significant_species,  # noqa: E402
+                     vjp_scaled_error)
 
 pytestmark = pytest.mark.gpu
 R = 8314.46261815324
@@ -67,14 +68,20 @@ def test_c4_jacobian_row_blocks(c4, prec, tol, npts):
     T, p, Y = _dev(s)
     J, w = crf.wdot_jac(g, T, p, Y, prec)
     torch.cuda.synchronize()
-    Jr = oracle.jacobian(om, s["T"], s["p"], s["Y"].T)
+    Jr, G = oracle.jacobian(om, s["T"], s["p"], s["Y"].T, return_gross=True)
     out = oracle.production_rates(om, s["T"], s["p"], s["Y"].T)
-    _, hRT, _, _ = oracle.nasa7(om, s["T"])
-    err = jac_scaled_error(J.double().cpu().numpy(), Jr, s["T"], s["Y"].T, out["turnover"], out["wdot"],
-                           R * s["T"][:, None] * hRT, out["hrr"])
+    Jg = J.double().cpu().numpy()
+    if prec == "mixed":
+        Jg, Jr = fp32_range_split(Jg, Jr)      # the hrr row exceeds the FP32 range at 40 atm
+    err = jac_scaled_error(Jg, Jr, G, s["T"], s["Y"].T, floor=1e-10 if prec == "mixed" else 0.0)
     print(f"c4 jac {prec}: {err.max():.2e}", flush=True)
     assert err.max() <= tol
-    assert e_turn(w.cpu().numpy(), out["wdot"], out["turnover"]).max() <= (1e-12 if prec == "fp64" else 1e-5)
+    w = w.cpu().numpy()
+    if prec == "fp64":
+        assert e_turn(w, out["wdot"], out["turnover"]).max() <= 1e-12
+    else:
+        sig = significant_species(out["wdot"], om.W)
+        assert e_norm(w, out["wdot"])[sig].max() <= 1e-5
 
 
 def test_c4_vjp(c4):
@@ -87,12 +94,11 @@ def test_c4_vjp(c4):
     u = rng.standard_normal((200, len(idx)))
     gT, gY = crf.wdot_vjp(g, T, p, Y, torch.from_numpy(u).cuda().t())
     torch.cuda.synchronize()
-    Jr = oracle.jacobian(om, s["T"], s["p"], s["Y"].T)
+    Jr, G = oracle.jacobian(om, s["T"], s["p"], s["Y"].T, return_gross=True)
     uu = np.concatenate([np.zeros((len(idx), 1)), u.T], axis=1)
     gref = np.einsum("nr,nrc->nc", uu, Jr)
-    scale = np.einsum("nr,nrc->nc", np.abs(uu), np.abs(Jr)) + 1e-300
     got = np.concatenate([gT.cpu().numpy()[:, None], gY.cpu().numpy()], axis=1)
-    assert np.max(np.abs(got - gref) / scale) <= 1e-11
+    assert vjp_scaled_error(got, gref, uu, G) <= 1e-12
 
 
 def test_c4_transport(c4):

@@ -25,10 +25,8 @@ def _states(m, n, seed, with_anchors=False):
 
 
 def _scaled(J1, J2, m, T, p, Y):
-    out = oracle.production_rates(m, T, p, Y)
-    _, hRT, _, _ = oracle.nasa7(m, T)
-    h = R * T[:, None] * hRT
-    return jac_scaled_error(J1, J2, T, Y, out["turnover"], out["wdot"], h, out["hrr"])
+    _, G = oracle.jacobian(m, T, p, Y, return_gross=True)
+    return jac_scaled_error(J1, J2, G, T, Y)
 
 
 @pytest.mark.parametrize("which", ["c0", "c1"])
@@ -46,6 +44,13 @@ def test_central_differences_agree(c0_path):
     J = oracle.jacobian(m, T, p, Y)
     Jf = oracle.central_fd_jacobian(m, T, p, Y)
     assert _scaled(Jf, J, m, T, p, Y).max() <= 1e-6
+
+
+def test_gross_jacobian_bounds_the_jacobian(c1_path):
+    m = oracle.read_mechanism(c1_path)
+    T, p, Y = _states(m, 6, 14, with_anchors=True)
+    J, G = oracle.jacobian(m, T, p, Y, return_gross=True)
+    assert np.all(np.abs(J) <= G * (1 + 1e-12) + 1e-300)
 
 
 def test_vjp_dot_product_identity(c1_path):
