@@ -87,6 +87,13 @@ int crf_n_species(const crf_mech *m);     /* -1 for NULL */
 int crf_n_reactions(const crf_mech *m);   /* -1 for NULL */
 int crf_device(const crf_mech *m);        /* device the tables live on, -1 for host-only or NULL */
 
+/* Which kernel crf_wdot_jac runs for this mechanism: "segmented" (one workgroup per
+ * point, one reaction per thread, lockstep gather of the derivative sums; needs at
+ * most 384 reactions, 64 species, 3 molecules per side and 64 KB of LDS) or
+ * "row-block (<reason>)" for the general kernel.  Informational; the string is owned
+ * by the mechanism and valid until the next call on it or crf_free_mech. "" for NULL. */
+const char *crf_jac_plan(const crf_mech *m);
+
 /* Message describing the last non-OK status returned on this thread ("" if none). */
 const char *crf_last_error(void);
 const char *crf_status_str(crf_status s);

@@ -5,7 +5,7 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcrf.so")
 
 EXPORTED = (
-    "crf_load_mech", "crf_free_mech", "crf_n_species", "crf_n_reactions", "crf_device",
+    "crf_load_mech", "crf_free_mech", "crf_n_species", "crf_n_reactions", "crf_device", "crf_jac_plan",
     "crf_last_error", "crf_status_str", "crf_thermo", "crf_wdot", "crf_transport",
     "crf_wdot_vjp", "crf_wdot_jac",
 )
@@ -44,6 +44,8 @@ def lib():
     for f in ("crf_n_species", "crf_n_reactions", "crf_device"):
         getattr(L, f).argtypes = [P]
         getattr(L, f).restype = I
+    L.crf_jac_plan.argtypes = [P]
+    L.crf_jac_plan.restype = ctypes.c_char_p
     L.crf_last_error.argtypes = []
     L.crf_last_error.restype = ctypes.c_char_p
     L.crf_status_str.argtypes = [I]

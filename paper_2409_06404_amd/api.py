@@ -58,6 +58,11 @@ class Mechanism:
         return _lib.lib().crf_n_reactions(self.handle)
 
     @property
+    def jac_plan(self):
+        """Which Jacobian kernel crf_wdot_jac runs: 'segmented' or 'row-block (<reason>)'."""
+        return _lib.lib().crf_jac_plan(self.handle).decode()
+
+    @property
     def device(self):
         return _lib.lib().crf_device(self.handle)
 

@@ -56,21 +56,35 @@ struct DevMech {
     const double *troe;       // [n_troe][8]: lnA0, b0, theta0, alpha, 1/T3, 1/T1, T2, 0
     const int *eff_sp;        // [n_exc]
     const double *eff_m1;     // [n_exc] eps - 1
-    // Jacobian gather schedule (see build_jac_schedule in mech.cpp); js_len == 0 if absent
-    const int *dofs;          // [nr] first per-point derivative slot of reaction i
-    const unsigned *jsched;   // [js_len][js_threads] packed records (build_jac_schedule)
-    int js_len, js_threads;
-    int rd_size, rd_exc, rd_t, rd_q, rd_mf, rd_sig;   // per-point reaction-data layout
-    int js_sr;                // row stride of the accumulator matrix (>= ns + 4)
+    // Segmented Jacobian plan (build_jac_plan in mech.cpp); jp_ok == 0 if the mechanism does not fit it
+    const int *jp_thr;        // [JS_THREADS] per-thread reaction constants (JsThr)
+    const unsigned *jp_recs;  // gather rounds (quad rounds: 2 x uint4 per lane, d rounds: uint2 per lane)
+    const int *jp_prog;       // [JS_WAVES][4]: quad rounds, d rounds, quad offset, d offset (in 32-bit words)
+    int jp_ok, jp_nd, jp_sr, jp_lds;
+    int jp_off_rdq, jp_off_a, jp_off_sp, jp_off_row, jp_off_p, jp_off_sc;   // LDS byte offsets
 };
 
-// Register-schedule Jacobian kernel: threads per workgroup (3 wavefronts), most
-// schedule records per thread, reactions per thread, species (one per lane of the
-// state wavefront).
-constexpr int JAC_THREADS = 192;
-constexpr int JAC_SCHED_MAX = 64;
-constexpr int JAC_RXN_PER_THREAD = 2;
-constexpr int JAC_MAX_SPECIES = 64;
+// Segmented Jacobian kernel (k_jac_seg): six wavefronts per workgroup, one reaction per
+// thread, gather rounds of JS_LQ "quad" records (4 accumulators: dq/dT, q, dq/d[M],
+// sum_j C_j dq/dC_j) or JS_LD single-value records per lane.
+constexpr int JS_WAVES = 6;
+constexpr int JS_THREADS = 64 * JS_WAVES;
+constexpr int JS_LQ = 15;
+constexpr int JS_LD = 3;
+constexpr int JS_PWAVES = 3;        // wavefronts that form the heat-release row
+constexpr int JS_MAX_LDS = 64 * 1024;
+
+// Per-thread constants of k_jac_seg (8 ints, two 16-byte loads).
+struct alignas(16) JsThr {
+    int r;        // reaction, -1 if the thread is idle
+    int sp03;     // species of molecule slots 0..3, 8 bits each (ns = the unit dummy species)
+    int sp45;     // slots 4, 5 (bits 0-15) | reactant molecules << 16 | product molecules << 19 | kind << 22
+    int dpos;     // first derivative value of the reaction (index into the d values)
+    int xpos;     // first efficiency-exception value (bits 0-15) | exception count << 16
+    int exc0;     // first exception in eff_sp / eff_m1
+    int troe;     // Troe parameter row, -1 if none
+    int dnu;      // sum_k (nu''_k - nu'_k)
+};
 
 // Host copy of a parsed mechanism.
 struct HostMech {
@@ -90,10 +104,13 @@ struct HostMech {
     std::vector<double> troe;            // [n_troe][8]
     std::vector<int> eff_sp;
     std::vector<double> eff_m1;
-    // Jacobian gather schedule
-    std::vector<int> dofs;
-    std::vector<unsigned> jsched;
-    int js_len = 0, rd_size = 0, rd_exc = 0, rd_t = 0, rd_q = 0, rd_mf = 0, rd_sig = 0, js_sr = 0;
+    // segmented Jacobian plan
+    std::vector<JsThr> jp_thr;
+    std::vector<unsigned> jp_recs;
+    std::vector<int> jp_prog;
+    int jp_ok = 0, jp_nd = 0, jp_sr = 0, jp_lds = 0;
+    int jp_off_rdq = 0, jp_off_a = 0, jp_off_sp = 0, jp_off_row = 0, jp_off_p = 0, jp_off_sc = 0;
+    std::string jp_why;                  // why the plan is absent (for diagnostics)
     int ns() const { return (int)names.size(); }
     int nr() const { return (int)lnA.size(); }
 };
@@ -105,6 +122,7 @@ struct crf_mech {
     crf::DevMech dev{};
     int device = -1;
     void *dev_buf = nullptr;
+    mutable std::string plan_text;   // storage for crf_jac_plan
 };
 
 namespace crf {
@@ -115,7 +133,7 @@ void clear_error();
 
 // Parsing / validation / upload (mech.cpp).
 crf_status parse_mechanism(const char *path, HostMech &out);
-void build_jac_schedule(HostMech &h, int threads);
+void build_jac_plan(HostMech &h);
 crf_status upload_mechanism(crf_mech *m, int device);
 
 // Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.

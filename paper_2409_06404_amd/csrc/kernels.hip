@@ -56,7 +56,30 @@ __device__ inline double ipow_m1(double x, int n) {   // n * x^(n-1), n in 1..3
 }
 
 template <class R> __device__ inline R exp_r(R x);
-template <> __device__ inline double exp_r<double>(double x) { return exp(x); }
+// e^x in FP64: Cody-Waite reduction x = k ln2 + f (ln2 split in a 32-bit head and a
+// tail, so k ln2_hi is exact for |k| < 2^21), |f| <= ln2/2, then a degree-11
+// polynomial interpolating e^f at the Chebyshev nodes of that interval (fitted in
+// extended precision; about 2 ulp over the interval), scaled by 2^k.  Underflows to 0
+// and overflows to +inf like e^x; NaN propagates.
+__device__ inline double exp_fast(double x) {
+    const double k = rint(x * 1.4426950408889634074);
+    double f = fma(-k, 6.93147180369123816490e-01, x);
+    f = fma(-k, 1.90821492927058770002e-10, f);
+    double q = 2.51107961235593001e-08;
+    q = fma(q, f, 2.76326740329670590e-07);
+    q = fma(q, f, 2.75572379539371718e-06);
+    q = fma(q, f, 2.48014853795884660e-05);
+    q = fma(q, f, 1.98412698943924382e-04);
+    q = fma(q, f, 1.38888889524247327e-03);
+    q = fma(q, f, 8.33333333331670763e-03);
+    q = fma(q, f, 4.16666666664875993e-02);
+    q = fma(q, f, 1.66666666666666879e-01);
+    q = fma(q, f, 5.00000000000001887e-01);
+    q = fma(q, f, 1.0);
+    q = fma(q, f, 1.0);
+    return ldexp(q, (int)fmax(fmin(k, 2100.0), -2100.0));
+}
+template <> __device__ inline double exp_r<double>(double x) { return exp_fast(x); }
 template <> __device__ inline float exp_r<float>(float x) { return __expf(x); }
 template <class R> __device__ inline R log_r(R x);
 template <> __device__ inline double log_r<double>(double x) { return log(x); }
@@ -567,184 +590,335 @@ __global__ __launch_bounds__(64) void k_jac(DevMech m, int64_t n, const double *
     }
 }
 
-// ------------------------------------------------------------------ Jacobian (register schedule)
-// One workgroup of JAC_THREADS threads (3 wavefronts) per point, persistent over a
-// strided sequence of points.  Each thread keeps its gather-schedule records
-// (<= JAC_SCHED_MAX words) in registers for the workgroup's lifetime, and the next
-// point's T, p and Y are prefetched while the current point is processed.
-// Phases, separated by workgroup barriers:
-//   A  state (wavefront 0, lane = species) from the prefetched registers; the other
-//      wavefronts clear the accumulators;
-//   B  threads = reactions: every derivative of every rate of progress into the
-//      per-point reaction data RD (layout in build_jac_schedule);
-//   C  threads run their schedule: A[(1+k) sr + c] = sum of (coef, RD[src]) records,
-//      each entry written once.  Columns: c < Ns  J_C[k][c] without the
-//      efficiency-1 part; Ns  dw_k/dT at fixed C; Ns+1  w_k; Ns+2  tau_k (the
-//      efficiency-1 part of every column); Ns+3  R_k = sum_j J_C[k][j] C_j;
-//   D  hrr row A0[c] = -sum_k h_k A[1+k][c] in FP64 (h_k times rates can exceed the
-//      FP32 range), summed over species by all three wavefronts;
+// ------------------------------------------------------------------ Jacobian (segmented gather)
+// One workgroup of JS_THREADS threads (6 wavefronts) per point, persistent over a
+// strided sequence of points; thread t owns one reaction for the workgroup's lifetime
+// (its constants stay in registers).  Phases, separated by workgroup barriers:
+//   A  state: wavefront 0 (lane = species) forms C_k, Wbar, rho and [M] from the
+//      prefetched T, p, Y of this point and prefetches the next point; wavefront 1
+//      evaluates the NASA-7 polynomials (g/RT, h/RT, cp/R) and the T-functions;
+//   B  threads = reactions: rate of progress and all its derivatives into the
+//      per-point reaction data (d values and quads, layout in build_jac_plan);
+//   C  lockstep gather rounds (build_jac_plan) into the accumulator matrix
+//      A[k][0..3] = (dw_k/dT at fixed C, w_k, tau_k, R_k), A[k][5 + j] = the mass-action
+//      and efficiency-exception part of dw_k/dC_j; entries that no reaction reaches stay
+//      zero from the workgroup's start;
+//   D  hrr row partial sums -RT sum_k h_k A[k][c] in FP64 (JS_PWAVES wavefronts split the
+//      species), the row scalars alpha_k = rho tau_k - Wbar R_k and J_T of each row,
+//      sum_k cp_k w_k, and w_k to global memory;
 //   E  emission, each thread a fixed pair of columns over a strided set of rows:
-//        J[row][T]   = A[row][Ns] - R_row/T (- sum_k cp_k w_k on row 0)
-//        J[row][Y_j] = (rho A[row][j] + (rho tau_row - Wbar R_row)) / W_j
-// No LDS atomics: every LDS word has one writer per phase.
+//        J[row][T]   = A[row][0] - R_row/T (- sum_k cp_k w_k on row 0)
+//        J[row][Y_j] = (rho A[row][5 + j] + alpha_row) / W_j
+// No LDS atomics: every LDS word has one writer per phase, and every sum is taken in
+// an order fixed by the plan, so results are bitwise reproducible.
 template <bool MIXED>
-__global__ __launch_bounds__(JAC_THREADS) void k_jac_reg(DevMech m, int64_t n, const double *__restrict__ T,
-                                                        const double *__restrict__ p, int64_t ps,
-                                                        const double *__restrict__ Y, int64_t ld,
-                                                        void *__restrict__ Jv, double *__restrict__ wdot,
-                                                        int nsp) {
-    using Acc = typename std::conditional<MIXED, float, double>::type;
-    extern __shared__ double lds[];
-    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
-    constexpr int nthr = JAC_THREADS;
-    const int ns = m.ns, n1 = ns + 1, sr = m.js_sr, nc = ns + 4;
-    double *C = lds, *G = C + nsp, *H = G + nsp, *CP = H + nsp;
-    double *A0 = CP + nsp;                         // hrr row [nsp + 4]
-    double *P3 = A0 + (nsp + 4);                   // partial hrr sums [3][nsp + 4]
-    double *SC = P3 + 3 * (nsp + 4);               // point scalars [8]
-    double *RD = SC + 8;                           // [rd_size]
-    Acc *A = (Acc *)(RD + m.rd_size);              // [(ns + 1) * sr]
-    Acc *J = (Acc *)Jv;
-    const int a_entries = n1 * sr;
-    const int len = m.js_len;
-    // ---- per-workgroup constants in registers
-    unsigned sched[JAC_SCHED_MAX];
+__device__ inline void jac_seg_reaction(const DevMech &m, int r, unsigned sp03, unsigned sp45, int dpos, int xpos,
+                                        int n_exc, int exc0, int troe, int dnu, double lnA, double bb, double th,
+                                        const double *SP, const double *SC, int nd, double *RDd, double *RDq) {
+    using Rt = typename std::conditional<MIXED, float, double>::type;
+    const int nfm = (sp45 >> 16) & 7, nrm = (sp45 >> 19) & 7, kind = (sp45 >> 22) & 3;
+    const double Ctot = SC[4], lnT = SC[5], invT = SC[6], lnp0RT = SC[7];
+    // third-body concentration [M] = Ctot + sum_exc (eps - 1) C_k
+    double M = 0.0;
+    if (kind != RXN_ELEMENTARY) {
+        M = Ctot;
+        for (int e = 0; e < n_exc; ++e) M += m.eff_m1[exc0 + e] * SP[4 * m.eff_sp[exc0 + e]];
+    }
+    // forward rate constant (Arrhenius; Lindemann-Troe blending for falloff reactions)
+    const Rt rlnT = (Rt)lnT, rinvT = (Rt)invT;
+    const Rt lnkinf = (Rt)lnA + (Rt)bb * rlnT - (Rt)th * rinvT;
+    const Rt kinf = exp_r<Rt>(lnkinf);
+    const Rt dlnkinf = ((Rt)bb + (Rt)th * rinvT) * rinvT;
+    Rt kf = kinf, dkf_dT = kinf * dlnkinf, dkf_dM = 0;
+    if (kind == RXN_TROE) {
+        const double *tp = m.troe + 8 * troe;
+        const Rt lnA0 = (Rt)tp[0], b0 = (Rt)tp[1], th0 = (Rt)tp[2], alpha = (Rt)tp[3];
+        const Rt iT3 = (Rt)tp[4], iT1 = (Rt)tp[5], T2 = (Rt)tp[6];
+        const Rt rT = (Rt)SC[0];
+        const Rt lnk0 = lnA0 + b0 * rlnT - th0 * rinvT;
+        const Rt lnM = log_r<Rt>((Rt)M);
+        const Rt lnPr = lnk0 - lnkinf + lnM;
+        const Rt Pr = exp_r<Rt>(lnPr);
+        const Rt e3 = exp_r<Rt>(-rT * iT3), e1 = exp_r<Rt>(-rT * iT1), e2 = exp_r<Rt>(-T2 * rinvT);
+        const Rt Fc = ((Rt)1 - alpha) * e3 + alpha * e1 + e2;
+        const Rt tiny = MIXED ? (Rt)1e-37 : (Rt)1e-300;
+        const Rt lFc = log_r<Rt>(Fc > tiny ? Fc : tiny) * (Rt)INV_LN10;
+        const Rt cc = (Rt)-0.4 - (Rt)0.67 * lFc;
+        const Rt nn = (Rt)0.75 - (Rt)1.27 * lFc;
+        const Rt lnfloor = MIXED ? (Rt)-85.19 : (Rt)-690.7755278982137;
+        const Rt ell = (lnPr > lnfloor ? lnPr : lnfloor) * (Rt)INV_LN10;
+        const Rt u = ell + cc;
+        const Rt den = nn - (Rt)0.14 * u;
+        const Rt f1 = u / den;
+        const Rt gg = (Rt)1 / ((Rt)1 + f1 * f1);
+        const Rt F = exp_r<Rt>(lFc * gg * (Rt)LN10);
+        const Rt Prp = (Rt)1 / ((Rt)1 + (Rt)1 / Pr);
+        kf = kinf * Prp * F;
+        const Rt idd = (Rt)1 / (den * den);
+        const Rt df1_dell = nn * idd;
+        const Rt df1_dlFc = ((Rt)-0.67 * den - u * ((Rt)-1.27 + (Rt)0.67 * (Rt)0.14)) * idd;
+        const Rt dlogF_dell = -lFc * (Rt)2 * f1 * df1_dell * gg * gg;
+        const Rt dlogF_dlFc = gg - lFc * (Rt)2 * f1 * df1_dlFc * gg * gg;
+        const Rt dlnk0 = (b0 + th0 * rinvT) * rinvT;
+        const Rt dlnPr = dlnk0 - dlnkinf;
+        const Rt dFc = -((Rt)1 - alpha) * iT3 * e3 - alpha * iT1 * e1 + T2 * rinvT * rinvT * e2;
+        const Rt dlFc = dFc / (Fc * (Rt)LN10);
+        const Rt dlnF = dlogF_dell * dlnPr + (Rt)LN10 * dlogF_dlFc * dlFc;
+        const Rt ip1 = (Rt)1 / ((Rt)1 + Pr);
+        dkf_dT = kf * (dlnkinf + dlnPr * ip1 + dlnF);
+        const Rt k0 = exp_r<Rt>(lnk0);
+        dkf_dM = k0 * F * ip1 * (ip1 + dlogF_dell);
+    }
+    __builtin_amdgcn_sched_barrier(0);   // the slot loads below start after the rate constant
+    double c[SLOTS], g[SLOTS], h[SLOTS];
 #pragma unroll
-    for (int it = 0; it < JAC_SCHED_MAX; ++it) sched[it] = it < len ? m.jsched[it * nthr + tid] : (4u << 13);
+    for (int s = 0; s < SLOTS; ++s) {
+        const unsigned k = s < 4 ? (sp03 >> (8 * s)) & 255u : (sp45 >> (8 * (s - 4))) & 255u;
+        const double2 cg = *(const double2 *)(SP + 4 * k);
+        c[s] = cg.x;
+        g[s] = cg.y;
+        h[s] = SP[4 * k + 2];
+    }
+    // equilibrium constant and rates of progress (FP64)
+    const double lnKc = (double)dnu * lnp0RT - ((g[3] + g[4] + g[5]) - (g[0] + g[1] + g[2]));
+    const double dlnKc = ((h[3] + h[4] + h[5]) - (h[0] + h[1] + h[2]) - (double)dnu) * invT;
+    const double invKc = MIXED ? exp_split(-lnKc) : exp_r<double>(-lnKc);
+    const double kfd = (double)kf;
+    const double fac = kind == RXN_THREEBODY ? M : 1.0;
+    const double fk = fac * kfd, fr = fk * invKc;
+    const double pf = c[0] * c[1] * c[2], pr = c[3] * c[4] * c[5];
+    const double qf = fk * pf, qr = fr * pr;
+    const double bracket = pf - invKc * pr;
+    const double t = fac * (double)dkf_dT * bracket + fr * pr * dlnKc;
+    const double mf = kind == RXN_THREEBODY ? kfd * bracket : kind == RXN_TROE ? (double)dkf_dM * bracket : 0.0;
+    const double sig = (double)nfm * qf - (double)nrm * qr + mf * M;
+    double2 *qd = (double2 *)(RDq + 4 * r);
+    qd[0] = double2{t, qf - qr};
+    qd[1] = double2{mf, sig};
+    // dq/dC of each molecule slot: the product of the other slots of its side
+    const double dv[SLOTS] = {fk * c[1] * c[2], fk * c[0] * c[2], fk * c[0] * c[1],
+                              -fr * c[4] * c[5], -fr * c[3] * c[5], -fr * c[3] * c[4]};
+    double *pos = RDd + 1 + dpos, *neg = RDd + 1 + nd + dpos;
+#pragma unroll
+    for (int s = 0; s < MAX_SIDE; ++s)
+        if (s < nfm) {
+            pos[s] = dv[s];
+            neg[s] = -dv[s];
+        }
+#pragma unroll
+    for (int s = 0; s < MAX_SIDE; ++s)
+        if (s < nrm) {
+            pos[nfm + s] = dv[MAX_SIDE + s];
+            neg[nfm + s] = -dv[MAX_SIDE + s];
+        }
+    for (int e = 0; e < n_exc; ++e) {
+        const double v = mf * m.eff_m1[exc0 + e];
+        RDd[1 + xpos + e] = v;
+        RDd[1 + nd + xpos + e] = -v;
+    }
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n, const double *__restrict__ T,
+                                                       const double *__restrict__ p, int64_t ps,
+                                                       const double *__restrict__ Y, int64_t ld,
+                                                       void *__restrict__ Jv, double *__restrict__ wdot) {
+    using Acc = typename std::conditional<MIXED, float, double>::type;
+    extern __shared__ __align__(16) unsigned char lds_b[];
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    const int ns = m.ns, n1 = ns + 1, sr = m.jp_sr, nd = m.jp_nd;
+    double *RDd = (double *)lds_b;
+    double *RDq = (double *)(lds_b + m.jp_off_rdq);
+    Acc *A = (Acc *)(lds_b + m.jp_off_a);
+    double *SP = (double *)(lds_b + m.jp_off_sp);
+    double *ROW = (double *)(lds_b + m.jp_off_row);
+    double *P = (double *)(lds_b + m.jp_off_p);
+    double *SC = (double *)(lds_b + m.jp_off_sc);
+    Acc *J = (Acc *)Jv;
+    // ---- workgroup set-up: zero accumulators, the no-op entries and the unit dummy species
+    for (int e = tid; e < ns * sr + 4; e += JS_THREADS) A[e] = (Acc)0;
+    if (tid == 0) RDd[0] = 0.0;
+    if (tid < 4) {
+        RDq[4 * m.nr + tid] = 0.0;
+        SP[4 * ns + tid] = tid == 0 ? 1.0 : 0.0;
+    }
+    // this thread's reaction
+    const int4 ta = ((const int4 *)m.jp_thr)[2 * tid], tb = ((const int4 *)m.jp_thr)[2 * tid + 1];
+    const int r = ta.x;
+    const unsigned sp03 = (unsigned)ta.y, sp45 = (unsigned)ta.z;
+    const int dpos = ta.w, xpos = tb.x & 0xffff, n_exc = (tb.x >> 16) & 0xffff, exc0 = tb.y, troe = tb.z, dnu = tb.w;
+    double lnA = 0.0, bb = 0.0, th = 0.0;
+    if (r >= 0) {
+        lnA = m.lnA[r];
+        bb = m.b[r];
+        th = m.theta[r];
+    }
+    // gather program of this wavefront (uniform)
+    const int4 prog = ((const int4 *)m.jp_prog)[wave];
+    const int nq = __builtin_amdgcn_readfirstlane(prog.x), ndr = __builtin_amdgcn_readfirstlane(prog.y);
+    const uint4 *qrec = (const uint4 *)(m.jp_recs + __builtin_amdgcn_readfirstlane(prog.z));
+    const uint2 *drec = (const uint2 *)(m.jp_recs + __builtin_amdgcn_readfirstlane(prog.w));
     // emission mapping: a pair of columns (c0, c0 + 1) and a row phase per thread
     const int npair = (n1 + 1) / 2;
-    const int rphase = nthr / npair;                 // rows handled in parallel
-    const int pr_c0 = 2 * (tid % npair), pr_r0 = tid / npair;
-    const bool pr_on = pr_r0 < rphase;
-    const double iw0 = (pr_c0 >= 1 && pr_c0 - 1 < ns) ? m.invW[pr_c0 - 1] : 0.0;
-    const double iw1 = (pr_c0 < ns) ? m.invW[pr_c0] : 0.0;
-    // prefetch of the first point (wavefront 0; lane = species)
+    const int rphase = JS_THREADS / npair;
+    const int pc0 = 2 * (tid % npair), pr0 = tid / npair;
+    const bool pon = pr0 < rphase;
+    const double iw0 = (pc0 >= 1 && pc0 - 1 < ns) ? m.invW[pc0 - 1] : 0.0;
+    const double iw1 = (pc0 < ns) ? m.invW[pc0] : 0.0;
+    // prefetch of the first point
     double pf_T = 0.0, pf_p = 0.0, pf_Y = 0.0;
-    if (wave == 0 && (int64_t)blockIdx.x < n) {
+    if (wave <= 1 && (int64_t)blockIdx.x < n) {
         const int64_t i0 = blockIdx.x;
         pf_T = T[i0];
-        pf_p = p[i0 * ps];
-        if (lane < ns) pf_Y = Y[(int64_t)lane * ld + i0];
+        if (wave == 0) {
+            pf_p = p[i0 * ps];
+            if (lane < ns) pf_Y = Y[(int64_t)lane * ld + i0];
+        }
     }
     for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
-        __syncthreads();
+        const int64_t inext = i + gridDim.x;
         // ---- A
         if (wave == 0) {
-            PointState st;
-            st.T = pf_T; st.p = pf_p;
-            st.lnT = log(st.T);
-            st.invT = 1.0 / st.T;
-            st.lnp0RT = log(m.p0 / (m.R * st.T));
             const bool has = lane < ns;
-            const double yv = has ? pf_Y : 0.0;
-            const double wbar = 1.0 / wave_sum(has ? yv * m.invW[lane] : 0.0);
-            const double rho = st.p * wbar / (m.R * st.T);
-            double c = 0.0;
-            if (has) {
-                c = rho * yv * m.invW[lane];
-                double cp, h, sr_;
-                nasa7(m.nasa + 16 * lane, st.T, st.lnT, st.invT, cp, h, sr_);
-                C[lane] = c; G[lane] = h - sr_; H[lane] = h; CP[lane] = cp;
-            }
-            const double ct = wave_sum(c);
+            double yw = 0.0;
+            if (has) yw = pf_Y * m.invW[lane];
+            const double wbar = 1.0 / wave_sum(yw);
+            const double rho = pf_p * wbar / (m.R * pf_T);
+            const double cv = rho * yw;
+            if (has) SP[4 * lane] = cv;
+            const double ct = wave_sum(cv);
             if (lane == 0) {
-                SC[0] = st.T; SC[1] = st.lnT; SC[2] = st.invT; SC[3] = st.lnp0RT;
-                SC[4] = rho; SC[5] = wbar; SC[6] = ct; SC[7] = st.p;
+                SC[1] = pf_p;
+                SC[2] = rho;
+                SC[3] = wbar;
+                SC[4] = ct;
             }
-            const int64_t inext = i + gridDim.x;
             if (inext < n) {
                 pf_T = T[inext];
                 pf_p = p[inext * ps];
                 if (has) pf_Y = Y[(int64_t)lane * ld + inext];
             }
-        } else {
-            for (int e = tid - WAVE; e < a_entries; e += nthr - WAVE) A[e] = (Acc)0;
+        } else if (wave == 1) {
+            const double Tt = pf_T, lnT = log(Tt), invT = 1.0 / Tt;
+            if (lane < ns) {
+                double cp, hh, sr_;
+                nasa7(m.nasa + 16 * lane, Tt, lnT, invT, cp, hh, sr_);
+                SP[4 * lane + 1] = hh - sr_;
+                SP[4 * lane + 2] = hh;
+                SP[4 * lane + 3] = cp;
+            }
+            if (lane == 0) {
+                SC[0] = Tt;
+                SC[5] = lnT;
+                SC[6] = invT;
+                SC[7] = log(m.p0 / (m.R * Tt));
+            }
+            if (inext < n) pf_T = T[inext];
         }
         __syncthreads();
-        PointState st;
-        st.T = SC[0]; st.lnT = SC[1]; st.invT = SC[2]; st.lnp0RT = SC[3];
-        st.rho = SC[4]; st.Wbar = SC[5]; st.Ctot = SC[6]; st.p = SC[7]; st.valid = true;
         // ---- B
-#pragma unroll 1
-        for (int q = 0; q < JAC_RXN_PER_THREAD; ++q) {
-            const int r = tid + q * nthr;
-            if (r >= m.nr) continue;
-            const int info = m.info[r];
-            const RxnInts ri = m.ri[r];
-            RxnEval o;
-            eval_reaction<MIXED, true>(m, r, st, C, G, H, info, ri, m.lnA[r], m.b[r], m.theta[r],
-                                       m.dnu_sum[r], o);
-            const int nre = info_nreac(info), npr = info_nprod(info);
-            double *dst = RD + m.dofs[r];
-            int rank = 0;
-#pragma unroll
-            for (int s = 0; s < SLOTS; ++s) {
-                const bool used = s < MAX_SIDE ? s < nre : (s - MAX_SIDE) < npr;
-                if (used) dst[rank++] = o.d[s];
-            }
-            RD[m.rd_t + r] = o.t;
-            RD[m.rd_q + r] = o.q;
-            RD[m.rd_mf + r] = o.mfac;
-            RD[m.rd_sig + r] = o.sigma;
-            const int n_exc = ri.v[7] & 255;
-            for (int e = 0; e < n_exc; ++e) RD[m.rd_exc + ri.v[6] + e] = o.mfac * m.eff_m1[ri.v[6] + e];
-        }
+        if (r >= 0)
+            jac_seg_reaction<MIXED>(m, r, sp03, sp45, dpos, xpos, n_exc, exc0, troe, dnu, lnA, bb, th, SP, SC, nd,
+                                    RDd, RDq);
+        const double Tt = SC[0], rho = SC[2], wbar = SC[3], invT = SC[6];
         __syncthreads();
         // ---- C
         {
-            double acc = 0.0;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            const unsigned char *RQ = lds_b + m.jp_off_rdq;
+            for (int rr = 0; rr < nq; ++rr) {
+                const uint4 w0 = qrec[rr * 128 + lane], w1 = qrec[rr * 128 + 64 + lane];
+                const unsigned u[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
 #pragma unroll
-            for (int it = 0; it < JAC_SCHED_MAX; ++it) {
-                if (it < len) {                   // uniform: skips the padding beyond the schedule
-                    unsigned d = sched[it];
-                    asm volatile("" : "+v"(d));   // decode here, not hoisted out of the point loop
-                    acc = fma((double)((int)((d >> 13) & 7u) - 4), RD[d & 0x1fffu], acc);
-                    if (d & (1u << 16)) {
-                        A[d >> 17] = (Acc)acc;
-                        acc = 0.0;
-                    }
+                for (int j = 1; j <= JS_LQ; ++j) {
+                    const unsigned rec = (u[j >> 1] >> (16 * (j & 1))) & 0xffffu;
+                    const double cf = (double)(int)__builtin_amdgcn_sbfe((int)rec, 0, 3);   // signed 3-bit field
+                    const double2 *v = (const double2 *)(RQ + (rec & 0xffe0u));
+                    const double2 x = v[0], y = v[1];
+                    a0 = fma(cf, x.x, a0);
+                    a1 = fma(cf, x.y, a1);
+                    a2 = fma(cf, y.x, a2);
+                    a3 = fma(cf, y.y, a3);
                 }
-                if ((it & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+                const unsigned tw = u[0] & 0xffffu;
+                if (tw & 0x8000u) {
+                    typedef Acc Acc4 __attribute__((ext_vector_type(4)));
+                    *(Acc4 *)(A + (tw & 0x7fffu)) = Acc4{(Acc)a0, (Acc)a1, (Acc)a2, (Acc)a3};
+                    a0 = a1 = a2 = a3 = 0.0;
+                }
+            }
+            double acc = 0.0;
+            uint2 wn = ndr > 0 ? drec[lane] : uint2{0u, 0u};
+            for (int rr = 0; rr < ndr; ++rr) {
+                const uint2 w = wn;
+                if (rr + 1 < ndr) wn = drec[(rr + 1) * 64 + lane];
+                acc += *(const double *)(lds_b + (w.x >> 16));
+                acc += *(const double *)(lds_b + (w.y & 0xffffu));
+                acc += *(const double *)(lds_b + (w.y >> 16));
+                const unsigned tw = w.x & 0xffffu;
+                if (tw & 0x8000u) {
+                    A[tw & 0x7fffu] = (Acc)acc;
+                    acc = 0.0;
+                }
             }
         }
         __syncthreads();
-        // ---- D: hrr row, species split over the three wavefronts (lane = column)
-        const double RT = m.R * st.T;
-        for (int c = lane; c < nc; c += WAVE) {
-            double s0 = 0.0;
-            for (int k = wave; k < ns; k += 3) s0 -= H[k] * (double)A[(1 + k) * sr + c];
-            P3[wave * (nsp + 4) + c] = RT * s0;
+        // ---- D
+        if (wave < JS_PWAVES) {
+            const double mRT = -m.R * Tt;
+            for (int cc = lane; cc < ns + 5; cc += WAVE) {
+                double s0 = 0.0;
+                for (int k = wave; k < ns; k += JS_PWAVES) s0 += SP[4 * k + 2] * (double)A[k * sr + cc];
+                P[wave * sr + cc] = mRT * s0;
+            }
+        } else if (wave == JS_PWAVES) {
+            double cwp = 0.0;
+            for (int k = lane; k < ns; k += WAVE) {
+                const Acc *Ar = A + k * sr;
+                const double tk = (double)Ar[0], wk = (double)Ar[1], tau = (double)Ar[2], Rk = (double)Ar[3];
+                ROW[2 * k] = rho * tau - wbar * Rk;
+                ROW[2 * k + 1] = tk - Rk * invT;
+                cwp += SP[4 * k + 3] * wk;
+                if (wdot) wdot[(int64_t)k * ld + i] = wk;
+            }
+            const double cw = wave_sum(cwp) * m.R;
+            if (lane == 0) SC[8] = cw;
         }
         __syncthreads();
-        for (int c = tid; c < nc; c += nthr) A0[c] = P3[c] + P3[(nsp + 4) + c] + P3[2 * (nsp + 4) + c];
-        if (wave == 2) {
-            double cw = 0.0;
-            for (int k = lane; k < ns; k += WAVE) cw += CP[k] * (double)A[(1 + k) * sr + ns + 1];
-            cw = wave_sum(cw) * m.R;
-            if (lane == 0) SC[0] = cw;     // T is no longer read from SC for this point
-        }
-        __syncthreads();
-        const double cw = SC[0];
-        // ---- E: emission
+        // ---- E
         Acc *Jp = J + (size_t)i * n1 * n1;
-        if (pr_on) {
-            for (int row = pr_r0; row < n1; row += rphase) {
-                double a0, a1, jtc, tau, R;
+        if (pon) {
+            const double cw = SC[8];
+            for (int row = pr0; row < n1; row += rphase) {
+                double a0, a1, al, jt;
                 if (row == 0) {
-                    a0 = pr_c0 >= 1 ? A0[pr_c0 - 1] : 0.0;
-                    a1 = pr_c0 < ns ? A0[pr_c0] : 0.0;
-                    jtc = A0[ns] - cw; tau = A0[ns + 2]; R = A0[ns + 3];
+                    double t0 = 0.0, tau0 = 0.0, R0 = 0.0;
+                    a0 = 0.0;
+                    a1 = 0.0;
+#pragma unroll
+                    for (int w = 0; w < JS_PWAVES; ++w) {
+                        const double *Pw = P + w * sr;
+                        t0 += Pw[0];
+                        tau0 += Pw[2];
+                        R0 += Pw[3];
+                        a0 += Pw[4 + pc0];
+                        if (pc0 + 1 < n1) a1 += Pw[5 + pc0];
+                    }
+                    al = rho * tau0 - wbar * R0;
+                    jt = t0 - cw - R0 * invT;
                 } else {
-                    const Acc *Ar = A + row * sr;
-                    a0 = pr_c0 >= 1 ? (double)Ar[pr_c0 - 1] : 0.0;
-                    a1 = pr_c0 < ns ? (double)Ar[pr_c0] : 0.0;
-                    jtc = (double)Ar[ns]; tau = (double)Ar[ns + 2]; R = (double)Ar[ns + 3];
+                    const Acc *Ar = A + (row - 1) * sr + 4 + pc0;
+                    a0 = (double)Ar[0];
+                    a1 = pc0 + 1 < n1 ? (double)Ar[1] : 0.0;
+                    const double2 rw = *(const double2 *)(ROW + 2 * (row - 1));
+                    al = rw.x;
+                    jt = rw.y;
                 }
-                const double alpha = st.rho * tau - st.Wbar * R;
-                const Acc v0 = (Acc)(pr_c0 == 0 ? jtc - R * st.invT : (st.rho * a0 + alpha) * iw0);
-                const Acc v1 = (Acc)((st.rho * a1 + alpha) * iw1);
-                Acc *dst = Jp + row * n1 + pr_c0;
-                if (pr_c0 + 1 < n1) {
+                const Acc v0 = (Acc)(pc0 == 0 ? jt : (rho * a0 + al) * iw0);
+                const Acc v1 = (Acc)((rho * a1 + al) * iw1);
+                Acc *dst = Jp + row * n1 + pc0;
+                if (pc0 + 1 < n1) {
                     if ((((uintptr_t)dst) & (2 * sizeof(Acc) - 1)) == 0) {
                         typedef Acc Acc2 __attribute__((ext_vector_type(2)));
                         *(Acc2 *)dst = Acc2{v0, v1};
@@ -757,8 +931,6 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jac_reg(DevMech m, int64_t n, c
                 }
             }
         }
-        if (wdot)
-            for (int k = tid; k < ns; k += nthr) wdot[(int64_t)k * ld + i] = (double)A[(1 + k) * sr + ns + 1];
     }
 }
 
@@ -919,24 +1091,14 @@ hipError_t launch_vjp(const DevMech &m, int mixed, int64_t n, const double *T, c
     return hipGetLastError();
 }
 
-// LDS bytes of k_jac_reg for this mechanism (0 if it has no register schedule).
-size_t jac_gather_lds(const DevMech &m, int mixed) {
-    if (m.js_len <= 0) return 0;
-    const int nsp = pad_odd(m.ns);
-    return (size_t)(4 * nsp + 4 * (nsp + 4) + 8 + m.rd_size) * sizeof(double) +
-           (size_t)(m.ns + 1) * m.js_sr * (mixed ? sizeof(float) : sizeof(double));
-}
-
 hipError_t launch_jac(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
                       const double *Y, int64_t ld, void *J, double *wdot, hipStream_t st) {
-    const size_t gl = jac_gather_lds(m, mixed);
-    if (gl > 0 && gl <= 64 * 1024) {
-        const int nsp = pad_odd(m.ns);
-        const dim3 grid(grid_for(n, 1, 8)), block(JAC_THREADS);
+    if (m.jp_ok && m.jp_lds <= JS_MAX_LDS) {
+        const dim3 grid(grid_for(n, 1, 2)), block(JS_THREADS);
         if (mixed)
-            hipLaunchKernelGGL((k_jac_reg<true>), grid, block, gl, st, m, n, T, p, ps, Y, ld, J, wdot, nsp);
+            hipLaunchKernelGGL((k_jac_seg<true>), grid, block, m.jp_lds, st, m, n, T, p, ps, Y, ld, J, wdot);
         else
-            hipLaunchKernelGGL((k_jac_reg<false>), grid, block, gl, st, m, n, T, p, ps, Y, ld, J, wdot, nsp);
+            hipLaunchKernelGGL((k_jac_seg<false>), grid, block, m.jp_lds, st, m, n, T, p, ps, Y, ld, J, wdot);
         return hipGetLastError();
     }
     const int nsp = pad_odd(m.ns);

@@ -6,6 +6,7 @@
 // of plain tables that table-driven kernels read.
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -237,99 +238,323 @@ crf_status parse_mechanism(const char *path, HostMech &h) {
     }
     return CRF_OK;
 }
+// ---------------------------------------------------------------------------- Jacobian plan
+// The segmented Jacobian kernel evaluates one reaction per thread and stores, per
+// point, the reaction's derivative data in LDS:
+//   d values  (index x < nd): dq_i/dC of molecule slot s of reaction i (mass-action
+//             part; a species with coefficient nu fills nu slots), then
+//             dq_i/d[M] (eps - 1) for every third-body efficiency exception;
+//             stored at byte 8 (1 + x) and, negated, at byte 8 (1 + nd + x); byte 0
+//             holds 0.0 (the no-op record);
+//   quad      (RDq + 32 i): dq_i/dT at fixed C, q_i, dq_i/d[M], sum_j C_j dq_i/dC_j;
+//             entry nr is zero.
+// The accumulator matrix A (species rows k, stride sr) is then plain sums of these:
+//   A[k][0..3] = sum_i dnu_ki quad_i                     ("quad" targets)
+//   A[k][5+j]  = sum_i dnu_ki (dq_i/dC_j + exception terms)  ("d" targets)
+// Each target is summed by one lane, in rounds that every lane of a wavefront runs in
+// lockstep: a quad round reads JS_LQ records per lane (32 r | dnu as a signed 3-bit
+// field), a d round JS_LD records (LDS byte offsets of the signed copy; |dnu| = 2, 3
+// repeat the record).  A target longer than one round continues in the same lane in
+// the next round of its kind; the lane's target word (bits 0-14 A index, bit 15 =
+// store and reset after this round) is the first 16-bit field of the round.  Targets
+// are packed into shelves of 64 lanes x R rounds (first fit, longest first) and the
+// shelves are dealt to the wavefronts, costliest first, onto the least-loaded one.
+namespace {
 
-// ---------------------------------------------------------------------------- Jacobian schedule
-// The register-schedule Jacobian kernel first stores, per point, every reaction's
-// derivative data in LDS ("reaction data", RD):
-//   RD[dofs[i] + r]   dq_i/dC of the r-th used slot of reaction i (mass-action part)
-//   RD[rd_exc + x]    dq_i/d[M] (eps_x - 1) for efficiency exception x of reaction i
-//   RD[rd_t + i]      dq_i/dT at fixed concentrations
-//   RD[rd_q + i]      q_i
-//   RD[rd_mf + i]     dq_i/d[M]
-//   RD[rd_sig + i]    sum_j C_j dq_i/dC_j
-// and then assembles the accumulator matrix A[(1 + k) * sr + c] (species rows) as
-// plain sums over these values:
-//   c < Ns   : sum_i dnu_ki (dq_i/dC_c mass-action + exception terms)
-//   c = Ns   : sum_i dnu_ki dq_i/dT        c = Ns + 1 : sum_i dnu_ki q_i (= w_k)
-//   c = Ns+2 : sum_i dnu_ki dq_i/d[M]     (the efficiency-1 part of every column)
-//   c = Ns+3 : sum_i dnu_ki sum_j C_j dq_i/dC_j  (= sum_j J_C[k][j] C_j)
-// Every entry is computed by exactly one thread (no atomics): contributions are
-// grouped by target entry and the entries are dealt to `threads` threads, longest
-// first, onto the least-loaded thread; each thread's stream is padded to the common
-// length with no-op records.  A record is one 32-bit word, kept in registers:
-//   bits 0-12 src, bits 13-15 coef + 4 (coef = dnu_ki in -3..3), bit 16 closes an
-//   entry, bits 17-31 target.
-// When the mechanism does not fit these fields or the length limit, js_len = 0 and
-// the Jacobian falls back to the row-block kernel.
-void build_jac_schedule(HostMech &h, int threads) {
+struct GatherTarget {
+    int aidx;
+    std::vector<unsigned> recs;
+};
+
+struct Shelf {
+    int R = 0;
+    std::vector<std::vector<int>> lane;   // targets of each lane, in order
+    std::vector<int> load;                // rounds used by each lane
+};
+
+std::vector<Shelf> pack_shelves(const std::vector<GatherTarget> &tg, int L) {
+    std::vector<int> order(tg.size());
+    for (size_t t = 0; t < tg.size(); ++t) order[t] = (int)t;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return tg[a].recs.size() > tg[b].recs.size(); });
+    std::vector<Shelf> sh;
+    for (int t : order) {
+        const int u = ((int)tg[t].recs.size() + L - 1) / L;
+        bool placed = false;
+        for (auto &s : sh) {
+            for (int l = 0; l < 64 && !placed; ++l)
+                if (s.load[l] + u <= s.R) {
+                    s.lane[l].push_back(t);
+                    s.load[l] += u;
+                    placed = true;
+                }
+            if (placed) break;
+        }
+        if (!placed) {
+            Shelf s;
+            s.R = u;
+            s.lane.assign(64, {});
+            s.load.assign(64, 0);
+            s.lane[0].push_back(t);
+            s.load[0] = u;
+            sh.push_back(std::move(s));
+        }
+    }
+    return sh;
+}
+
+// Writes the rounds of `shelves` (all of one kind, L records per round) for one
+// wavefront into `out` starting at word `base`; `words` = 32-bit words per lane and round.
+void emit_rounds(const std::vector<GatherTarget> &tg, const std::vector<const Shelf *> &shelves, int L,
+                 int words, unsigned trash_word, unsigned zero_rec, std::vector<unsigned> &out, size_t base) {
+    size_t round = 0;
+    for (const Shelf *s : shelves) {
+        for (int l = 0; l < 64; ++l) {
+            std::vector<unsigned> f;   // 16-bit fields of this lane, round after round
+            for (int t : s->lane[l]) {
+                const auto &g = tg[t];
+                const int u = ((int)g.recs.size() + L - 1) / L;
+                for (int part = 0; part < u; ++part) {
+                    f.push_back((unsigned)g.aidx | (part == u - 1 ? 0x8000u : 0u));
+                    for (int j = 0; j < L; ++j) {
+                        const size_t x = (size_t)part * L + j;
+                        f.push_back(x < g.recs.size() ? g.recs[x] : zero_rec);
+                    }
+                }
+            }
+            while ((int)(f.size() / (1 + L)) < s->R) {
+                f.push_back(trash_word);
+                for (int j = 0; j < L; ++j) f.push_back(zero_rec);
+            }
+            for (int r = 0; r < s->R; ++r)
+                for (int x = 0; x <= L; ++x) {
+                    // field x of round r: word x / 2 (low or high half); quad rounds split
+                    // their 8 words into two uint4 halves laid out [half][lane][4]
+                    const int w = x / 2;
+                    const size_t idx = words == 8 ? base + (round + r) * 512 + (w / 4) * 256 + (size_t)l * 4 + (w % 4)
+                                                  : base + (round + r) * 128 + (size_t)l * 2 + w;
+                    out[idx] |= (f[(size_t)r * (1 + L) + x] & 0xffffu) << (16 * (x & 1));
+                }
+        }
+        round += s->R;
+    }
+}
+
+}  // namespace
+
+void build_jac_plan(HostMech &h) {
+    h.jp_ok = 0;
+    h.jp_thr.clear();
+    h.jp_recs.clear();
+    h.jp_prog.clear();
     const int ns = h.ns(), nr = h.nr();
-    h.dofs.assign(nr, 0);
+    auto no = [&](const std::string &why) {
+        h.jp_ok = 0;
+        h.jp_why = why;
+        h.jp_thr.clear();
+        h.jp_recs.clear();
+        h.jp_prog.clear();
+    };
+    if (ns < 1 || nr < 1) return no("empty mechanism");
+    if (ns > 64) return no("more than 64 species (the state phase is one species per lane)");
+    if (nr > JS_THREADS) return no("more reactions than threads per workgroup");
+    // threads: non-Troe reactions first; Troe reactions from the next wavefront boundary
+    // (the falloff branch then runs on as few wavefronts as possible)
+    int n_non = 0, n_tr = 0;
+    for (int i = 0; i < nr; ++i) (info_kind(h.info[i]) == RXN_TROE ? n_tr : n_non)++;
+    int tstart = (n_non + 63) / 64 * 64;
+    if (tstart + n_tr > JS_THREADS) tstart = n_non;
+    std::vector<int> thr_of(nr);
+    {
+        int a = 0, b = tstart;
+        for (int i = 0; i < nr; ++i) thr_of[i] = info_kind(h.info[i]) == RXN_TROE ? b++ : a++;
+    }
+    // molecule slots and positions of the d values
+    std::vector<std::array<int, SLOTS>> mol(nr);
+    std::vector<int> dpos(nr), xpos(nr), nfm(nr), nrm(nr);
     int nd = 0;
     for (int i = 0; i < nr; ++i) {
-        h.dofs[i] = nd;
-        nd += info_nreac(h.info[i]) + info_nprod(h.info[i]);
-    }
-    h.rd_exc = nd;
-    h.rd_t = nd + (int)h.eff_sp.size();
-    h.rd_q = h.rd_t + nr;
-    h.rd_mf = h.rd_q + nr;
-    h.rd_sig = h.rd_mf + nr;
-    h.rd_size = h.rd_sig + nr;
-    h.js_sr = (ns + 4) | 1;
-    h.js_len = 0;
-    h.jsched.clear();
-    if (h.rd_size > (1 << 13) || (ns + 1) * h.js_sr > (1 << 15) || ns > JAC_MAX_SPECIES ||
-        nr > JAC_RXN_PER_THREAD * threads)
-        return;
-    std::map<int, std::vector<std::pair<int, int>>> by_target;   // target -> (src, coef)
-    for (int i = 0; i < nr; ++i) {
         const int info = h.info[i];
-        const int nre = info_nreac(info), npr = info_nprod(info);
-        const RxnInts &r = h.ri[i];
-        int used[SLOTS], nused = 0;
+        const RxnInts &ri = h.ri[i];
+        mol[i].fill(-1);
+        int nf = 0, np = 0;
+        for (int s = 0; s < info_nreac(info); ++s)
+            for (int c = 0; c < info_nu(info, s); ++c) {
+                if (nf == MAX_SIDE) return no("a reaction with more than 3 reactant molecules");
+                mol[i][nf++] = ri.v[s];
+            }
+        for (int s = 0; s < info_nprod(info); ++s)
+            for (int c = 0; c < info_nu(info, MAX_SIDE + s); ++c) {
+                if (np == MAX_SIDE) return no("a reaction with more than 3 product molecules");
+                mol[i][MAX_SIDE + np++] = ri.v[MAX_SIDE + s];
+            }
+        nfm[i] = nf;
+        nrm[i] = np;
+        dpos[i] = nd;
+        nd += nf + np;
+    }
+    for (int i = 0; i < nr; ++i) {
+        xpos[i] = nd;
+        nd += h.ri[i].v[7] & 255;
+    }
+    if (8 * (1 + 2 * nd) > 0xffff) return no("too many derivative values for 16-bit records");
+    const int sr = (ns + 5 + 3) / 4 * 4;
+    const int a_trash = ns * sr;
+    if (a_trash + 4 > 0x7fff) return no("accumulator matrix too large for 15-bit targets");
+    h.jp_nd = nd;
+    h.jp_sr = sr;
+    // per-thread constants
+    h.jp_thr.assign(JS_THREADS, JsThr{-1, 0, 0, 0, 0, 0, -1, 0});
+    for (int i = 0; i < nr; ++i) {
+        JsThr &c = h.jp_thr[thr_of[i]];
+        const int info = h.info[i];
+        auto sp = [&](int s) { return (unsigned)(mol[i][s] < 0 ? ns : mol[i][s]); };
+        c.r = i;
+        c.sp03 = (int)(sp(0) | sp(1) << 8 | sp(2) << 16 | sp(3) << 24);
+        c.sp45 = (int)(sp(4) | sp(5) << 8 | (unsigned)nfm[i] << 16 | (unsigned)nrm[i] << 19 |
+                       (unsigned)info_kind(info) << 22);
+        c.dpos = dpos[i];
+        c.xpos = xpos[i] | (h.ri[i].v[7] & 255) << 16;
+        c.exc0 = h.ri[i].v[6];
+        c.troe = info_kind(info) == RXN_TROE ? (h.ri[i].v[7] >> 8) : -1;
+        c.dnu = h.dnu_sum[i];
+    }
+    // gather targets
+    std::vector<std::vector<unsigned>> qrec(ns);
+    std::map<int, std::vector<unsigned>> drec;
+    for (int i = 0; i < nr; ++i) {
+        std::map<int, int> dn;
         for (int s = 0; s < SLOTS; ++s)
-            if (s < MAX_SIDE ? s < nre : (s - MAX_SIDE) < npr) used[nused++] = s;
-        for (int ua = 0; ua < nused; ++ua) {
-            const int a = used[ua];
-            const int k = r.v[a];
-            const int dn = (a < MAX_SIDE ? -1 : 1) * info_nu(info, a);
-            const int row = (1 + k) * h.js_sr;
-            by_target[row + ns].push_back({h.rd_t + i, dn});
-            by_target[row + ns + 1].push_back({h.rd_q + i, dn});
-            if (info_kind(info) != RXN_ELEMENTARY) by_target[row + ns + 2].push_back({h.rd_mf + i, dn});
-            by_target[row + ns + 3].push_back({h.rd_sig + i, dn});
-            for (int ub = 0; ub < nused; ++ub) by_target[row + r.v[used[ub]]].push_back({h.dofs[i] + ub, dn});
-            const int n_exc = r.v[7] & 255;
-            for (int e = 0; e < n_exc; ++e)
-                by_target[row + h.eff_sp[r.v[6] + e]].push_back({h.rd_exc + r.v[6] + e, dn});
+            if (mol[i][s] >= 0) dn[mol[i][s]] += s < MAX_SIDE ? -1 : 1;
+        const int n_exc = h.ri[i].v[7] & 255;
+        for (const auto &kv : dn) {
+            const int k = kv.first, v = kv.second;
+            if (v == 0) continue;
+            qrec[k].push_back(32u * (unsigned)i | ((unsigned)v & 7u));
+            const int reps = v < 0 ? -v : v;
+            const int neg = v < 0 ? nd : 0;
+            for (int s = 0; s < SLOTS; ++s) {
+                if (mol[i][s] < 0) continue;
+                const int x = dpos[i] + (s < MAX_SIDE ? s : nfm[i] + s - MAX_SIDE);
+                for (int c = 0; c < reps; ++c) drec[k * sr + 5 + mol[i][s]].push_back(8u * (unsigned)(1 + neg + x));
+            }
+            for (int e = 0; e < n_exc; ++e) {
+                const int j = h.eff_sp[h.ri[i].v[6] + e];
+                for (int c = 0; c < reps; ++c) drec[k * sr + 5 + j].push_back(8u * (unsigned)(1 + neg + xpos[i] + e));
+            }
         }
     }
-    // longest-processing-time assignment of entries to threads
-    std::vector<std::pair<int, int>> order;   // (count, target)
-    for (auto &kv : by_target) order.push_back({(int)kv.second.size(), kv.first});
-    std::sort(order.begin(), order.end(),
-              [](auto &x, auto &y) { return x.first > y.first || (x.first == y.first && x.second < y.second); });
-    std::vector<std::vector<unsigned>> stream(threads);
-    std::vector<int> load(threads, 0);
-    for (auto &ct : order) {
-        int t = 0;
-        for (int u = 1; u < threads; ++u)
-            if (load[u] < load[t]) t = u;
-        const auto &lst = by_target[ct.second];
-        for (size_t c = 0; c < lst.size(); ++c) {
-            const bool last = c + 1 == lst.size();
-            stream[t].push_back((unsigned)lst[c].first | ((unsigned)(lst[c].second + 4) << 13) |
-                                (last ? (1u << 16) | ((unsigned)ct.second << 17) : 0u));
-        }
-        load[t] += (int)lst.size();
+    std::vector<GatherTarget> tq, td;
+    for (int k = 0; k < ns; ++k)
+        if (!qrec[k].empty()) tq.push_back({k * sr, qrec[k]});
+    for (auto &kv : drec) td.push_back({kv.first, kv.second});
+    const std::vector<Shelf> sq = pack_shelves(tq, JS_LQ), sd = pack_shelves(td, JS_LD);
+    // deal shelves to wavefronts (cost ~ VALU per round of each kind)
+    constexpr int CQ = 9 * JS_LQ + 14, CD = 3 * JS_LD + 6;
+    struct Item { int cost, kind, idx; };
+    std::vector<Item> items;
+    for (size_t s = 0; s < sq.size(); ++s) items.push_back({sq[s].R * CQ, 0, (int)s});
+    for (size_t s = 0; s < sd.size(); ++s) items.push_back({sd[s].R * CD, 1, (int)s});
+    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
+    std::vector<int> wload(JS_WAVES, 0);
+    std::vector<std::vector<const Shelf *>> wq(JS_WAVES), wd(JS_WAVES);
+    for (const Item &it : items) {
+        int w = 0;
+        for (int u = 1; u < JS_WAVES; ++u)
+            if (wload[u] < wload[w]) w = u;
+        wload[w] += it.cost;
+        (it.kind == 0 ? wq[w] : wd[w]).push_back(it.kind == 0 ? &sq[it.idx] : &sd[it.idx]);
     }
-    int len = 0;
-    for (int t = 0; t < threads; ++t) len = std::max(len, load[t]);
-    if (len > JAC_SCHED_MAX) return;
-    h.js_len = len;
-    h.jsched.assign((size_t)len * threads, 4u << 13);      // padding: src 0, coef 0
-    for (int t = 0; t < threads; ++t)
-        for (int it = 0; it < load[t]; ++it) h.jsched[(size_t)it * threads + t] = stream[t][it];
+    // emit
+    h.jp_prog.assign(4 * JS_WAVES, 0);
+    size_t words = 0;
+    std::vector<size_t> qoff(JS_WAVES), doff(JS_WAVES);
+    for (int w = 0; w < JS_WAVES; ++w) {
+        int nq = 0, ndr = 0;
+        for (const Shelf *s : wq[w]) nq += s->R;
+        for (const Shelf *s : wd[w]) ndr += s->R;
+        qoff[w] = words;
+        words += (size_t)nq * 512;
+        doff[w] = words;
+        words += (size_t)ndr * 128;
+        h.jp_prog[4 * w + 0] = nq;
+        h.jp_prog[4 * w + 1] = ndr;
+        h.jp_prog[4 * w + 2] = (int)qoff[w];
+        h.jp_prog[4 * w + 3] = (int)doff[w];
+    }
+    h.jp_recs.assign(words ? words : 4, 0u);
+    for (int w = 0; w < JS_WAVES; ++w) {
+        emit_rounds(tq, wq[w], JS_LQ, 8, (unsigned)a_trash | 0x8000u, 32u * (unsigned)nr, h.jp_recs, qoff[w]);
+        emit_rounds(td, wd[w], JS_LD, 2, (unsigned)a_trash | 0x8000u, 0u, h.jp_recs, doff[w]);
+    }
+    // self-check: replay the rounds and compare every target's records with the stoichiometry
+    {
+        std::map<int, std::vector<unsigned>> got_q, got_d;
+        auto field = [&](size_t round_base, int words_pl, int l, int x) {
+            const int w = x / 2;
+            const size_t idx = words_pl == 8 ? round_base + (w / 4) * 256 + (size_t)l * 4 + (w % 4)
+                                             : round_base + (size_t)l * 2 + w;
+            return (h.jp_recs[idx] >> (16 * (x & 1))) & 0xffffu;
+        };
+        const unsigned q_lim = 32u * (unsigned)(nr + 1), d_lim = 8u * (unsigned)(1 + 2 * nd);
+        for (int w = 0; w < JS_WAVES; ++w)
+            for (int kind = 0; kind < 2; ++kind) {
+                const int L = kind == 0 ? JS_LQ : JS_LD, wpl = kind == 0 ? 8 : 2;
+                const int nrnd = h.jp_prog[4 * w + kind];
+                const size_t base = kind == 0 ? qoff[w] : doff[w];
+                for (int l = 0; l < 64; ++l) {
+                    std::vector<unsigned> cur;
+                    for (int r = 0; r < nrnd; ++r) {
+                        const size_t rb = base + (size_t)r * (wpl == 8 ? 512 : 128);
+                        const unsigned tw = field(rb, wpl, l, 0);
+                        for (int x = 1; x <= L; ++x) {
+                            const unsigned rec = field(rb, wpl, l, x);
+                            if (kind == 0 ? (rec & 0xffe0u) >= q_lim : (rec >= d_lim || (rec & 7u) != 0))
+                                return no("plan self-check: record out of range");
+                            const bool zero = kind == 0 ? (rec & 7u) == 0 : rec == 0;
+                            if (!zero) cur.push_back(rec);
+                        }
+                        if (tw & 0x8000u) {
+                            const int a = (int)(tw & 0x7fffu);
+                            if (a + (kind == 0 ? 4 : 1) > a_trash + 4) return no("plan self-check: target out of range");
+                            if (kind == 0 && (a % 4) != 0) return no("plan self-check: misaligned quad target");
+                            if (a != a_trash) {
+                                auto &dst = kind == 0 ? got_q : got_d;
+                                if (dst.count(a)) return no("plan self-check: target written twice");
+                                dst[a] = cur;
+                            } else if (!cur.empty()) {
+                                return no("plan self-check: records on the trash target");
+                            }
+                            cur.clear();
+                        }
+                    }
+                    if (!cur.empty()) return no("plan self-check: unterminated target");
+                }
+            }
+        auto same = [](std::vector<unsigned> a, std::vector<unsigned> b) {
+            std::sort(a.begin(), a.end());
+            std::sort(b.begin(), b.end());
+            return a == b;
+        };
+        if (got_q.size() != tq.size() || got_d.size() != td.size()) return no("plan self-check: target count");
+        for (const auto &g : tq)
+            if (!got_q.count(g.aidx) || !same(got_q[g.aidx], g.recs)) return no("plan self-check: quad records");
+        for (const auto &g : td)
+            if (!got_d.count(g.aidx) || !same(got_d[g.aidx], g.recs)) return no("plan self-check: d records");
+    }
+    // LDS layout (bytes; A is sized for double accumulators in both precisions)
+    auto up16 = [](int b) { return (b + 15) / 16 * 16; };
+    int off = up16(8 * (1 + 2 * nd));
+    h.jp_off_rdq = off;  off += up16(32 * (nr + 1));
+    h.jp_off_a = off;    off += up16(8 * (ns * sr + 4));
+    h.jp_off_sp = off;   off += up16(32 * (ns + 1));
+    h.jp_off_row = off;  off += up16(16 * ns);
+    h.jp_off_p = off;    off += up16(8 * JS_PWAVES * sr);
+    h.jp_off_sc = off;   off += up16(8 * 16);
+    h.jp_lds = off;
+    if (off > JS_MAX_LDS) return no("LDS footprint " + std::to_string(off) + " B above the limit");
+    h.jp_ok = 1;
+    h.jp_why.clear();
 }
 
 // ---------------------------------------------------------------------------- upload
@@ -349,7 +574,6 @@ struct Packer {
 }  // namespace
 
 crf_status upload_mechanism(crf_mech *mm, int device) {
-    build_jac_schedule(mm->host, JAC_THREADS);
     const HostMech &h = mm->host;
     const int ns = h.ns(), nr = h.nr();
     // derived species tables
@@ -374,7 +598,7 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
            oLam = P.add(h.lam_fit), oW4 = P.add(w4), oIw4 = P.add(iw4), oWc = P.add(wc), oDif = P.add(dif),
            oPjk = P.add(pjk), oLnA = P.add(h.lnA), oB = P.add(h.b), oTh = P.add(h.theta), oInfo = P.add(h.info),
            oDs = P.add(h.dnu_sum), oRi = P.add(h.ri), oTroe = P.add(h.troe), oEs = P.add(h.eff_sp),
-           oEm = P.add(h.eff_m1), oDofs = P.add(h.dofs), oJs = P.add(h.jsched);
+           oEm = P.add(h.eff_m1), oJt = P.add(h.jp_thr), oJr = P.add(h.jp_recs), oJp = P.add(h.jp_prog);
     int prev = -1;
     if (hipGetDevice(&prev) != hipSuccess) return fail(CRF_E_DEVICE, "hipGetDevice failed (no HIP device?)");
     if (hipSetDevice(device) != hipSuccess) return fail(CRF_E_DEVICE, "hipSetDevice(" + std::to_string(device) + ") failed");
@@ -396,9 +620,10 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
     m.theta = (const double *)at(oTh); m.info = (const int *)at(oInfo); m.dnu_sum = (const int *)at(oDs);
     m.ri = (const RxnInts *)at(oRi); m.troe = (const double *)at(oTroe); m.eff_sp = (const int *)at(oEs);
     m.eff_m1 = (const double *)at(oEm);
-    m.dofs = (const int *)at(oDofs); m.jsched = (const unsigned *)at(oJs);
-    m.js_len = h.js_len; m.js_threads = JAC_THREADS; m.rd_size = h.rd_size; m.rd_exc = h.rd_exc;
-    m.rd_t = h.rd_t; m.rd_q = h.rd_q; m.rd_mf = h.rd_mf; m.rd_sig = h.rd_sig; m.js_sr = h.js_sr;
+    m.jp_thr = (const int *)at(oJt); m.jp_recs = (const unsigned *)at(oJr); m.jp_prog = (const int *)at(oJp);
+    m.jp_ok = h.jp_ok; m.jp_nd = h.jp_nd; m.jp_sr = h.jp_sr; m.jp_lds = h.jp_lds;
+    m.jp_off_rdq = h.jp_off_rdq; m.jp_off_a = h.jp_off_a; m.jp_off_sp = h.jp_off_sp;
+    m.jp_off_row = h.jp_off_row; m.jp_off_p = h.jp_off_p; m.jp_off_sc = h.jp_off_sc;
     mm->dev_buf = d;
     mm->device = device;
     return CRF_OK;
