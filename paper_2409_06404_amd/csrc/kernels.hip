@@ -593,56 +593,53 @@ __global__ __launch_bounds__(64) void k_jac(DevMech m, int64_t n, const double *
 // ------------------------------------------------------------------ Jacobian (segmented gather)
 // One workgroup of JS_THREADS threads (6 wavefronts) per point, persistent over a
 // strided sequence of points; thread t owns one reaction for the workgroup's lifetime
-// (its constants stay in registers).  Phases, separated by workgroup barriers:
-//   A  state: wavefront 0 (lane = species) forms C_k, Wbar, rho and [M] from the
-//      prefetched T, p, Y of this point and prefetches the next point; wavefront 1
-//      evaluates the NASA-7 polynomials (g/RT, h/RT, cp/R) and the T-functions;
-//   B  threads = reactions: rate of progress and all its derivatives into the
-//      per-point reaction data (d values and quads, layout in build_jac_plan);
-//   C  lockstep gather rounds (build_jac_plan) into the accumulator matrix
+// (its constants stay in registers).  The mechanism's Troe parameters and efficiency
+// exceptions are staged in LDS once.  Per point, separated by workgroup barriers:
+//   B  threads = reactions: rate of progress and all its derivatives into the per-point
+//      reaction data (d values and quads, layout in build_jac_plan); each thread then
+//      loads its wavefront's gather records into registers;
+//   C  gather rounds (build_jac_plan) into the FP64 accumulator matrix
 //      A[k][0..3] = (dw_k/dT at fixed C, w_k, tau_k, R_k), A[k][5 + j] = the mass-action
 //      and efficiency-exception part of dw_k/dC_j; entries that no reaction reaches stay
 //      zero from the workgroup's start;
-//   D  hrr row partial sums -RT sum_k h_k A[k][c] in FP64 (JS_PWAVES wavefronts split the
+//   D  hrr row partial sums -RT sum_k h_k A[k][c] (JS_PWAVES wavefronts split the
 //      species), the row scalars alpha_k = rho tau_k - Wbar R_k and J_T of each row,
-//      sum_k cp_k w_k, and w_k to global memory;
+//      sum_k cp_k w_k and w_k to global memory (wavefront 3); meanwhile wavefronts 4 and
+//      5 form the NEXT point's state (NASA-7 polynomials; C_k, Wbar, rho from the
+//      prefetched T, p, Y) in the other half of the double-buffered state arrays;
 //   E  emission, each thread a fixed pair of columns over a strided set of rows:
 //        J[row][T]   = A[row][0] - R_row/T (- sum_k cp_k w_k on row 0)
 //        J[row][Y_j] = (rho A[row][5 + j] + alpha_row) / W_j
 // No LDS atomics: every LDS word has one writer per phase, and every sum is taken in
 // an order fixed by the plan, so results are bitwise reproducible.
 template <bool MIXED>
-__device__ inline void jac_seg_reaction(const DevMech &m, int r, unsigned sp03, unsigned sp45, int dpos, int xpos,
-                                        int n_exc, int exc0, int troe, int dnu, double lnA, double bb, double th,
-                                        const double *SP, const double *SC, int nd, double *RDd, double *RDq) {
+__device__ inline void jac_seg_reaction(int r, unsigned sp03, unsigned sp45, int dpos, int xpos, int n_exc,
+                                        int exc0, int troe, int dnu, double lnA, double bb, double th,
+                                        const double *SP, const double *SC, const double *TQ, const double *MQ,
+                                        const double *EXm, double *RDd, double *RDq) {
     using Rt = typename std::conditional<MIXED, float, double>::type;
     const int nfm = (sp45 >> 16) & 7, nrm = (sp45 >> 19) & 7, kind = (sp45 >> 22) & 3;
-    const double Ctot = SC[4], lnT = SC[5], invT = SC[6], lnp0RT = SC[7];
-    // third-body concentration [M] = Ctot + sum_exc (eps - 1) C_k
-    double M = 0.0;
+    const double lnT = SC[5], invT = SC[6], lnp0RT = SC[7];
+    // third-body concentration [M] and its logarithm (formed with the state)
+    double M = 0.0, lnMd = 0.0;
     if (kind != RXN_ELEMENTARY) {
-        M = Ctot;
-        for (int e = 0; e < n_exc; ++e) M += m.eff_m1[exc0 + e] * SP[4 * m.eff_sp[exc0 + e]];
+        const double2 mq = *(const double2 *)(MQ + 2 * (troe >> 16));
+        M = mq.x;
+        lnMd = mq.y;
     }
-    // forward rate constant (Arrhenius; Lindemann-Troe blending for falloff reactions)
+    troe &= 0xffff;
+    // forward rate constant (Arrhenius; Lindemann-Troe blending for falloff reactions,
+    // whose temperature-only terms come from jac_seg_troe_t)
     const Rt rlnT = (Rt)lnT, rinvT = (Rt)invT;
     const Rt lnkinf = (Rt)lnA + (Rt)bb * rlnT - (Rt)th * rinvT;
     const Rt kinf = exp_r<Rt>(lnkinf);
     const Rt dlnkinf = ((Rt)bb + (Rt)th * rinvT) * rinvT;
     Rt kf = kinf, dkf_dT = kinf * dlnkinf, dkf_dM = 0;
     if (kind == RXN_TROE) {
-        const double *tp = m.troe + 8 * troe;
-        const Rt lnA0 = (Rt)tp[0], b0 = (Rt)tp[1], th0 = (Rt)tp[2], alpha = (Rt)tp[3];
-        const Rt iT3 = (Rt)tp[4], iT1 = (Rt)tp[5], T2 = (Rt)tp[6];
-        const Rt rT = (Rt)SC[0];
-        const Rt lnk0 = lnA0 + b0 * rlnT - th0 * rinvT;
-        const Rt lnM = log_r<Rt>((Rt)M);
-        const Rt lnPr = lnk0 - lnkinf + lnM;
+        const double *tq = TQ + JS_TQ * troe;
+        const Rt lFc = (Rt)tq[0], dlFc = (Rt)tq[1], lnkr = (Rt)tq[2], dlnPr = (Rt)tq[3], k0 = (Rt)tq[4];
+        const Rt lnPr = lnkr + (Rt)lnMd;
         const Rt Pr = exp_r<Rt>(lnPr);
-        const Rt e3 = exp_r<Rt>(-rT * iT3), e1 = exp_r<Rt>(-rT * iT1), e2 = exp_r<Rt>(-T2 * rinvT);
-        const Rt Fc = ((Rt)1 - alpha) * e3 + alpha * e1 + e2;
-        const Rt tiny = MIXED ? (Rt)1e-37 : (Rt)1e-300;
-        const Rt lFc = log_r<Rt>(Fc > tiny ? Fc : tiny) * (Rt)INV_LN10;
         const Rt cc = (Rt)-0.4 - (Rt)0.67 * lFc;
         const Rt nn = (Rt)0.75 - (Rt)1.27 * lFc;
         const Rt lnfloor = MIXED ? (Rt)-85.19 : (Rt)-690.7755278982137;
@@ -659,14 +656,9 @@ __device__ inline void jac_seg_reaction(const DevMech &m, int r, unsigned sp03, 
         const Rt df1_dlFc = ((Rt)-0.67 * den - u * ((Rt)-1.27 + (Rt)0.67 * (Rt)0.14)) * idd;
         const Rt dlogF_dell = -lFc * (Rt)2 * f1 * df1_dell * gg * gg;
         const Rt dlogF_dlFc = gg - lFc * (Rt)2 * f1 * df1_dlFc * gg * gg;
-        const Rt dlnk0 = (b0 + th0 * rinvT) * rinvT;
-        const Rt dlnPr = dlnk0 - dlnkinf;
-        const Rt dFc = -((Rt)1 - alpha) * iT3 * e3 - alpha * iT1 * e1 + T2 * rinvT * rinvT * e2;
-        const Rt dlFc = dFc / (Fc * (Rt)LN10);
         const Rt dlnF = dlogF_dell * dlnPr + (Rt)LN10 * dlogF_dlFc * dlFc;
         const Rt ip1 = (Rt)1 / ((Rt)1 + Pr);
         dkf_dT = kf * (dlnkinf + dlnPr * ip1 + dlnF);
-        const Rt k0 = exp_r<Rt>(lnk0);
         dkf_dM = k0 * F * ip1 * (ip1 + dlogF_dell);
     }
     __builtin_amdgcn_sched_barrier(0);   // the slot loads below start after the rate constant
@@ -698,51 +690,175 @@ __device__ inline void jac_seg_reaction(const DevMech &m, int r, unsigned sp03, 
     // dq/dC of each molecule slot: the product of the other slots of its side
     const double dv[SLOTS] = {fk * c[1] * c[2], fk * c[0] * c[2], fk * c[0] * c[1],
                               -fr * c[4] * c[5], -fr * c[3] * c[5], -fr * c[3] * c[4]};
-    double *pos = RDd + 1 + dpos, *neg = RDd + 1 + nd + dpos;
+    double *pos = RDd + 1 + dpos;
 #pragma unroll
     for (int s = 0; s < MAX_SIDE; ++s)
-        if (s < nfm) {
-            pos[s] = dv[s];
-            neg[s] = -dv[s];
-        }
+        if (s < nfm) pos[s] = dv[s];
 #pragma unroll
     for (int s = 0; s < MAX_SIDE; ++s)
-        if (s < nrm) {
-            pos[nfm + s] = dv[MAX_SIDE + s];
-            neg[nfm + s] = -dv[MAX_SIDE + s];
+        if (s < nrm) pos[nfm + s] = dv[MAX_SIDE + s];
+    for (int e = 0; e < n_exc; ++e) RDd[1 + xpos + e] = mf * EXm[exc0 + e];
+}
+
+// Temperature-only terms of the falloff reactions at temperature Tt (lane j = falloff
+// reaction j), in two halves that run on different wavefronts:
+//   jac_seg_troe_fc: log10 Fcent and its T-derivative (TQ[0], TQ[1]);
+//   jac_seg_troe_k:  ln(k0/kinf), its T-derivative and k0 (TQ[2..4]).
+template <bool MIXED>
+__device__ inline void jac_seg_troe_fc(int lane, int n_troe, double Tt, const double *TP, double *TQ) {
+    using Rt = typename std::conditional<MIXED, float, double>::type;
+    for (int j = lane; j < n_troe; j += WAVE) {
+        const double *tp = TP + JS_TP * j;
+        const Rt T = (Rt)Tt, invT = (Rt)1 / T;
+        const Rt alpha = (Rt)tp[3], iT3 = (Rt)tp[4], iT1 = (Rt)tp[5], T2 = (Rt)tp[6];
+        const Rt e3 = exp_r<Rt>(-T * iT3), e1 = exp_r<Rt>(-T * iT1), e2 = exp_r<Rt>(-T2 * invT);
+        const Rt Fc = ((Rt)1 - alpha) * e3 + alpha * e1 + e2;
+        const Rt tiny = MIXED ? (Rt)1e-37 : (Rt)1e-300;
+        const Rt dFc = -((Rt)1 - alpha) * iT3 * e3 - alpha * iT1 * e1 + T2 * invT * invT * e2;
+        double *tq = TQ + JS_TQ * j;
+        tq[0] = (double)(log_r<Rt>(Fc > tiny ? Fc : tiny) * (Rt)INV_LN10);
+        tq[1] = (double)(dFc / (Fc * (Rt)LN10));
+    }
+}
+
+template <bool MIXED>
+__device__ inline void jac_seg_troe_k(int lane, int n_troe, double lnT_, double invT_, const double *TP, double *TQ) {
+    using Rt = typename std::conditional<MIXED, float, double>::type;
+    for (int j = lane; j < n_troe; j += WAVE) {
+        const double *tp = TP + JS_TP * j;
+        const Rt lnT = (Rt)lnT_, invT = (Rt)invT_;
+        const Rt lnA0 = (Rt)tp[0], b0 = (Rt)tp[1], th0 = (Rt)tp[2];
+        const Rt lnA = (Rt)tp[8], bb = (Rt)tp[9], th = (Rt)tp[10];
+        const Rt lnk0 = lnA0 + b0 * lnT - th0 * invT;
+        const Rt lnkinf = lnA + bb * lnT - th * invT;
+        double *tq = TQ + JS_TQ * j;
+        tq[2] = (double)(lnk0 - lnkinf);
+        tq[3] = (double)((b0 + th0 * invT) * invT - (bb + th * invT) * invT);
+        tq[4] = (double)exp_r<Rt>(lnk0);
+    }
+}
+
+// State phase of k_jac_seg for one point: wavefront `wy` (lane = species) forms C_k,
+// Wbar, rho and Ctot from the prefetched Y, p, T; wavefront `wy - 1` evaluates the
+// NASA-7 polynomials (coefficients staged in LDS) and the T-functions.  Writes
+// SP[k][C, g/RT, h/RT, cp/R] and SC.
+template <bool MIXED>
+__device__ inline void jac_seg_state(int ns, double R, double lnp0R, int wave, int wy, int lane, double Tt,
+                                     double pp, double yk, const double *NS, const double *IW, const int *MX,
+                                     int n_m, const double *EXm, const int *EXs, int n_troe, const double *TP,
+                                     double *SP, double *SC, double *MQ, double *TQ) {
+    if (wave == wy) {
+        const bool has = lane < ns;
+        double yw = 0.0;
+        if (has) yw = yk * IW[lane];
+        const double wbar = 1.0 / wave_sum(yw);
+        const double rho = pp * wbar / (R * Tt);
+        const double cv = rho * yw;
+        if (has) SP[4 * lane] = cv;
+        const double ct = wave_sum(cv);
+        if (lane == 0) {
+            SC[1] = pp;
+            SC[2] = rho;
+            SC[3] = wbar;
+            SC[4] = ct;
         }
-    for (int e = 0; e < n_exc; ++e) {
-        const double v = mf * m.eff_m1[exc0 + e];
-        RDd[1 + xpos + e] = v;
-        RDd[1 + nd + xpos + e] = -v;
+        // [M] = Ctot + sum_exc (eps - 1) C_k of every third-body / falloff reaction, and
+        // ln [M] of the falloff ones (slots 0 .. n_troe - 1)
+        wave_lds_sync();
+        for (int j = lane; j < n_m; j += WAVE) {
+            const int2 mx = *(const int2 *)(MX + 2 * j);
+            double M = ct;
+            int e = 0;
+            for (; e + 4 <= mx.y; e += 4) {   // the exceptions' loads issued together
+                const int k0 = EXs[mx.x + e], k1 = EXs[mx.x + e + 1], k2 = EXs[mx.x + e + 2], k3 = EXs[mx.x + e + 3];
+                const double c0 = SP[4 * k0], c1 = SP[4 * k1], c2 = SP[4 * k2], c3 = SP[4 * k3];
+                M += EXm[mx.x + e] * c0 + EXm[mx.x + e + 1] * c1 + EXm[mx.x + e + 2] * c2 + EXm[mx.x + e + 3] * c3;
+            }
+            for (; e < mx.y; ++e) M += EXm[mx.x + e] * SP[4 * EXs[mx.x + e]];
+            double lnM = 0.0;
+            if (j < n_troe) lnM = MIXED ? (double)__logf((float)M) : log(M);
+            *(double2 *)(MQ + 2 * j) = double2{M, lnM};
+        }
+    } else if (wave == wy - 1) {
+        const double lnT = log(Tt), invT = 1.0 / Tt;
+        if (lane < ns) {
+            const double *c16 = NS + 16 * lane;
+            double a[16];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double2 v = *(const double2 *)(c16 + 2 * q);
+                a[2 * q] = v.x;
+                a[2 * q + 1] = v.y;
+            }
+            const bool lo = Tt <= a[0];
+            double b[7];
+#pragma unroll
+            for (int q = 0; q < 7; ++q) b[q] = lo ? a[1 + q] : a[8 + q];
+            const double cp = b[0] + Tt * (b[1] + Tt * (b[2] + Tt * (b[3] + Tt * b[4])));
+            const double hh = b[0] + Tt * (b[1] * 0.5 + Tt * (b[2] * (1.0 / 3.0) + Tt * (b[3] * 0.25 + Tt * (b[4] * 0.2)))) +
+                              b[5] * invT;
+            const double sr_ = b[0] * lnT + Tt * (b[1] + Tt * (b[2] * 0.5 + Tt * (b[3] * (1.0 / 3.0) + Tt * (b[4] * 0.25)))) + b[6];
+            SP[4 * lane + 1] = hh - sr_;
+            SP[4 * lane + 2] = hh;
+            SP[4 * lane + 3] = cp;
+        }
+        if (lane == 0) {
+            SC[0] = Tt;
+            SC[5] = lnT;
+            SC[6] = invT;
+            SC[7] = lnp0R - lnT;
+        }
+        jac_seg_troe_k<MIXED>(lane, n_troe, lnT, invT, TP, TQ);
     }
 }
 
 template <bool MIXED>
 __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n, const double *__restrict__ T,
-                                                       const double *__restrict__ p, int64_t ps,
-                                                       const double *__restrict__ Y, int64_t ld,
-                                                       void *__restrict__ Jv, double *__restrict__ wdot) {
-    using Acc = typename std::conditional<MIXED, float, double>::type;
+                                                          const double *__restrict__ p, int64_t ps,
+                                                          const double *__restrict__ Y, int64_t ld,
+                                                          void *__restrict__ Jv, double *__restrict__ wdot) {
+    using Out = typename std::conditional<MIXED, float, double>::type;
     extern __shared__ __align__(16) unsigned char lds_b[];
     const int tid = threadIdx.x, lane = tid & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
-    const int ns = m.ns, n1 = ns + 1, sr = m.jp_sr, nd = m.jp_nd;
+    const int ns = m.ns, n1 = ns + 1, sr = m.jp_sr, n_troe = m.n_troe;
+    constexpr int WY = JS_WAVES - 1;        // wavefront that forms the mixture state
+    constexpr int WT = JS_PWAVES;           // wavefront that forms the falloff temperature terms
     double *RDd = (double *)lds_b;
     double *RDq = (double *)(lds_b + m.jp_off_rdq);
-    Acc *A = (Acc *)(lds_b + m.jp_off_a);
-    double *SP = (double *)(lds_b + m.jp_off_sp);
+    double *A = (double *)(lds_b + m.jp_off_a);
+    double *SP0 = (double *)(lds_b + m.jp_off_sp);
     double *ROW = (double *)(lds_b + m.jp_off_row);
     double *P = (double *)(lds_b + m.jp_off_p);
-    double *SC = (double *)(lds_b + m.jp_off_sc);
-    Acc *J = (Acc *)Jv;
-    // ---- workgroup set-up: zero accumulators, the no-op entries and the unit dummy species
-    for (int e = tid; e < ns * sr + 4; e += JS_THREADS) A[e] = (Acc)0;
+    double *SC0 = (double *)(lds_b + m.jp_off_sc);
+    double *TP = (double *)(lds_b + m.jp_off_tp);
+    double *TQ0 = (double *)(lds_b + m.jp_off_tq);
+    double *NS = (double *)(lds_b + m.jp_off_ns);
+    double *IW = (double *)(lds_b + m.jp_off_iw);
+    double *EXm = (double *)(lds_b + m.jp_off_ex);
+    int *EXs = (int *)(EXm + m.n_exc);
+    int *MX = (int *)(lds_b + m.jp_off_mx);
+    double *MQ0 = (double *)(lds_b + m.jp_off_mq);
+    const int n_m = m.jp_nm;
+    Out *J = (Out *)Jv;
+    // ---- workgroup set-up: zero accumulators and the no-op entries, the unit dummy
+    // species in both state buffers, the Troe and efficiency tables
+    for (int e = tid; e < ns * sr + 4; e += JS_THREADS) A[e] = 0.0;
     if (tid == 0) RDd[0] = 0.0;
     if (tid < 4) {
         RDq[4 * m.nr + tid] = 0.0;
-        SP[4 * ns + tid] = tid == 0 ? 1.0 : 0.0;
+        SP0[4 * ns + tid] = tid == 0 ? 1.0 : 0.0;
+        SP0[4 * (ns + 1) + 4 * ns + tid] = tid == 0 ? 1.0 : 0.0;
     }
+    for (int e = tid; e < 8 * n_troe; e += JS_THREADS) TP[JS_TP * (e / 8) + e % 8] = m.troe[e];
+    for (int e = tid; e < m.n_exc; e += JS_THREADS) {
+        EXm[e] = m.eff_m1[e];
+        EXs[e] = m.eff_sp[e];
+    }
+    for (int e = tid; e < 16 * ns; e += JS_THREADS) NS[e] = m.nasa[e];
+    for (int e = tid; e < ns; e += JS_THREADS) IW[e] = m.invW[e];
+    for (int e = tid; e < 2 * n_m; e += JS_THREADS) MX[e] = m.jp_mrx[e];
+    const double lnp0R = log(m.p0 / m.R);
     // this thread's reaction
     const int4 ta = ((const int4 *)m.jp_thr)[2 * tid], tb = ((const int4 *)m.jp_thr)[2 * tid + 1];
     const int r = ta.x;
@@ -753,83 +869,70 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
         lnA = m.lnA[r];
         bb = m.b[r];
         th = m.theta[r];
+        const int ti = troe & 0xffff;
+        if (ti != 0xffff) {   // the high-pressure Arrhenius constants beside the Troe constants
+            TP[JS_TP * ti + 8] = lnA;
+            TP[JS_TP * ti + 9] = bb;
+            TP[JS_TP * ti + 10] = th;
+        }
     }
     // gather program of this wavefront (uniform)
-    const int4 prog = ((const int4 *)m.jp_prog)[wave];
-    const int nq = __builtin_amdgcn_readfirstlane(prog.x), ndr = __builtin_amdgcn_readfirstlane(prog.y);
-    const uint4 *qrec = (const uint4 *)(m.jp_recs + __builtin_amdgcn_readfirstlane(prog.z));
-    const uint2 *drec = (const uint2 *)(m.jp_recs + __builtin_amdgcn_readfirstlane(prog.w));
-    // emission mapping: a pair of columns (c0, c0 + 1) and a row phase per thread
+    const int *prog = m.jp_prog + 8 * wave;
+    const int nq = __builtin_amdgcn_readfirstlane(prog[0]), ndr = __builtin_amdgcn_readfirstlane(prog[1]);
+    const uint4 *qrec = (const uint4 *)(m.jp_recs + __builtin_amdgcn_readfirstlane(prog[2]));
+    const uint2 *drec = (const uint2 *)(m.jp_recs + __builtin_amdgcn_readfirstlane(prog[3]));
+    const unsigned qsync = __builtin_amdgcn_readfirstlane(prog[4]), dsync = __builtin_amdgcn_readfirstlane(prog[5]);
+    // emission mapping: a pair of columns (c0, c0 + 1) and a row phase per thread, on
+    // wavefronts 0..JS_EWAVES-1 (the falloff and third-body wavefronts, which take longest
+    // in the rate phase that follows, and the state wavefronts do not emit)
     const int npair = (n1 + 1) / 2;
-    const int rphase = JS_THREADS / npair;
+    const int rphase = JS_EWAVES * WAVE / npair;
     const int pc0 = 2 * (tid % npair), pr0 = tid / npair;
-    const bool pon = pr0 < rphase;
+    const bool pon = tid < JS_EWAVES * WAVE && pr0 < rphase;
     const double iw0 = (pc0 >= 1 && pc0 - 1 < ns) ? m.invW[pc0 - 1] : 0.0;
     const double iw1 = (pc0 < ns) ? m.invW[pc0] : 0.0;
-    // prefetch of the first point
+    // state of the first point into buffer 0; prefetch of the second (indices clamped:
+    // a block always has a first point, and a repeat past the end is never used)
     double pf_T = 0.0, pf_p = 0.0, pf_Y = 0.0;
-    if (wave <= 1 && (int64_t)blockIdx.x < n) {
-        const int64_t i0 = blockIdx.x;
-        pf_T = T[i0];
-        if (wave == 0) {
-            pf_p = p[i0 * ps];
-            if (lane < ns) pf_Y = Y[(int64_t)lane * ld + i0];
-        }
+    __syncthreads();   // staged tables complete
+    if (n > 0) {
+        const int64_t i0 = min((int64_t)blockIdx.x, n - 1), i1 = min(i0 + (int64_t)gridDim.x, n - 1);
+        const int ky = min(lane, ns - 1);
+        if (wave >= WY - 1)
+            jac_seg_state<MIXED>(ns, m.R, lnp0R, wave, WY, lane, T[i0], p[i0 * ps], Y[(int64_t)ky * ld + i0], NS,
+                                 IW, MX, n_m, EXm, EXs, n_troe, TP, SP0, SC0, MQ0, TQ0);
+        else if (wave == WT)
+            jac_seg_troe_fc<MIXED>(lane, n_troe, T[i0], TP, TQ0);
+        pf_T = T[i1];
+        pf_p = p[i1 * ps];
+        pf_Y = Y[(int64_t)ky * ld + i1];
     }
-    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const int64_t inext = i + gridDim.x;
-        // ---- A
-        if (wave == 0) {
-            const bool has = lane < ns;
-            double yw = 0.0;
-            if (has) yw = pf_Y * m.invW[lane];
-            const double wbar = 1.0 / wave_sum(yw);
-            const double rho = pf_p * wbar / (m.R * pf_T);
-            const double cv = rho * yw;
-            if (has) SP[4 * lane] = cv;
-            const double ct = wave_sum(cv);
-            if (lane == 0) {
-                SC[1] = pf_p;
-                SC[2] = rho;
-                SC[3] = wbar;
-                SC[4] = ct;
-            }
-            if (inext < n) {
-                pf_T = T[inext];
-                pf_p = p[inext * ps];
-                if (has) pf_Y = Y[(int64_t)lane * ld + inext];
-            }
-        } else if (wave == 1) {
-            const double Tt = pf_T, lnT = log(Tt), invT = 1.0 / Tt;
-            if (lane < ns) {
-                double cp, hh, sr_;
-                nasa7(m.nasa + 16 * lane, Tt, lnT, invT, cp, hh, sr_);
-                SP[4 * lane + 1] = hh - sr_;
-                SP[4 * lane + 2] = hh;
-                SP[4 * lane + 3] = cp;
-            }
-            if (lane == 0) {
-                SC[0] = Tt;
-                SC[5] = lnT;
-                SC[6] = invT;
-                SC[7] = log(m.p0 / (m.R * Tt));
-            }
-            if (inext < n) pf_T = T[inext];
-        }
-        __syncthreads();
+    __syncthreads();
+    int buf = 0;
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x, buf ^= 1) {
+        const double *SP = SP0 + buf * 4 * (ns + 1);
+        double *SC = SC0 + buf * 16;
         // ---- B
         if (r >= 0)
-            jac_seg_reaction<MIXED>(m, r, sp03, sp45, dpos, xpos, n_exc, exc0, troe, dnu, lnA, bb, th, SP, SC, nd,
-                                    RDd, RDq);
+            jac_seg_reaction<MIXED>(r, sp03, sp45, dpos, xpos, n_exc, exc0, troe, dnu, lnA, bb, th, SP, SC,
+                                    TQ0 + buf * JS_TQ * n_troe, MQ0 + buf * 2 * n_m, EXm, RDd, RDq);
         const double Tt = SC[0], rho = SC[2], wbar = SC[3], invT = SC[6];
+        // this wavefront's gather records (the same for every point; L1/L2 resident)
+        uint4 qr[JS_QMAX];
+        uint2 dr[JS_DMAX];
+#pragma unroll
+        for (int q = 0; q < JS_QMAX; ++q) qr[q] = q < nq ? qrec[q * 64 + lane] : uint4{0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int q = 0; q < JS_DMAX; ++q) dr[q] = q < ndr ? drec[q * 64 + lane] : uint2{0u, 0u};
         __syncthreads();
         // ---- C
-        {
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-            const unsigned char *RQ = lds_b + m.jp_off_rdq;
-            for (int rr = 0; rr < nq; ++rr) {
-                const uint4 w0 = qrec[rr * 128 + lane], w1 = qrec[rr * 128 + 64 + lane];
-                const unsigned u[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+        const unsigned char *RQ = lds_b + m.jp_off_rdq;
+#pragma unroll
+        for (int q = 0; q < JS_QMAX; ++q) {
+            if (q < nq) {
+                if (qsync >> q & 1u) wave_lds_sync();
+                const unsigned u[4] = {qr[q].x, qr[q].y, qr[q].z, qr[q].w};
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
                 for (int j = 1; j <= JS_LQ; ++j) {
                     const unsigned rec = (u[j >> 1] >> (16 * (j & 1))) & 0xffffu;
@@ -841,93 +944,126 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
                     a2 = fma(cf, y.x, a2);
                     a3 = fma(cf, y.y, a3);
                 }
-                const unsigned tw = u[0] & 0xffffu;
-                if (tw & 0x8000u) {
-                    typedef Acc Acc4 __attribute__((ext_vector_type(4)));
-                    *(Acc4 *)(A + (tw & 0x7fffu)) = Acc4{(Acc)a0, (Acc)a1, (Acc)a2, (Acc)a3};
-                    a0 = a1 = a2 = a3 = 0.0;
-                }
+                double2 *dst = (double2 *)(lds_b + 16u * (u[0] & 0xffffu));
+                dst[0] = double2{a0, a1};
+                dst[1] = double2{a2, a3};
             }
-            double acc = 0.0;
-            uint2 wn = ndr > 0 ? drec[lane] : uint2{0u, 0u};
-            for (int rr = 0; rr < ndr; ++rr) {
-                const uint2 w = wn;
-                if (rr + 1 < ndr) wn = drec[(rr + 1) * 64 + lane];
-                acc += *(const double *)(lds_b + (w.x >> 16));
-                acc += *(const double *)(lds_b + (w.y & 0xffffu));
-                acc += *(const double *)(lds_b + (w.y >> 16));
-                const unsigned tw = w.x & 0xffffu;
-                if (tw & 0x8000u) {
-                    A[tw & 0x7fffu] = (Acc)acc;
-                    acc = 0.0;
+        }
+        // d rounds, software-pipelined: round q + 1's values are read before round q's store
+        // unless a sync separates them (then round q + 1 reads what round q may write)
+        {
+            double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+            auto rd = [&](const uint2 w) {
+                v0 = *(const double *)(lds_b + ((w.x >> 16) & 0xfff8u));
+                v1 = *(const double *)(lds_b + (w.y & 0xfff8u));
+                v2 = *(const double *)(lds_b + ((w.y >> 16) & 0xfff8u));
+            };
+            auto cf = [](unsigned rec) { return (double)(int)__builtin_amdgcn_sbfe((int)rec, 0, 3); };
+            if (ndr > 0) {
+                if (dsync & 1u) wave_lds_sync();
+                rd(dr[0]);
+            }
+#pragma unroll
+            for (int q = 0; q < JS_DMAX; ++q) {
+                if (q < ndr) {
+                    const uint2 w = dr[q];
+                    const double acc = fma(cf(w.y >> 16), v2, fma(cf(w.y), v1, cf(w.x >> 16) * v0));
+                    const bool more = q + 1 < ndr && q + 1 < JS_DMAX;
+                    const bool sync_next = more && (dsync >> (q + 1) & 1u);
+                    if (more && !sync_next) rd(dr[q + 1 < JS_DMAX ? q + 1 : q]);
+                    *(double *)(lds_b + 8u * (w.x & 0xffffu)) = acc;
+                    if (sync_next) {
+                        wave_lds_sync();
+                        rd(dr[q + 1 < JS_DMAX ? q + 1 : q]);
+                    }
                 }
             }
         }
         __syncthreads();
-        // ---- D
+        // ---- D (and the next point's state on wavefronts WY - 1, WY)
         if (wave < JS_PWAVES) {
             const double mRT = -m.R * Tt;
             for (int cc = lane; cc < ns + 5; cc += WAVE) {
-                double s0 = 0.0;
-                for (int k = wave; k < ns; k += JS_PWAVES) s0 += SP[4 * k + 2] * (double)A[k * sr + cc];
-                P[wave * sr + cc] = mRT * s0;
+                double s0 = 0.0, s1 = 0.0;
+                int k = wave;
+#pragma unroll 4
+                for (; k + JS_PWAVES < ns; k += 2 * JS_PWAVES) {
+                    s0 += SP[4 * k + 2] * A[k * sr + cc];
+                    s1 += SP[4 * (k + JS_PWAVES) + 2] * A[(k + JS_PWAVES) * sr + cc];
+                }
+                if (k < ns) s0 += SP[4 * k + 2] * A[k * sr + cc];
+                P[wave * sr + cc] = mRT * (s0 + s1);
             }
         } else if (wave == JS_PWAVES) {
             double cwp = 0.0;
             for (int k = lane; k < ns; k += WAVE) {
-                const Acc *Ar = A + k * sr;
-                const double tk = (double)Ar[0], wk = (double)Ar[1], tau = (double)Ar[2], Rk = (double)Ar[3];
-                ROW[2 * k] = rho * tau - wbar * Rk;
-                ROW[2 * k + 1] = tk - Rk * invT;
-                cwp += SP[4 * k + 3] * wk;
-                if (wdot) wdot[(int64_t)k * ld + i] = wk;
+                const double2 q01 = *(const double2 *)(A + k * sr), q23 = *(const double2 *)(A + k * sr + 2);
+                *(double2 *)(ROW + 2 * k) = double2{rho * q23.x - wbar * q23.y, q01.x - q23.y * invT};
+                cwp += SP[4 * k + 3] * q01.y;
+                if (wdot) wdot[(int64_t)k * ld + i] = q01.y;
             }
             const double cw = wave_sum(cwp) * m.R;
             if (lane == 0) SC[8] = cw;
+            jac_seg_troe_fc<MIXED>(lane, n_troe, pf_T, TP, TQ0 + (buf ^ 1) * JS_TQ * n_troe);
+        } else {
+            // state of point i + gridDim.x (past the end: a repeat of the last point, unused)
+            double *SPn = SP0 + (buf ^ 1) * 4 * (ns + 1), *SCn = SC0 + (buf ^ 1) * 16;
+            jac_seg_state<MIXED>(ns, m.R, lnp0R, wave, WY, lane, pf_T, pf_p, pf_Y, NS, IW, MX, n_m, EXm, EXs,
+                                 n_troe, TP, SPn, SCn, MQ0 + (buf ^ 1) * 2 * n_m, TQ0 + (buf ^ 1) * JS_TQ * n_troe);
+        }
+        {   // prefetch of point i + 2 gridDim.x, in straight-line code on every wavefront
+            const int64_t i2 = min(i + 2 * (int64_t)gridDim.x, n - 1);
+            pf_T = T[i2];
+            pf_p = p[i2 * ps];
+            pf_Y = Y[(int64_t)min(lane, ns - 1) * ld + i2];
         }
         __syncthreads();
         // ---- E
-        Acc *Jp = J + (size_t)i * n1 * n1;
+        Out *Jp = J + (size_t)i * n1 * n1;
         if (pon) {
             const double cw = SC[8];
-            for (int row = pr0; row < n1; row += rphase) {
-                double a0, a1, al, jt;
-                if (row == 0) {
-                    double t0 = 0.0, tau0 = 0.0, R0 = 0.0;
-                    a0 = 0.0;
-                    a1 = 0.0;
+#pragma unroll 2
+            for (int q = 0; q < JS_EROWS; ++q) {
+                const int row = pr0 + q * rphase;
+                if (row < n1) {
+                    double a0, a1, al, jt;
+                    if (row == 0) {
+                        double t0 = 0.0, tau0 = 0.0, R0 = 0.0;
+                        a0 = 0.0;
+                        a1 = 0.0;
 #pragma unroll
-                    for (int w = 0; w < JS_PWAVES; ++w) {
-                        const double *Pw = P + w * sr;
-                        t0 += Pw[0];
-                        tau0 += Pw[2];
-                        R0 += Pw[3];
-                        a0 += Pw[4 + pc0];
-                        if (pc0 + 1 < n1) a1 += Pw[5 + pc0];
+                        for (int w = 0; w < JS_PWAVES; ++w) {
+                            const double *Pw = P + w * sr;
+                            t0 += Pw[0];
+                            tau0 += Pw[2];
+                            R0 += Pw[3];
+                            a0 += Pw[4 + pc0];
+                            if (pc0 + 1 < n1) a1 += Pw[5 + pc0];
+                        }
+                        al = rho * tau0 - wbar * R0;
+                        jt = t0 - cw - R0 * invT;
+                    } else {
+                        const double2 av = *(const double2 *)(A + (row - 1) * sr + 4 + pc0);   // 16-byte aligned
+                        a0 = av.x;
+                        a1 = av.y;
+                        const double2 rw = *(const double2 *)(ROW + 2 * (row - 1));
+                        al = rw.x;
+                        jt = rw.y;
                     }
-                    al = rho * tau0 - wbar * R0;
-                    jt = t0 - cw - R0 * invT;
-                } else {
-                    const Acc *Ar = A + (row - 1) * sr + 4 + pc0;
-                    a0 = (double)Ar[0];
-                    a1 = pc0 + 1 < n1 ? (double)Ar[1] : 0.0;
-                    const double2 rw = *(const double2 *)(ROW + 2 * (row - 1));
-                    al = rw.x;
-                    jt = rw.y;
-                }
-                const Acc v0 = (Acc)(pc0 == 0 ? jt : (rho * a0 + al) * iw0);
-                const Acc v1 = (Acc)((rho * a1 + al) * iw1);
-                Acc *dst = Jp + row * n1 + pc0;
-                if (pc0 + 1 < n1) {
-                    if ((((uintptr_t)dst) & (2 * sizeof(Acc) - 1)) == 0) {
-                        typedef Acc Acc2 __attribute__((ext_vector_type(2)));
-                        *(Acc2 *)dst = Acc2{v0, v1};
+                    const Out v0 = (Out)(pc0 == 0 ? jt : (rho * a0 + al) * iw0);
+                    const Out v1 = (Out)((rho * a1 + al) * iw1);
+                    Out *dst = Jp + row * n1 + pc0;
+                    if (pc0 + 1 < n1) {
+                        if ((((uintptr_t)dst) & (2 * sizeof(Out) - 1)) == 0) {
+                            typedef Out Out2 __attribute__((ext_vector_type(2)));
+                            *(Out2 *)dst = Out2{v0, v1};
+                        } else {
+                            dst[0] = v0;
+                            dst[1] = v1;
+                        }
                     } else {
                         dst[0] = v0;
-                        dst[1] = v1;
                     }
-                } else {
-                    dst[0] = v0;
                 }
             }
         }
@@ -1095,6 +1231,10 @@ hipError_t launch_jac(const DevMech &m, int mixed, int64_t n, const double *T, c
                       const double *Y, int64_t ld, void *J, double *wdot, hipStream_t st) {
     if (m.jp_ok && m.jp_lds <= JS_MAX_LDS) {
         const dim3 grid(grid_for(n, 1, 2)), block(JS_THREADS);
+        const void *fn = mixed ? (const void *)k_jac_seg<true> : (const void *)k_jac_seg<false>;
+        // more than 64 KB of dynamic LDS per workgroup has to be allowed explicitly
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, m.jp_lds);
+        if (e != hipSuccess) return e;
         if (mixed)
             hipLaunchKernelGGL((k_jac_seg<true>), grid, block, m.jp_lds, st, m, n, T, p, ps, Y, ld, J, wdot);
         else

@@ -244,101 +244,62 @@ crf_status parse_mechanism(const char *path, HostMech &h) {
 //   d values  (index x < nd): dq_i/dC of molecule slot s of reaction i (mass-action
 //             part; a species with coefficient nu fills nu slots), then
 //             dq_i/d[M] (eps - 1) for every third-body efficiency exception;
-//             stored at byte 8 (1 + x) and, negated, at byte 8 (1 + nd + x); byte 0
-//             holds 0.0 (the no-op record);
-//   quad      (RDq + 32 i): dq_i/dT at fixed C, q_i, dq_i/d[M], sum_j C_j dq_i/dC_j;
-//             entry nr is zero.
-// The accumulator matrix A (species rows k, stride sr) is then plain sums of these:
+//             stored at byte 8 (1 + x); byte 0 holds 0.0; partial sums follow at
+//             8 (1 + nd + p);
+//   quads     (RQ + 32 i): dq_i/dT at fixed C, q_i, dq_i/d[M], sum_j C_j dq_i/dC_j;
+//             quad nr is zero; partial quads follow at RQ + 32 (nr + 1 + p).
+// The accumulator matrix A (species rows k, stride sr, FP64) is plain sums of these:
 //   A[k][0..3] = sum_i dnu_ki quad_i                     ("quad" targets)
 //   A[k][5+j]  = sum_i dnu_ki (dq_i/dC_j + exception terms)  ("d" targets)
-// Each target is summed by one lane, in rounds that every lane of a wavefront runs in
-// lockstep: a quad round reads JS_LQ records per lane (32 r | dnu as a signed 3-bit
-// field), a d round JS_LD records (LDS byte offsets of the signed copy; |dnu| = 2, 3
-// repeat the record).  A target longer than one round continues in the same lane in
-// the next round of its kind; the lane's target word (bits 0-14 A index, bit 15 =
-// store and reset after this round) is the first 16-bit field of the round.  Targets
-// are packed into shelves of 64 lanes x R rounds (first fit, longest first) and the
-// shelves are dealt to the wavefronts, costliest first, onto the least-loaded one.
+// Every target becomes a small reduction tree of tasks; a task is one lane of one
+// round: it adds at most JS_LQ quad records (32 r | dnu as a signed 3-bit field, or a
+// partial quad with coefficient +1) or JS_LD d records (LDS byte offset of the value or
+// of a partial | dnu or +1 as a signed 3-bit field) and stores the sum to its
+// destination word (the first 16-bit field of the lane's round: the LDS index of the
+// destination in 16-byte units for quads, 8-byte units for d values).  A target's
+// tasks run on one wavefront, level by level; a wave-local LDS sync precedes the first
+// round of every level above 0.  Targets are dealt to the wavefronts so that the
+// estimated round cost per wavefront is balanced.
 namespace {
 
-struct GatherTarget {
-    int aidx;
-    std::vector<unsigned> recs;
+struct PlanTask {
+    bool partial;                 // destination is a partial slot (else the final entry)
+    int dest;                     // partial index or final index (row k for quads, A entry for d)
+    std::vector<unsigned> recs;   // records (resolved except for nothing: sources are fixed offsets)
+    int level;
 };
 
-struct Shelf {
-    int R = 0;
-    std::vector<std::vector<int>> lane;   // targets of each lane, in order
-    std::vector<int> load;                // rounds used by each lane
+struct PlanTree {
+    int kind;                     // 0 quad, 1 d
+    int final_dest;
+    std::vector<unsigned> leaves; // the target's leaf records (for the self-check)
+    std::vector<PlanTask> tasks;
+    int depth;
 };
 
-std::vector<Shelf> pack_shelves(const std::vector<GatherTarget> &tg, int L) {
-    std::vector<int> order(tg.size());
-    for (size_t t = 0; t < tg.size(); ++t) order[t] = (int)t;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return tg[a].recs.size() > tg[b].recs.size(); });
-    std::vector<Shelf> sh;
-    for (int t : order) {
-        const int u = ((int)tg[t].recs.size() + L - 1) / L;
-        bool placed = false;
-        for (auto &s : sh) {
-            for (int l = 0; l < 64 && !placed; ++l)
-                if (s.load[l] + u <= s.R) {
-                    s.lane[l].push_back(t);
-                    s.load[l] += u;
-                    placed = true;
-                }
-            if (placed) break;
+// Splits `recs` into tasks of at most L records; full chunks become partial sums,
+// leftovers are carried to the next level with the new partial records.
+void build_tree(PlanTree &t, std::vector<unsigned> recs, int L, int &n_partial,
+                unsigned (*partial_rec)(int p, int base), int base) {
+    int level = 0;
+    while ((int)recs.size() > L) {
+        std::vector<unsigned> next;
+        const size_t full = recs.size() / L * L;
+        for (size_t c = 0; c < full; c += L) {
+            const int p = n_partial++;
+            t.tasks.push_back({true, p, std::vector<unsigned>(recs.begin() + c, recs.begin() + c + L), level});
+            next.push_back(partial_rec(p, base));
         }
-        if (!placed) {
-            Shelf s;
-            s.R = u;
-            s.lane.assign(64, {});
-            s.load.assign(64, 0);
-            s.lane[0].push_back(t);
-            s.load[0] = u;
-            sh.push_back(std::move(s));
-        }
+        for (size_t c = full; c < recs.size(); ++c) next.push_back(recs[c]);
+        recs = std::move(next);
+        ++level;
     }
-    return sh;
+    t.tasks.push_back({false, t.final_dest, recs, level});
+    t.depth = level + 1;
 }
 
-// Writes the rounds of `shelves` (all of one kind, L records per round) for one
-// wavefront into `out` starting at word `base`; `words` = 32-bit words per lane and round.
-void emit_rounds(const std::vector<GatherTarget> &tg, const std::vector<const Shelf *> &shelves, int L,
-                 int words, unsigned trash_word, unsigned zero_rec, std::vector<unsigned> &out, size_t base) {
-    size_t round = 0;
-    for (const Shelf *s : shelves) {
-        for (int l = 0; l < 64; ++l) {
-            std::vector<unsigned> f;   // 16-bit fields of this lane, round after round
-            for (int t : s->lane[l]) {
-                const auto &g = tg[t];
-                const int u = ((int)g.recs.size() + L - 1) / L;
-                for (int part = 0; part < u; ++part) {
-                    f.push_back((unsigned)g.aidx | (part == u - 1 ? 0x8000u : 0u));
-                    for (int j = 0; j < L; ++j) {
-                        const size_t x = (size_t)part * L + j;
-                        f.push_back(x < g.recs.size() ? g.recs[x] : zero_rec);
-                    }
-                }
-            }
-            while ((int)(f.size() / (1 + L)) < s->R) {
-                f.push_back(trash_word);
-                for (int j = 0; j < L; ++j) f.push_back(zero_rec);
-            }
-            for (int r = 0; r < s->R; ++r)
-                for (int x = 0; x <= L; ++x) {
-                    // field x of round r: word x / 2 (low or high half); quad rounds split
-                    // their 8 words into two uint4 halves laid out [half][lane][4]
-                    const int w = x / 2;
-                    const size_t idx = words == 8 ? base + (round + r) * 512 + (w / 4) * 256 + (size_t)l * 4 + (w % 4)
-                                                  : base + (round + r) * 128 + (size_t)l * 2 + w;
-                    out[idx] |= (f[(size_t)r * (1 + L) + x] & 0xffffu) << (16 * (x & 1));
-                }
-        }
-        round += s->R;
-    }
-}
+unsigned quad_partial_rec(int p, int nr) { return 32u * (unsigned)(nr + 1 + p) | 1u; }
+unsigned d_partial_rec(int p, int nd) { return 8u * (unsigned)(1 + nd + p) | 1u; }
 
 }  // namespace
 
@@ -347,6 +308,7 @@ void build_jac_plan(HostMech &h) {
     h.jp_thr.clear();
     h.jp_recs.clear();
     h.jp_prog.clear();
+    h.jp_mrx.clear();
     const int ns = h.ns(), nr = h.nr();
     auto no = [&](const std::string &why) {
         h.jp_ok = 0;
@@ -354,10 +316,15 @@ void build_jac_plan(HostMech &h) {
         h.jp_thr.clear();
         h.jp_recs.clear();
         h.jp_prog.clear();
+        h.jp_mrx.clear();
     };
     if (ns < 1 || nr < 1) return no("empty mechanism");
     if (ns > 64) return no("more than 64 species (the state phase is one species per lane)");
     if (nr > JS_THREADS) return no("more reactions than threads per workgroup");
+    {   // emission: column pairs x row phases over JS_EWAVES wavefronts, at most JS_EROWS rows each
+        const int n1 = ns + 1, npair = (n1 + 1) / 2, rphase = JS_EWAVES * 64 / npair;
+        if (rphase < 1 || (n1 + rphase - 1) / rphase > JS_EROWS) return no("Jacobian rows per emitting thread");
+    }
     // threads: non-Troe reactions first; Troe reactions from the next wavefront boundary
     // (the falloff branch then runs on as few wavefronts as possible)
     int n_non = 0, n_tr = 0;
@@ -397,14 +364,12 @@ void build_jac_plan(HostMech &h) {
         xpos[i] = nd;
         nd += h.ri[i].v[7] & 255;
     }
-    if (8 * (1 + 2 * nd) > 0xffff) return no("too many derivative values for 16-bit records");
-    const int sr = (ns + 5 + 3) / 4 * 4;
-    const int a_trash = ns * sr;
-    if (a_trash + 4 > 0x7fff) return no("accumulator matrix too large for 15-bit targets");
+    const int sr = (ns + 5 + 1) / 2 * 2;
     h.jp_nd = nd;
     h.jp_sr = sr;
     // per-thread constants
     h.jp_thr.assign(JS_THREADS, JsThr{-1, 0, 0, 0, 0, 0, -1, 0});
+    h.jp_mrx.clear();
     for (int i = 0; i < nr; ++i) {
         JsThr &c = h.jp_thr[thr_of[i]];
         const int info = h.info[i];
@@ -416,12 +381,23 @@ void build_jac_plan(HostMech &h) {
         c.dpos = dpos[i];
         c.xpos = xpos[i] | (h.ri[i].v[7] & 255) << 16;
         c.exc0 = h.ri[i].v[6];
-        c.troe = info_kind(info) == RXN_TROE ? (h.ri[i].v[7] >> 8) : -1;
+        c.troe = info_kind(info) == RXN_TROE ? (h.ri[i].v[7] >> 8) & 0xffff : 0xffff;
         c.dnu = h.dnu_sum[i];
     }
-    // gather targets
+    // [M] slots, formed with the state: falloff reactions first (only they need ln [M])
+    for (int pass = 0; pass < 2; ++pass)
+        for (int i = 0; i < nr; ++i) {
+            const int kind = info_kind(h.info[i]);
+            if (kind == RXN_ELEMENTARY || (kind == RXN_TROE) != (pass == 0)) continue;
+            h.jp_thr[thr_of[i]].troe |= ((int)h.jp_mrx.size() / 2) << 16;
+            h.jp_mrx.push_back(h.ri[i].v[6]);
+            h.jp_mrx.push_back(h.ri[i].v[7] & 255);
+        }
+    for (int i = 0; i < nr; ++i)
+        if (info_kind(h.info[i]) == RXN_ELEMENTARY) h.jp_thr[thr_of[i]].troe |= 0xffff << 16;
+    // gather targets (leaf records)
     std::vector<std::vector<unsigned>> qrec(ns);
-    std::map<int, std::vector<unsigned>> drec;
+    std::map<int, std::vector<unsigned>> drec;   // A entry -> records
     for (int i = 0; i < nr; ++i) {
         std::map<int, int> dn;
         for (int s = 0; s < SLOTS; ++s)
@@ -430,129 +406,243 @@ void build_jac_plan(HostMech &h) {
         for (const auto &kv : dn) {
             const int k = kv.first, v = kv.second;
             if (v == 0) continue;
-            qrec[k].push_back(32u * (unsigned)i | ((unsigned)v & 7u));
-            const int reps = v < 0 ? -v : v;
-            const int neg = v < 0 ? nd : 0;
+            const unsigned cf = (unsigned)v & 7u;
+            qrec[k].push_back(32u * (unsigned)i | cf);
             for (int s = 0; s < SLOTS; ++s) {
                 if (mol[i][s] < 0) continue;
                 const int x = dpos[i] + (s < MAX_SIDE ? s : nfm[i] + s - MAX_SIDE);
-                for (int c = 0; c < reps; ++c) drec[k * sr + 5 + mol[i][s]].push_back(8u * (unsigned)(1 + neg + x));
+                drec[k * sr + 5 + mol[i][s]].push_back(8u * (unsigned)(1 + x) | cf);
             }
             for (int e = 0; e < n_exc; ++e) {
                 const int j = h.eff_sp[h.ri[i].v[6] + e];
-                for (int c = 0; c < reps; ++c) drec[k * sr + 5 + j].push_back(8u * (unsigned)(1 + neg + xpos[i] + e));
+                drec[k * sr + 5 + j].push_back(8u * (unsigned)(1 + xpos[i] + e) | cf);
             }
         }
     }
-    std::vector<GatherTarget> tq, td;
+    // reduction trees
+    std::vector<PlanTree> trees;
+    int npq = 0, npd = 0;
     for (int k = 0; k < ns; ++k)
-        if (!qrec[k].empty()) tq.push_back({k * sr, qrec[k]});
-    for (auto &kv : drec) td.push_back({kv.first, kv.second});
-    const std::vector<Shelf> sq = pack_shelves(tq, JS_LQ), sd = pack_shelves(td, JS_LD);
-    // deal shelves to wavefronts (cost ~ VALU per round of each kind)
-    constexpr int CQ = 9 * JS_LQ + 14, CD = 3 * JS_LD + 6;
-    struct Item { int cost, kind, idx; };
-    std::vector<Item> items;
-    for (size_t s = 0; s < sq.size(); ++s) items.push_back({sq[s].R * CQ, 0, (int)s});
-    for (size_t s = 0; s < sd.size(); ++s) items.push_back({sd[s].R * CD, 1, (int)s});
-    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
-    std::vector<int> wload(JS_WAVES, 0);
-    std::vector<std::vector<const Shelf *>> wq(JS_WAVES), wd(JS_WAVES);
-    for (const Item &it : items) {
-        int w = 0;
-        for (int u = 1; u < JS_WAVES; ++u)
-            if (wload[u] < wload[w]) w = u;
-        wload[w] += it.cost;
-        (it.kind == 0 ? wq[w] : wd[w]).push_back(it.kind == 0 ? &sq[it.idx] : &sd[it.idx]);
+        if (!qrec[k].empty()) {
+            PlanTree t{0, k, qrec[k], {}, 0};
+            build_tree(t, qrec[k], JS_LQ, npq, quad_partial_rec, nr);
+            trees.push_back(std::move(t));
+        }
+    for (auto &kv : drec) {
+        PlanTree t{1, kv.first, kv.second, {}, 0};
+        build_tree(t, kv.second, JS_LD, npd, d_partial_rec, nd);
+        trees.push_back(std::move(t));
     }
-    // emit
-    h.jp_prog.assign(4 * JS_WAVES, 0);
-    size_t words = 0;
-    std::vector<size_t> qoff(JS_WAVES), doff(JS_WAVES);
-    for (int w = 0; w < JS_WAVES; ++w) {
-        int nq = 0, ndr = 0;
-        for (const Shelf *s : wq[w]) nq += s->R;
-        for (const Shelf *s : wd[w]) ndr += s->R;
-        qoff[w] = words;
-        words += (size_t)nq * 512;
-        doff[w] = words;
-        words += (size_t)ndr * 128;
-        h.jp_prog[4 * w + 0] = nq;
-        h.jp_prog[4 * w + 1] = ndr;
-        h.jp_prog[4 * w + 2] = (int)qoff[w];
-        h.jp_prog[4 * w + 3] = (int)doff[w];
-    }
-    h.jp_recs.assign(words ? words : 4, 0u);
-    for (int w = 0; w < JS_WAVES; ++w) {
-        emit_rounds(tq, wq[w], JS_LQ, 8, (unsigned)a_trash | 0x8000u, 32u * (unsigned)nr, h.jp_recs, qoff[w]);
-        emit_rounds(td, wd[w], JS_LD, 2, (unsigned)a_trash | 0x8000u, 0u, h.jp_recs, doff[w]);
-    }
-    // self-check: replay the rounds and compare every target's records with the stoichiometry
-    {
-        std::map<int, std::vector<unsigned>> got_q, got_d;
-        auto field = [&](size_t round_base, int words_pl, int l, int x) {
-            const int w = x / 2;
-            const size_t idx = words_pl == 8 ? round_base + (w / 4) * 256 + (size_t)l * 4 + (w % 4)
-                                             : round_base + (size_t)l * 2 + w;
-            return (h.jp_recs[idx] >> (16 * (x & 1))) & 0xffffu;
-        };
-        const unsigned q_lim = 32u * (unsigned)(nr + 1), d_lim = 8u * (unsigned)(1 + 2 * nd);
-        for (int w = 0; w < JS_WAVES; ++w)
-            for (int kind = 0; kind < 2; ++kind) {
-                const int L = kind == 0 ? JS_LQ : JS_LD, wpl = kind == 0 ? 8 : 2;
-                const int nrnd = h.jp_prog[4 * w + kind];
-                const size_t base = kind == 0 ? qoff[w] : doff[w];
-                for (int l = 0; l < 64; ++l) {
-                    std::vector<unsigned> cur;
-                    for (int r = 0; r < nrnd; ++r) {
-                        const size_t rb = base + (size_t)r * (wpl == 8 ? 512 : 128);
-                        const unsigned tw = field(rb, wpl, l, 0);
-                        for (int x = 1; x <= L; ++x) {
-                            const unsigned rec = field(rb, wpl, l, x);
-                            if (kind == 0 ? (rec & 0xffe0u) >= q_lim : (rec >= d_lim || (rec & 7u) != 0))
-                                return no("plan self-check: record out of range");
-                            const bool zero = kind == 0 ? (rec & 7u) == 0 : rec == 0;
-                            if (!zero) cur.push_back(rec);
-                        }
-                        if (tw & 0x8000u) {
-                            const int a = (int)(tw & 0x7fffu);
-                            if (a + (kind == 0 ? 4 : 1) > a_trash + 4) return no("plan self-check: target out of range");
-                            if (kind == 0 && (a % 4) != 0) return no("plan self-check: misaligned quad target");
-                            if (a != a_trash) {
-                                auto &dst = kind == 0 ? got_q : got_d;
-                                if (dst.count(a)) return no("plan self-check: target written twice");
-                                dst[a] = cur;
-                            } else if (!cur.empty()) {
-                                return no("plan self-check: records on the trash target");
-                            }
-                            cur.clear();
-                        }
-                    }
-                    if (!cur.empty()) return no("plan self-check: unterminated target");
-                }
+    if (8 * (1 + nd + npd) > 0xfff8) return no("too many derivative values for 16-bit records");
+    if (32 * (nr + 1 + npq) > 0xffff) return no("too many reactions for 16-bit quad records");
+    // deal the trees to the wavefronts: per wave and level, task counts; rounds = sum of
+    // ceil(tasks / 64) over levels; cost = CQ quad rounds + CD d rounds
+    constexpr int CQ = 3, CD = 1, MAXLV = 8;
+    std::vector<std::array<std::array<int, MAXLV>, 2>> cnt(JS_WAVES);
+    for (auto &c : cnt)
+        for (auto &l : c) l.fill(0);
+    auto rounds_of = [&](const std::array<int, MAXLV> &lv) {
+        int r = 0;
+        for (int x : lv) r += (x + 63) / 64;
+        return r;
+    };
+    std::vector<int> order(trees.size());
+    for (size_t t = 0; t < trees.size(); ++t) order[t] = (int)t;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (trees[a].kind != trees[b].kind) return trees[a].kind < trees[b].kind;
+        if (trees[a].depth != trees[b].depth) return trees[a].depth > trees[b].depth;
+        return trees[a].tasks.size() > trees[b].tasks.size();
+    });
+    // choice per tree: the smallest resulting makespan, then the smallest cost increase
+    // (deep trees cluster on the wavefronts that already run their levels), then the
+    // wavefront with the fewest tasks
+    std::vector<int> wave_of(trees.size(), -1), wtasks(JS_WAVES, 0), wcost(JS_WAVES, 0);
+    for (int t : order) {
+        const PlanTree &tr = trees[t];
+        if (tr.depth > MAXLV) return no("reduction tree too deep");
+        const int span = *std::max_element(wcost.begin(), wcost.end());
+        int best = -1, best_span = 0, best_inc = 0;
+        for (int w = 0; w < JS_WAVES; ++w) {
+            auto lv = cnt[w][tr.kind];
+            for (const auto &tk : tr.tasks) lv[tk.level]++;
+            const int rq = tr.kind == 0 ? rounds_of(lv) : rounds_of(cnt[w][0]);
+            const int rd = tr.kind == 1 ? rounds_of(lv) : rounds_of(cnt[w][1]);
+            if (rq > JS_QMAX || rd > JS_DMAX) continue;
+            const int cost = CQ * rq + CD * rd;
+            const int nspan = std::max(span, cost), inc = cost - wcost[w];
+            if (best < 0 || nspan < best_span || (nspan == best_span && inc < best_inc) ||
+                (nspan == best_span && inc == best_inc && wtasks[w] < wtasks[best])) {
+                best = w;
+                best_span = nspan;
+                best_inc = inc;
             }
-        auto same = [](std::vector<unsigned> a, std::vector<unsigned> b) {
-            std::sort(a.begin(), a.end());
-            std::sort(b.begin(), b.end());
-            return a == b;
-        };
-        if (got_q.size() != tq.size() || got_d.size() != td.size()) return no("plan self-check: target count");
-        for (const auto &g : tq)
-            if (!got_q.count(g.aidx) || !same(got_q[g.aidx], g.recs)) return no("plan self-check: quad records");
-        for (const auto &g : td)
-            if (!got_d.count(g.aidx) || !same(got_d[g.aidx], g.recs)) return no("plan self-check: d records");
+        }
+        if (best < 0) return no("gather rounds exceed the per-wavefront register budget");
+        wave_of[t] = best;
+        for (const auto &tk : tr.tasks) cnt[best][tr.kind][tk.level]++;
+        wtasks[best] += (int)tr.tasks.size();
+        wcost[best] = CQ * rounds_of(cnt[best][0]) + CD * rounds_of(cnt[best][1]);
     }
-    // LDS layout (bytes; A is sized for double accumulators in both precisions)
-    auto up16 = [](int b) { return (b + 15) / 16 * 16; };
-    int off = up16(8 * (1 + 2 * nd));
-    h.jp_off_rdq = off;  off += up16(32 * (nr + 1));
-    h.jp_off_a = off;    off += up16(8 * (ns * sr + 4));
-    h.jp_off_sp = off;   off += up16(32 * (ns + 1));
-    h.jp_off_row = off;  off += up16(16 * ns);
-    h.jp_off_p = off;    off += up16(8 * JS_PWAVES * sr);
-    h.jp_off_sc = off;   off += up16(8 * 16);
+    // LDS layout (bytes)
+    auto up = [](int b, int a) { return (b + a - 1) / a * a; };
+    const int n_troe = (int)(h.troe.size() / 8);
+    int off = up(8 * (1 + nd + npd), 32);
+    h.jp_off_rdq = off;  off = up(off + 32 * (nr + 1 + npq), 32);
+    h.jp_off_a = off;    off = up(off + 8 * (ns * sr + 4), 16);
+    h.jp_off_sp = off;   off = up(off + 2 * 32 * (ns + 1), 16);
+    h.jp_off_row = off;  off = up(off + 16 * ns, 16);
+    h.jp_off_p = off;    off = up(off + 8 * JS_PWAVES * sr, 16);
+    h.jp_off_sc = off;   off = up(off + 8 * 32, 16);
+    h.jp_off_tp = off;   off = up(off + 8 * JS_TP * n_troe, 16);
+    h.jp_off_tq = off;   off = up(off + 2 * 8 * JS_TQ * n_troe, 16);
+    h.jp_off_ns = off;   off = up(off + 8 * 16 * ns, 16);
+    h.jp_off_iw = off;   off = up(off + 8 * ns, 16);
+    h.jp_off_ex = off;   off = up(off + 12 * (int)h.eff_sp.size(), 16);
+    h.jp_nm = (int)h.jp_mrx.size() / 2;
+    h.jp_off_mx = off;   off = up(off + 8 * h.jp_nm, 16);
+    h.jp_off_mq = off;   off = up(off + 2 * 16 * h.jp_nm, 16);
     h.jp_lds = off;
     if (off > JS_MAX_LDS) return no("LDS footprint " + std::to_string(off) + " B above the limit");
+    const int a_trash = ns * sr;
+    auto dest_word = [&](const PlanTree &tr, const PlanTask &tk) -> unsigned {
+        if (tr.kind == 0)
+            return tk.partial ? (unsigned)((h.jp_off_rdq + 32 * (nr + 1 + tk.dest)) / 16)
+                              : (unsigned)((h.jp_off_a + 8 * tk.dest * sr) / 16);
+        return tk.partial ? (unsigned)(1 + nd + tk.dest) : (unsigned)(h.jp_off_a / 8 + tk.dest);
+    };
+    const unsigned trash_q = (unsigned)((h.jp_off_a + 8 * a_trash) / 16), trash_d = (unsigned)(h.jp_off_a / 8 + a_trash);
+    if (trash_d > 0xffff) return no("accumulator matrix beyond 16-bit destination words");
+    // emit: per wave, quad rounds then d rounds, each kind level by level
+    h.jp_prog.assign(8 * JS_WAVES, 0);
+    struct Slot { int tree, task; };
+    std::vector<std::array<std::vector<std::vector<Slot>>, 2>> rounds(JS_WAVES);   // [w][kind][round] -> lanes
+    std::vector<std::array<unsigned, 2>> syncm(JS_WAVES, {0u, 0u});
+    for (int w = 0; w < JS_WAVES; ++w)
+        for (int kind = 0; kind < 2; ++kind)
+            for (int lv = 0; lv < MAXLV; ++lv) {
+                std::vector<Slot> tasks;
+                for (size_t t = 0; t < trees.size(); ++t)
+                    if (wave_of[t] == w && trees[t].kind == kind)
+                        for (size_t q = 0; q < trees[t].tasks.size(); ++q)
+                            if (trees[t].tasks[q].level == lv) tasks.push_back({(int)t, (int)q});
+                for (size_t c = 0; c < tasks.size(); c += 64) {
+                    if (c == 0 && lv > 0) syncm[w][kind] |= 1u << rounds[w][kind].size();
+                    rounds[w][kind].emplace_back(tasks.begin() + c, tasks.begin() + std::min(c + 64, tasks.size()));
+                }
+            }
+    size_t words = 0;
+    std::vector<std::array<size_t, 2>> base(JS_WAVES);
+    for (int w = 0; w < JS_WAVES; ++w) {
+        base[w][0] = words;
+        words += rounds[w][0].size() * 256;
+        base[w][1] = words;
+        words += rounds[w][1].size() * 128;
+        h.jp_prog[8 * w + 0] = (int)rounds[w][0].size();
+        h.jp_prog[8 * w + 1] = (int)rounds[w][1].size();
+        h.jp_prog[8 * w + 2] = (int)base[w][0];
+        h.jp_prog[8 * w + 3] = (int)base[w][1];
+        h.jp_prog[8 * w + 4] = (int)syncm[w][0];
+        h.jp_prog[8 * w + 5] = (int)syncm[w][1];
+    }
+    h.jp_recs.assign(words ? words : 4, 0u);
+    const unsigned zero_q = 32u * (unsigned)nr, zero_d = 0u;
+    for (int w = 0; w < JS_WAVES; ++w)
+        for (int kind = 0; kind < 2; ++kind) {
+            const int L = kind == 0 ? JS_LQ : JS_LD, wpl = kind == 0 ? 4 : 2, rsz = 64 * wpl;
+            for (size_t r = 0; r < rounds[w][kind].size(); ++r)
+                for (int l = 0; l < 64; ++l) {
+                    std::vector<unsigned> f(1 + L, kind == 0 ? zero_q : zero_d);
+                    if (l < (int)rounds[w][kind][r].size()) {
+                        const Slot sl = rounds[w][kind][r][l];
+                        const PlanTask &tk = trees[sl.tree].tasks[sl.task];
+                        f[0] = dest_word(trees[sl.tree], tk);
+                        for (size_t x = 0; x < tk.recs.size(); ++x) f[1 + x] = tk.recs[x];
+                    } else {
+                        f[0] = kind == 0 ? trash_q : trash_d;
+                    }
+                    for (int x = 0; x <= L; ++x)
+                        h.jp_recs[base[w][kind] + r * rsz + (size_t)l * wpl + x / 2] |= (f[x] & 0xffffu) << (16 * (x & 1));
+                }
+        }
+    // self-check: replay the rounds symbolically (LDS word -> multiset of leaf records with
+    // coefficients) and compare every final entry with its target's leaves
+    {
+        std::map<unsigned, std::map<unsigned, int>> slot_val;             // byte address -> leaf -> coef
+        std::map<unsigned, std::pair<int, int>> written;                  // byte address -> (wave, round)
+        std::map<unsigned, std::map<unsigned, int>> final_q, final_d;     // dest word -> value
+        const unsigned q_leaf_lim = 32u * (unsigned)nr, d_leaf_lim = 8u * (unsigned)(1 + nd);
+        for (int w = 0; w < JS_WAVES; ++w)
+            for (int kind = 0; kind < 2; ++kind) {
+                const int L = kind == 0 ? JS_LQ : JS_LD, wpl = kind == 0 ? 4 : 2, rsz = 64 * wpl;
+                int last_sync = -1;
+                for (size_t r = 0; r < rounds[w][kind].size(); ++r) {
+                    if (syncm[w][kind] >> r & 1u) last_sync = (int)r;
+                    std::vector<std::pair<unsigned, std::map<unsigned, int>>> stores;
+                    for (int l = 0; l < 64; ++l) {
+                        auto field = [&](int x) {
+                            return (h.jp_recs[base[w][kind] + r * rsz + (size_t)l * wpl + x / 2] >> (16 * (x & 1))) & 0xffffu;
+                        };
+                        std::map<unsigned, int> v;
+                        for (int x = 1; x <= L; ++x) {
+                            const unsigned rec = field(x);
+                            const unsigned amask = kind == 0 ? 0xffe0u : 0xfff8u;
+                            const unsigned addr = (kind == 0 ? (unsigned)h.jp_off_rdq : 0u) + (rec & amask);
+                            const int coef = ((int)(rec & 7u) ^ 4) - 4;
+                            if (kind == 0 && (rec & 0x18u)) return no("plan self-check: bad quad record");
+                            const bool leaf = kind == 0 ? (rec & amask) <= q_leaf_lim : (rec & amask) < d_leaf_lim;
+                            if (coef == 0) continue;
+                            if (kind == 1 && (rec & amask) == 0) return no("plan self-check: record on the zero entry");
+                            if (leaf) {
+                                v[rec & amask] += coef;
+                            } else {
+                                auto it = written.find(addr);
+                                if (it == written.end()) return no("plan self-check: partial read before written");
+                                if (it->second.first != w || it->second.second >= last_sync)
+                                    return no("plan self-check: partial read without a sync after its write");
+                                for (const auto &lv : slot_val[addr]) v[lv.first] += coef * lv.second;
+                            }
+                        }
+                        const unsigned dw = field(0);
+                        const unsigned daddr = kind == 0 ? 16u * dw : 8u * dw;
+                        stores.push_back({daddr, v});
+                    }
+                    for (auto &st : stores) {
+                        const bool is_final = st.first >= (unsigned)h.jp_off_a;
+                        const bool is_trash = st.first == (kind == 0 ? 16u * trash_q : 8u * trash_d);
+                        if (is_trash) {
+                            for (const auto &lv : st.second)
+                                if (lv.second) return no("plan self-check: records on the trash target");
+                            continue;
+                        }
+                        auto &fin = kind == 0 ? final_q : final_d;
+                        if (is_final) {
+                            if (fin.count(st.first)) return no("plan self-check: final entry written twice");
+                            fin[st.first] = st.second;
+                        } else {
+                            if (written.count(st.first)) return no("plan self-check: partial written twice");
+                            written[st.first] = {w, (int)r};
+                            slot_val[st.first] = st.second;
+                        }
+                    }
+                }
+            }
+        size_t nq_targets = 0, nd_targets = 0;
+        for (const auto &tr : trees) {
+            std::map<unsigned, int> want;
+            for (unsigned rec : tr.leaves) want[rec & (tr.kind == 0 ? 0xffe0u : 0xfff8u)] += ((int)(rec & 7u) ^ 4) - 4;
+            for (auto it = want.begin(); it != want.end();) it = it->second == 0 ? want.erase(it) : std::next(it);
+            const unsigned daddr = tr.kind == 0 ? (unsigned)(h.jp_off_a + 8 * tr.final_dest * sr)
+                                                : (unsigned)(h.jp_off_a + 8 * tr.final_dest);
+            auto &fin = tr.kind == 0 ? final_q : final_d;
+            auto it = fin.find(daddr);
+            if (it == fin.end()) return no("plan self-check: target never written");
+            std::map<unsigned, int> got = it->second;
+            for (auto g = got.begin(); g != got.end();) g = g->second == 0 ? got.erase(g) : std::next(g);
+            if (got != want) return no("plan self-check: target sum differs from the stoichiometry");
+            (tr.kind == 0 ? nq_targets : nd_targets)++;
+        }
+        if (nq_targets != final_q.size() || nd_targets != final_d.size()) return no("plan self-check: stray final entries");
+    }
     h.jp_ok = 1;
     h.jp_why.clear();
 }
@@ -598,7 +688,7 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
            oLam = P.add(h.lam_fit), oW4 = P.add(w4), oIw4 = P.add(iw4), oWc = P.add(wc), oDif = P.add(dif),
            oPjk = P.add(pjk), oLnA = P.add(h.lnA), oB = P.add(h.b), oTh = P.add(h.theta), oInfo = P.add(h.info),
            oDs = P.add(h.dnu_sum), oRi = P.add(h.ri), oTroe = P.add(h.troe), oEs = P.add(h.eff_sp),
-           oEm = P.add(h.eff_m1), oJt = P.add(h.jp_thr), oJr = P.add(h.jp_recs), oJp = P.add(h.jp_prog);
+           oEm = P.add(h.eff_m1), oJt = P.add(h.jp_thr), oJr = P.add(h.jp_recs), oJp = P.add(h.jp_prog), oJm = P.add(h.jp_mrx);
     int prev = -1;
     if (hipGetDevice(&prev) != hipSuccess) return fail(CRF_E_DEVICE, "hipGetDevice failed (no HIP device?)");
     if (hipSetDevice(device) != hipSuccess) return fail(CRF_E_DEVICE, "hipSetDevice(" + std::to_string(device) + ") failed");
@@ -621,9 +711,12 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
     m.ri = (const RxnInts *)at(oRi); m.troe = (const double *)at(oTroe); m.eff_sp = (const int *)at(oEs);
     m.eff_m1 = (const double *)at(oEm);
     m.jp_thr = (const int *)at(oJt); m.jp_recs = (const unsigned *)at(oJr); m.jp_prog = (const int *)at(oJp);
+    m.jp_mrx = (const int *)at(oJm); m.jp_nm = h.jp_nm; m.jp_off_mx = h.jp_off_mx; m.jp_off_mq = h.jp_off_mq;
     m.jp_ok = h.jp_ok; m.jp_nd = h.jp_nd; m.jp_sr = h.jp_sr; m.jp_lds = h.jp_lds;
     m.jp_off_rdq = h.jp_off_rdq; m.jp_off_a = h.jp_off_a; m.jp_off_sp = h.jp_off_sp;
     m.jp_off_row = h.jp_off_row; m.jp_off_p = h.jp_off_p; m.jp_off_sc = h.jp_off_sc;
+    m.jp_off_tp = h.jp_off_tp; m.jp_off_ex = h.jp_off_ex; m.jp_off_tq = h.jp_off_tq;
+    m.jp_off_ns = h.jp_off_ns; m.jp_off_iw = h.jp_off_iw;
     mm->dev_buf = d;
     mm->device = device;
     return CRF_OK;
