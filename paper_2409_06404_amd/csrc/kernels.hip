@@ -35,10 +35,29 @@ constexpr double LN10 = 2.302585092994045684;
 constexpr double INV_LN10 = 0.4342944819032518277;
 
 // ------------------------------------------------------------------ helpers
+// v from the lane `ctrl` selects (DPP), 0 where the source lane is outside the pattern or
+// the lane is outside the row/bank masks; a double moves as two 32-bit halves.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes, returned in every lane.  Data-parallel prefix steps through
+// DPP (row shifts by 1, 2, 4, 8, then the row broadcasts of lanes 15 and 31), which stay
+// in the VALU; lane 63 ends with the total, read back as a uniform value.  The order of
+// additions is fixed, so the result is reproducible.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-    return v;   // butterfly: every lane holds the same (commutative) sum
+    v += dpp_f64<0x111, 0xf>(v);   // row_shr:1
+    v += dpp_f64<0x112, 0xf>(v);   // row_shr:2
+    v += dpp_f64<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_f64<0x118, 0xf>(v);   // row_shr:8
+    v += dpp_f64<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
 }
 
 // Makes LDS writes of all lanes of this wave visible to all its lanes.
@@ -95,6 +114,17 @@ __device__ inline double exp_split(double x) {
     const float e = __expf((float)f);
     return ldexp((double)e, (int)fmax(fmin(k, 2000.0), -2000.0));
 }
+
+// LDS access by byte offset from the start of the workgroup's LDS allocation (the
+// kernels that use these declare no static LDS, so dynamic LDS starts at offset 0);
+// saves the base-address add the compiler emits for the dynamic-LDS symbol.
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) double lds_f64;
+typedef __attribute__((address_space(3))) f64x2 lds_f64x2;
+__device__ inline double lds_ld(unsigned off) { return *(const lds_f64 *)(uintptr_t)off; }
+__device__ inline f64x2 lds_ld2(unsigned off) { return *(const lds_f64x2 *)(uintptr_t)off; }
+__device__ inline void lds_st(unsigned off, double v) { *(lds_f64 *)(uintptr_t)off = v; }
+__device__ inline void lds_st2(unsigned off, f64x2 v) { *(lds_f64x2 *)(uintptr_t)off = v; }
 
 struct PointState {
     double T, lnT, invT, lnp0RT, rho, Wbar, Ctot, p;
@@ -917,36 +947,41 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
             jac_seg_reaction<MIXED>(r, sp03, sp45, dpos, xpos, n_exc, exc0, troe, dnu, lnA, bb, th, SP, SC,
                                     TQ0 + buf * JS_TQ * n_troe, MQ0 + buf * 2 * n_m, EXm, RDd, RDq);
         const double Tt = SC[0], rho = SC[2], wbar = SC[3], invT = SC[6];
-        // this wavefront's gather records (the same for every point; L1/L2 resident)
+        // this wavefront's gather records (the same for every point; L1/L2 resident); the
+        // round counts pass through an empty asm each point so that the compiler does not
+        // hoist the per-round tests out of the point loop (their masks would be spilled)
+        int nq_i = nq, ndr_i = ndr;
+        unsigned qs_i = qsync, ds_i = dsync;
+        asm volatile("" : "+s"(nq_i), "+s"(ndr_i), "+s"(qs_i), "+s"(ds_i));
         uint4 qr[JS_QMAX];
         uint2 dr[JS_DMAX];
 #pragma unroll
-        for (int q = 0; q < JS_QMAX; ++q) qr[q] = q < nq ? qrec[q * 64 + lane] : uint4{0u, 0u, 0u, 0u};
+        for (int q = 0; q < JS_QMAX; ++q) qr[q] = q < nq_i ? qrec[q * 64 + lane] : uint4{0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int q = 0; q < JS_DMAX; ++q) dr[q] = q < ndr ? drec[q * 64 + lane] : uint2{0u, 0u};
+        for (int q = 0; q < JS_DMAX; ++q) dr[q] = q < ndr_i ? drec[q * 64 + lane] : uint2{0u, 0u};
         __syncthreads();
         // ---- C
-        const unsigned char *RQ = lds_b + m.jp_off_rdq;
+        const unsigned rq = (unsigned)m.jp_off_rdq;
 #pragma unroll
         for (int q = 0; q < JS_QMAX; ++q) {
-            if (q < nq) {
-                if (qsync >> q & 1u) wave_lds_sync();
+            if (q < nq_i) {
+                if (qs_i >> q & 1u) wave_lds_sync();
                 const unsigned u[4] = {qr[q].x, qr[q].y, qr[q].z, qr[q].w};
                 double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
                 for (int j = 1; j <= JS_LQ; ++j) {
                     const unsigned rec = (u[j >> 1] >> (16 * (j & 1))) & 0xffffu;
                     const double cf = (double)(int)__builtin_amdgcn_sbfe((int)rec, 0, 3);   // signed 3-bit field
-                    const double2 *v = (const double2 *)(RQ + (rec & 0xffe0u));
-                    const double2 x = v[0], y = v[1];
+                    const unsigned a = rq + (rec & 0xffe0u);
+                    const f64x2 x = lds_ld2(a), y = lds_ld2(a + 16u);
                     a0 = fma(cf, x.x, a0);
                     a1 = fma(cf, x.y, a1);
                     a2 = fma(cf, y.x, a2);
                     a3 = fma(cf, y.y, a3);
                 }
-                double2 *dst = (double2 *)(lds_b + 16u * (u[0] & 0xffffu));
-                dst[0] = double2{a0, a1};
-                dst[1] = double2{a2, a3};
+                const unsigned d = 16u * (u[0] & 0xffffu);
+                lds_st2(d, f64x2{a0, a1});
+                lds_st2(d + 16u, f64x2{a2, a3});
             }
         }
         // d rounds, software-pipelined: round q + 1's values are read before round q's store
@@ -954,24 +989,24 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
         {
             double v0 = 0.0, v1 = 0.0, v2 = 0.0;
             auto rd = [&](const uint2 w) {
-                v0 = *(const double *)(lds_b + ((w.x >> 16) & 0xfff8u));
-                v1 = *(const double *)(lds_b + (w.y & 0xfff8u));
-                v2 = *(const double *)(lds_b + ((w.y >> 16) & 0xfff8u));
+                v0 = lds_ld((w.x >> 16) & 0xfff8u);
+                v1 = lds_ld(w.y & 0xfff8u);
+                v2 = lds_ld((w.y >> 16) & 0xfff8u);
             };
             auto cf = [](unsigned rec) { return (double)(int)__builtin_amdgcn_sbfe((int)rec, 0, 3); };
-            if (ndr > 0) {
-                if (dsync & 1u) wave_lds_sync();
+            if (ndr_i > 0) {
+                if (ds_i & 1u) wave_lds_sync();
                 rd(dr[0]);
             }
 #pragma unroll
             for (int q = 0; q < JS_DMAX; ++q) {
-                if (q < ndr) {
+                if (q < ndr_i) {
                     const uint2 w = dr[q];
                     const double acc = fma(cf(w.y >> 16), v2, fma(cf(w.y), v1, cf(w.x >> 16) * v0));
-                    const bool more = q + 1 < ndr && q + 1 < JS_DMAX;
-                    const bool sync_next = more && (dsync >> (q + 1) & 1u);
+                    const bool more = q + 1 < ndr_i && q + 1 < JS_DMAX;
+                    const bool sync_next = more && (ds_i >> (q + 1) & 1u);
                     if (more && !sync_next) rd(dr[q + 1 < JS_DMAX ? q + 1 : q]);
-                    *(double *)(lds_b + 8u * (w.x & 0xffffu)) = acc;
+                    lds_st(8u * (w.x & 0xffffu), acc);
                     if (sync_next) {
                         wave_lds_sync();
                         rd(dr[q + 1 < JS_DMAX ? q + 1 : q]);
