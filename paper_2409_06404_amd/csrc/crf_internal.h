@@ -58,25 +58,23 @@ struct DevMech {
     const double *eff_m1;     // [n_exc] eps - 1
     // Segmented Jacobian plan (build_jac_plan in mech.cpp); jp_ok == 0 if the mechanism does not fit it
     const int *jp_thr;        // [JS_THREADS] per-thread reaction constants (JsThr)
-    const unsigned *jp_recs;  // gather rounds (quad rounds: uint4 per lane, d rounds: uint2 per lane)
+    const unsigned *jp_recs;  // gather rounds, [JS_WAVES][JS_DMAX][64 lanes] uint2 (build_jac_plan)
     const int *jp_mrx;        // [jp_nm][2]: first efficiency exception, exception count of each [M] slot
-    const int *jp_prog;       // [JS_WAVES][8]: quad rounds, d rounds, quad offset, d offset (32-bit words),
-                              //   quad sync mask, d sync mask (bit r: wave-local LDS sync before round r)
+    const int *jp_prog;       // [JS_WAVES][8]: gather rounds in use, first 32-bit word of the rounds
     int jp_ok, jp_nd, jp_sr, jp_lds;
-    int jp_off_rdq, jp_off_a, jp_off_sp, jp_off_row, jp_off_p, jp_off_sc, jp_off_tp, jp_off_ex;  // LDS bytes
+    int jp_off_a, jp_off_sp, jp_off_row, jp_off_p, jp_off_sc, jp_off_tp, jp_off_ex;  // LDS bytes
     int jp_off_tq, jp_off_ns, jp_off_iw, jp_off_mx, jp_off_mq, jp_nm;
+    int jp_qb;                // first per-reaction (dT, q, d[M], sum) value among the d values
 };
 
 // Segmented Jacobian kernel (k_jac_seg): six wavefronts per workgroup, one reaction per
-// thread, gather rounds of JS_LQ "quad" records (4 accumulators: dq/dT, q, dq/d[M],
-// sum_j C_j dq/dC_j) or JS_LD single-value records per lane; at most JS_QMAX quad and
-// JS_DMAX single-value rounds per wavefront (their records are held in registers).
+// thread, JS_DMAX gather rounds of JS_LD records per lane (streamed through registers,
+// JS_DW rounds ahead).
 constexpr int JS_WAVES = 6;
 constexpr int JS_THREADS = 64 * JS_WAVES;
-constexpr int JS_LQ = 7;
 constexpr int JS_LD = 3;
-constexpr int JS_QMAX = 3;
-constexpr int JS_DMAX = 12;
+constexpr int JS_DMAX = 24;
+constexpr int JS_DW = 8;            // gather rounds whose records are in registers ahead of use
 constexpr int JS_PWAVES = 3;        // wavefronts that form the heat-release row
 constexpr int JS_EWAVES = 4;        // wavefronts that emit the Jacobian
 constexpr int JS_EROWS = 10;        // most Jacobian rows one emitting thread writes
@@ -119,9 +117,9 @@ struct HostMech {
     std::vector<unsigned> jp_recs;
     std::vector<int> jp_prog;
     int jp_ok = 0, jp_nd = 0, jp_sr = 0, jp_lds = 0;
-    int jp_off_rdq = 0, jp_off_a = 0, jp_off_sp = 0, jp_off_row = 0, jp_off_p = 0, jp_off_sc = 0;
+    int jp_off_a = 0, jp_off_sp = 0, jp_off_row = 0, jp_off_p = 0, jp_off_sc = 0;
     int jp_off_tp = 0, jp_off_ex = 0, jp_off_tq = 0, jp_off_ns = 0, jp_off_iw = 0, jp_off_mx = 0, jp_off_mq = 0;
-    int jp_nm = 0;
+    int jp_nm = 0, jp_qb = 0;
     std::vector<int> jp_mrx;
     std::string jp_why;                  // why the plan is absent (for diagnostics)
     int ns() const { return (int)names.size(); }

@@ -646,7 +646,7 @@ template <bool MIXED>
 __device__ inline void jac_seg_reaction(int r, unsigned sp03, unsigned sp45, int dpos, int xpos, int n_exc,
                                         int exc0, int troe, int dnu, double lnA, double bb, double th,
                                         const double *SP, const double *SC, const double *TQ, const double *MQ,
-                                        const double *EXm, double *RDd, double *RDq) {
+                                        const double *EXm, double *RDd, int qb) {
     using Rt = typename std::conditional<MIXED, float, double>::type;
     const int nfm = (sp45 >> 16) & 7, nrm = (sp45 >> 19) & 7, kind = (sp45 >> 22) & 3;
     const double lnT = SC[5], invT = SC[6], lnp0RT = SC[7];
@@ -714,7 +714,7 @@ __device__ inline void jac_seg_reaction(int r, unsigned sp03, unsigned sp45, int
     const double t = fac * (double)dkf_dT * bracket + fr * pr * dlnKc;
     const double mf = kind == RXN_THREEBODY ? kfd * bracket : kind == RXN_TROE ? (double)dkf_dM * bracket : 0.0;
     const double sig = (double)nfm * qf - (double)nrm * qr + mf * M;
-    double2 *qd = (double2 *)(RDq + 4 * r);
+    double2 *qd = (double2 *)(RDd + qb + 4 * r);   // 16-byte aligned (qb even)
     qd[0] = double2{t, qf - qr};
     qd[1] = double2{mf, sig};
     // dq/dC of each molecule slot: the product of the other slots of its side
@@ -813,17 +813,10 @@ __device__ inline void jac_seg_state(int ns, double R, double lnp0R, int wave, i
         const double lnT = log(Tt), invT = 1.0 / Tt;
         if (lane < ns) {
             const double *c16 = NS + 16 * lane;
-            double a[16];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const double2 v = *(const double2 *)(c16 + 2 * q);
-                a[2 * q] = v.x;
-                a[2 * q + 1] = v.y;
-            }
-            const bool lo = Tt <= a[0];
+            const double *a = c16 + (Tt <= c16[0] ? 1 : 8);   // the temperature range's 7 coefficients
             double b[7];
 #pragma unroll
-            for (int q = 0; q < 7; ++q) b[q] = lo ? a[1 + q] : a[8 + q];
+            for (int q = 0; q < 7; ++q) b[q] = a[q];
             const double cp = b[0] + Tt * (b[1] + Tt * (b[2] + Tt * (b[3] + Tt * b[4])));
             const double hh = b[0] + Tt * (b[1] * 0.5 + Tt * (b[2] * (1.0 / 3.0) + Tt * (b[3] * 0.25 + Tt * (b[4] * 0.2)))) +
                               b[5] * invT;
@@ -855,7 +848,6 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
     constexpr int WY = JS_WAVES - 1;        // wavefront that forms the mixture state
     constexpr int WT = JS_PWAVES;           // wavefront that forms the falloff temperature terms
     double *RDd = (double *)lds_b;
-    double *RDq = (double *)(lds_b + m.jp_off_rdq);
     double *A = (double *)(lds_b + m.jp_off_a);
     double *SP0 = (double *)(lds_b + m.jp_off_sp);
     double *ROW = (double *)(lds_b + m.jp_off_row);
@@ -876,7 +868,6 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
     for (int e = tid; e < ns * sr + 4; e += JS_THREADS) A[e] = 0.0;
     if (tid == 0) RDd[0] = 0.0;
     if (tid < 4) {
-        RDq[4 * m.nr + tid] = 0.0;
         SP0[4 * ns + tid] = tid == 0 ? 1.0 : 0.0;
         SP0[4 * (ns + 1) + 4 * ns + tid] = tid == 0 ? 1.0 : 0.0;
     }
@@ -908,10 +899,8 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
     }
     // gather program of this wavefront (uniform)
     const int *prog = m.jp_prog + 8 * wave;
-    const int nq = __builtin_amdgcn_readfirstlane(prog[0]), ndr = __builtin_amdgcn_readfirstlane(prog[1]);
-    const uint4 *qrec = (const uint4 *)(m.jp_recs + __builtin_amdgcn_readfirstlane(prog[2]));
-    const uint2 *drec = (const uint2 *)(m.jp_recs + __builtin_amdgcn_readfirstlane(prog[3]));
-    const unsigned qsync = __builtin_amdgcn_readfirstlane(prog[4]), dsync = __builtin_amdgcn_readfirstlane(prog[5]);
+    const uint2 *drec = (const uint2 *)(m.jp_recs + __builtin_amdgcn_readfirstlane(prog[1]));
+    const int qb = m.jp_qb;
     // emission mapping: a pair of columns (c0, c0 + 1) and a row phase per thread, on
     // wavefronts 0..JS_EWAVES-1 (the falloff and third-body wavefronts, which take longest
     // in the rate phase that follows, and the state wavefronts do not emit)
@@ -919,8 +908,6 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
     const int rphase = JS_EWAVES * WAVE / npair;
     const int pc0 = 2 * (tid % npair), pr0 = tid / npair;
     const bool pon = tid < JS_EWAVES * WAVE && pr0 < rphase;
-    const double iw0 = (pc0 >= 1 && pc0 - 1 < ns) ? m.invW[pc0 - 1] : 0.0;
-    const double iw1 = (pc0 < ns) ? m.invW[pc0] : 0.0;
     // state of the first point into buffer 0; prefetch of the second (indices clamped:
     // a block always has a first point, and a repeat past the end is never used)
     double pf_T = 0.0, pf_p = 0.0, pf_Y = 0.0;
@@ -945,73 +932,37 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
         // ---- B
         if (r >= 0)
             jac_seg_reaction<MIXED>(r, sp03, sp45, dpos, xpos, n_exc, exc0, troe, dnu, lnA, bb, th, SP, SC,
-                                    TQ0 + buf * JS_TQ * n_troe, MQ0 + buf * 2 * n_m, EXm, RDd, RDq);
+                                    TQ0, MQ0, EXm, RDd, qb);
         const double Tt = SC[0], rho = SC[2], wbar = SC[3], invT = SC[6];
-        // this wavefront's gather records (the same for every point; L1/L2 resident); the
-        // round counts pass through an empty asm each point so that the compiler does not
-        // hoist the per-round tests out of the point loop (their masks would be spilled)
-        int nq_i = nq, ndr_i = ndr;
-        unsigned qs_i = qsync, ds_i = dsync;
-        asm volatile("" : "+s"(nq_i), "+s"(ndr_i), "+s"(qs_i), "+s"(ds_i));
-        uint4 qr[JS_QMAX];
+        // this wavefront's gather records (the same for every point; L1/L2 resident); every
+        // wavefront runs JS_DMAX rounds (the plan pads with no-op rounds), so the gather
+        // below is straight-line code
         uint2 dr[JS_DMAX];
 #pragma unroll
-        for (int q = 0; q < JS_QMAX; ++q) qr[q] = q < nq_i ? qrec[q * 64 + lane] : uint4{0u, 0u, 0u, 0u};
-#pragma unroll
-        for (int q = 0; q < JS_DMAX; ++q) dr[q] = q < ndr_i ? drec[q * 64 + lane] : uint2{0u, 0u};
-        __syncthreads();
-        // ---- C
-        const unsigned rq = (unsigned)m.jp_off_rdq;
-#pragma unroll
-        for (int q = 0; q < JS_QMAX; ++q) {
-            if (q < nq_i) {
-                if (qs_i >> q & 1u) wave_lds_sync();
-                const unsigned u[4] = {qr[q].x, qr[q].y, qr[q].z, qr[q].w};
-                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-#pragma unroll
-                for (int j = 1; j <= JS_LQ; ++j) {
-                    const unsigned rec = (u[j >> 1] >> (16 * (j & 1))) & 0xffffu;
-                    const double cf = (double)(int)__builtin_amdgcn_sbfe((int)rec, 0, 3);   // signed 3-bit field
-                    const unsigned a = rq + (rec & 0xffe0u);
-                    const f64x2 x = lds_ld2(a), y = lds_ld2(a + 16u);
-                    a0 = fma(cf, x.x, a0);
-                    a1 = fma(cf, x.y, a1);
-                    a2 = fma(cf, y.x, a2);
-                    a3 = fma(cf, y.y, a3);
-                }
-                const unsigned d = 16u * (u[0] & 0xffffu);
-                lds_st2(d, f64x2{a0, a1});
-                lds_st2(d + 16u, f64x2{a2, a3});
-            }
-        }
-        // d rounds, software-pipelined: round q + 1's values are read before round q's store
-        // unless a sync separates them (then round q + 1 reads what round q may write)
+        for (int q = 0; q < JS_DW; ++q) dr[q] = drec[q * 64 + lane];   // the first window; the
+        __syncthreads();                                                 // rest streams in below
+        // ---- C: software-pipelined without branches: round q + 1's values are read before
+        // round q's store; the plan puts an empty round between levels, so a level's reads
+        // follow the previous level's stores in program order (LDS executes a wavefront's
+        // operations in order)
         {
-            double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-            auto rd = [&](const uint2 w) {
-                v0 = lds_ld((w.x >> 16) & 0xfff8u);
-                v1 = lds_ld(w.y & 0xfff8u);
-                v2 = lds_ld((w.y >> 16) & 0xfff8u);
-            };
             auto cf = [](unsigned rec) { return (double)(int)__builtin_amdgcn_sbfe((int)rec, 0, 3); };
-            if (ndr_i > 0) {
-                if (ds_i & 1u) wave_lds_sync();
-                rd(dr[0]);
-            }
+            double v0 = lds_ld((dr[0].x >> 16) & 0xfff8u);
+            double v1 = lds_ld(dr[0].y & 0xfff8u);
+            double v2 = lds_ld((dr[0].y >> 16) & 0xfff8u);
 #pragma unroll
             for (int q = 0; q < JS_DMAX; ++q) {
-                if (q < ndr_i) {
-                    const uint2 w = dr[q];
-                    const double acc = fma(cf(w.y >> 16), v2, fma(cf(w.y), v1, cf(w.x >> 16) * v0));
-                    const bool more = q + 1 < ndr_i && q + 1 < JS_DMAX;
-                    const bool sync_next = more && (ds_i >> (q + 1) & 1u);
-                    if (more && !sync_next) rd(dr[q + 1 < JS_DMAX ? q + 1 : q]);
-                    lds_st(8u * (w.x & 0xffffu), acc);
-                    if (sync_next) {
-                        wave_lds_sync();
-                        rd(dr[q + 1 < JS_DMAX ? q + 1 : q]);
-                    }
+                if (q + JS_DW < JS_DMAX) dr[q + JS_DW < JS_DMAX ? q + JS_DW : q] = drec[(q + JS_DW) * 64 + lane];
+                const uint2 w = dr[q];
+                const double acc = fma(cf(w.y >> 16), v2, fma(cf(w.y), v1, cf(w.x >> 16) * v0));
+                if (q + 1 < JS_DMAX) {
+                    const uint2 wn = dr[q + 1 < JS_DMAX ? q + 1 : q];
+                    v0 = lds_ld((wn.x >> 16) & 0xfff8u);
+                    v1 = lds_ld(wn.y & 0xfff8u);
+                    v2 = lds_ld((wn.y >> 16) & 0xfff8u);
                 }
+                lds_st(8u * (w.x & 0xffffu), acc);
+                __builtin_amdgcn_sched_barrier(0);   // keeps the record stream JS_DW rounds ahead
             }
         }
         __syncthreads();
@@ -1039,12 +990,12 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
             }
             const double cw = wave_sum(cwp) * m.R;
             if (lane == 0) SC[8] = cw;
-            jac_seg_troe_fc<MIXED>(lane, n_troe, pf_T, TP, TQ0 + (buf ^ 1) * JS_TQ * n_troe);
+            jac_seg_troe_fc<MIXED>(lane, n_troe, pf_T, TP, TQ0);
         } else {
             // state of point i + gridDim.x (past the end: a repeat of the last point, unused)
             double *SPn = SP0 + (buf ^ 1) * 4 * (ns + 1), *SCn = SC0 + (buf ^ 1) * 16;
             jac_seg_state<MIXED>(ns, m.R, lnp0R, wave, WY, lane, pf_T, pf_p, pf_Y, NS, IW, MX, n_m, EXm, EXs,
-                                 n_troe, TP, SPn, SCn, MQ0 + (buf ^ 1) * 2 * n_m, TQ0 + (buf ^ 1) * JS_TQ * n_troe);
+                                 n_troe, TP, SPn, SCn, MQ0, TQ0);
         }
         {   // prefetch of point i + 2 gridDim.x, in straight-line code on every wavefront
             const int64_t i2 = min(i + 2 * (int64_t)gridDim.x, n - 1);
@@ -1056,49 +1007,43 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
         // ---- E
         Out *Jp = J + (size_t)i * n1 * n1;
         if (pon) {
-            const double cw = SC[8];
+            auto emit = [&](int row, double a0, double a1, double al, double jt) {
+                const double iw0 = pc0 >= 1 ? IW[pc0 - 1] : 0.0, iw1 = pc0 < ns ? IW[pc0] : 0.0;
+                const Out v0 = (Out)(pc0 == 0 ? jt : (rho * a0 + al) * iw0);
+                const Out v1 = (Out)((rho * a1 + al) * iw1);
+                Out *dst = Jp + row * n1 + pc0;
+                if (pc0 + 1 < n1) {
+                    if ((((uintptr_t)dst) & (2 * sizeof(Out) - 1)) == 0) {
+                        typedef Out Out2 __attribute__((ext_vector_type(2)));
+                        *(Out2 *)dst = Out2{v0, v1};
+                    } else {
+                        dst[0] = v0;
+                        dst[1] = v1;
+                    }
+                } else {
+                    dst[0] = v0;
+                }
+            };
+            if (pr0 == 0) {   // the heat-release row: sum of the partial rows
+                double t0 = 0.0, tau0 = 0.0, R0 = 0.0, a0 = 0.0, a1 = 0.0;
+#pragma unroll 1
+                for (int w = 0; w < JS_PWAVES; ++w) {
+                    const double *Pw = P + w * sr;
+                    t0 += Pw[0];
+                    tau0 += Pw[2];
+                    R0 += Pw[3];
+                    a0 += Pw[4 + pc0];
+                    if (pc0 + 1 < n1) a1 += Pw[5 + pc0];
+                }
+                emit(0, a0, a1, rho * tau0 - wbar * R0, t0 - SC[8] - R0 * invT);
+            }
 #pragma unroll 2
             for (int q = 0; q < JS_EROWS; ++q) {
                 const int row = pr0 + q * rphase;
-                if (row < n1) {
-                    double a0, a1, al, jt;
-                    if (row == 0) {
-                        double t0 = 0.0, tau0 = 0.0, R0 = 0.0;
-                        a0 = 0.0;
-                        a1 = 0.0;
-#pragma unroll
-                        for (int w = 0; w < JS_PWAVES; ++w) {
-                            const double *Pw = P + w * sr;
-                            t0 += Pw[0];
-                            tau0 += Pw[2];
-                            R0 += Pw[3];
-                            a0 += Pw[4 + pc0];
-                            if (pc0 + 1 < n1) a1 += Pw[5 + pc0];
-                        }
-                        al = rho * tau0 - wbar * R0;
-                        jt = t0 - cw - R0 * invT;
-                    } else {
-                        const double2 av = *(const double2 *)(A + (row - 1) * sr + 4 + pc0);   // 16-byte aligned
-                        a0 = av.x;
-                        a1 = av.y;
-                        const double2 rw = *(const double2 *)(ROW + 2 * (row - 1));
-                        al = rw.x;
-                        jt = rw.y;
-                    }
-                    const Out v0 = (Out)(pc0 == 0 ? jt : (rho * a0 + al) * iw0);
-                    const Out v1 = (Out)((rho * a1 + al) * iw1);
-                    Out *dst = Jp + row * n1 + pc0;
-                    if (pc0 + 1 < n1) {
-                        if ((((uintptr_t)dst) & (2 * sizeof(Out) - 1)) == 0) {
-                            typedef Out Out2 __attribute__((ext_vector_type(2)));
-                            *(Out2 *)dst = Out2{v0, v1};
-                        } else {
-                            dst[0] = v0;
-                            dst[1] = v1;
-                        }
-                    } else {
-                        dst[0] = v0;
-                    }
+                if (row >= 1 && row < n1) {
+                    const f64x2 av = *(const f64x2 *)(A + (row - 1) * sr + 4 + pc0);   // 16-byte aligned
+                    const f64x2 rw = *(const f64x2 *)(ROW + 2 * (row - 1));
+                    emit(row, av.x, av.y, rw.x, rw.y);
                 }
             }
         }

@@ -240,37 +240,36 @@ crf_status parse_mechanism(const char *path, HostMech &h) {
 }
 // ---------------------------------------------------------------------------- Jacobian plan
 // The segmented Jacobian kernel evaluates one reaction per thread and stores, per
-// point, the reaction's derivative data in LDS:
-//   d values  (index x < nd): dq_i/dC of molecule slot s of reaction i (mass-action
-//             part; a species with coefficient nu fills nu slots), then
-//             dq_i/d[M] (eps - 1) for every third-body efficiency exception;
-//             stored at byte 8 (1 + x); byte 0 holds 0.0; partial sums follow at
-//             8 (1 + nd + p);
-//   quads     (RQ + 32 i): dq_i/dT at fixed C, q_i, dq_i/d[M], sum_j C_j dq_i/dC_j;
-//             quad nr is zero; partial quads follow at RQ + 32 (nr + 1 + p).
+// point, the reaction's derivative data in LDS as FP64 "d values" (index x, byte 8 x):
+//   x = 0                  0.0 (the no-op record)
+//   x = 1 + dpos_i + s     dq_i/dC of molecule slot s of reaction i (mass-action part;
+//                          a species with coefficient nu fills nu slots)
+//   x = 1 + xpos_i + e     dq_i/d[M] (eps - 1) for efficiency exception e of reaction i
+//   x = qb + 4 i + c       c = 0: dq_i/dT at fixed C, 1: q_i, 2: dq_i/d[M],
+//                          3: sum_j C_j dq_i/dC_j  (qb even: 16-byte aligned pairs)
+//   x = pb + p             partial sums of the gather
 // The accumulator matrix A (species rows k, stride sr, FP64) is plain sums of these:
-//   A[k][0..3] = sum_i dnu_ki quad_i                     ("quad" targets)
-//   A[k][5+j]  = sum_i dnu_ki (dq_i/dC_j + exception terms)  ("d" targets)
-// Every target becomes a small reduction tree of tasks; a task is one lane of one
-// round: it adds at most JS_LQ quad records (32 r | dnu as a signed 3-bit field, or a
-// partial quad with coefficient +1) or JS_LD d records (LDS byte offset of the value or
-// of a partial | dnu or +1 as a signed 3-bit field) and stores the sum to its
-// destination word (the first 16-bit field of the lane's round: the LDS index of the
-// destination in 16-byte units for quads, 8-byte units for d values).  A target's
-// tasks run on one wavefront, level by level; a wave-local LDS sync precedes the first
-// round of every level above 0.  Targets are dealt to the wavefronts so that the
-// estimated round cost per wavefront is balanced.
+//   A[k][c]     = sum_i dnu_ki value(qb + 4 i + c),  c = 0..3
+//   A[k][5 + j] = sum_i dnu_ki (dq_i/dC_j + exception terms)
+// Every target entry becomes a small reduction tree of tasks; a task is one lane of one
+// round: it adds at most JS_LD records (byte offset of a value | dnu or +1 as a signed
+// 3-bit field) and stores the sum to its destination word (the first 16-bit field of the
+// lane's round: the LDS index of the destination in 8-byte units).  A target's tasks run
+// on one wavefront, level by level, with one empty round between levels: the kernel
+// reads a round's values during the round before, so a level's reads follow the
+// previous level's stores.  Trees are dealt to the wavefronts to balance their rounds;
+// within a round, tasks are placed on lanes (and their records ordered) so that the
+// lanes of each 16- and 32-lane group address different LDS banks where possible.
 namespace {
 
 struct PlanTask {
     bool partial;                 // destination is a partial slot (else the final entry)
-    int dest;                     // partial index or final index (row k for quads, A entry for d)
-    std::vector<unsigned> recs;   // records (resolved except for nothing: sources are fixed offsets)
+    int dest;                     // partial index or A entry
+    std::vector<unsigned> recs;
     int level;
 };
 
 struct PlanTree {
-    int kind;                     // 0 quad, 1 d
     int final_dest;
     std::vector<unsigned> leaves; // the target's leaf records (for the self-check)
     std::vector<PlanTask> tasks;
@@ -278,9 +277,11 @@ struct PlanTree {
 };
 
 // Splits `recs` into tasks of at most L records; full chunks become partial sums,
-// leftovers are carried to the next level with the new partial records.
-void build_tree(PlanTree &t, std::vector<unsigned> recs, int L, int &n_partial,
-                unsigned (*partial_rec)(int p, int base), int base) {
+// leftovers are carried to the next level with the new partial records.  Partials are
+// symbolic here (PARTIAL_REC | id); LDS slots are assigned once the rounds are known.
+constexpr unsigned PARTIAL_REC = 0x80000000u;
+
+void build_tree(PlanTree &t, std::vector<unsigned> recs, int L, int &n_partial) {
     int level = 0;
     while ((int)recs.size() > L) {
         std::vector<unsigned> next;
@@ -288,7 +289,7 @@ void build_tree(PlanTree &t, std::vector<unsigned> recs, int L, int &n_partial,
         for (size_t c = 0; c < full; c += L) {
             const int p = n_partial++;
             t.tasks.push_back({true, p, std::vector<unsigned>(recs.begin() + c, recs.begin() + c + L), level});
-            next.push_back(partial_rec(p, base));
+            next.push_back(PARTIAL_REC | (unsigned)p);
         }
         for (size_t c = full; c < recs.size(); ++c) next.push_back(recs[c]);
         recs = std::move(next);
@@ -298,8 +299,7 @@ void build_tree(PlanTree &t, std::vector<unsigned> recs, int L, int &n_partial,
     t.depth = level + 1;
 }
 
-unsigned quad_partial_rec(int p, int nr) { return 32u * (unsigned)(nr + 1 + p) | 1u; }
-unsigned d_partial_rec(int p, int nd) { return 8u * (unsigned)(1 + nd + p) | 1u; }
+int coef_of(unsigned rec) { return ((int)(rec & 7u) ^ 4) - 4; }
 
 }  // namespace
 
@@ -364,12 +364,14 @@ void build_jac_plan(HostMech &h) {
         xpos[i] = nd;
         nd += h.ri[i].v[7] & 255;
     }
+    const int qb = (1 + nd + 1) / 2 * 2;          // first quad value (even index)
+    const int pb = qb + 4 * nr;                   // first partial
     const int sr = (ns + 5 + 1) / 2 * 2;
     h.jp_nd = nd;
+    h.jp_qb = qb;
     h.jp_sr = sr;
     // per-thread constants
     h.jp_thr.assign(JS_THREADS, JsThr{-1, 0, 0, 0, 0, 0, -1, 0});
-    h.jp_mrx.clear();
     for (int i = 0; i < nr; ++i) {
         JsThr &c = h.jp_thr[thr_of[i]];
         const int info = h.info[i];
@@ -395,19 +397,20 @@ void build_jac_plan(HostMech &h) {
         }
     for (int i = 0; i < nr; ++i)
         if (info_kind(h.info[i]) == RXN_ELEMENTARY) h.jp_thr[thr_of[i]].troe |= 0xffff << 16;
-    // gather targets (leaf records)
-    std::vector<std::vector<unsigned>> qrec(ns);
-    std::map<int, std::vector<unsigned>> drec;   // A entry -> records
+    // gather targets (leaf records) keyed by A entry
+    std::map<int, std::vector<unsigned>> drec;
     for (int i = 0; i < nr; ++i) {
         std::map<int, int> dn;
         for (int s = 0; s < SLOTS; ++s)
             if (mol[i][s] >= 0) dn[mol[i][s]] += s < MAX_SIDE ? -1 : 1;
         const int n_exc = h.ri[i].v[7] & 255;
+        const bool third = info_kind(h.info[i]) != RXN_ELEMENTARY;
         for (const auto &kv : dn) {
             const int k = kv.first, v = kv.second;
             if (v == 0) continue;
             const unsigned cf = (unsigned)v & 7u;
-            qrec[k].push_back(32u * (unsigned)i | cf);
+            for (int c = 0; c < 4; ++c)
+                if (c != 2 || third) drec[k * sr + c].push_back(8u * (unsigned)(qb + 4 * i + c) | cf);
             for (int s = 0; s < SLOTS; ++s) {
                 if (mol[i][s] < 0) continue;
                 const int x = dpos[i] + (s < MAX_SIDE ? s : nfm[i] + s - MAX_SIDE);
@@ -421,55 +424,42 @@ void build_jac_plan(HostMech &h) {
     }
     // reduction trees
     std::vector<PlanTree> trees;
-    int npq = 0, npd = 0;
-    for (int k = 0; k < ns; ++k)
-        if (!qrec[k].empty()) {
-            PlanTree t{0, k, qrec[k], {}, 0};
-            build_tree(t, qrec[k], JS_LQ, npq, quad_partial_rec, nr);
-            trees.push_back(std::move(t));
-        }
+    int nsym = 0;   // symbolic partials
     for (auto &kv : drec) {
-        PlanTree t{1, kv.first, kv.second, {}, 0};
-        build_tree(t, kv.second, JS_LD, npd, d_partial_rec, nd);
+        PlanTree t{kv.first, kv.second, {}, 0};
+        build_tree(t, kv.second, JS_LD, nsym);
         trees.push_back(std::move(t));
     }
-    if (8 * (1 + nd + npd) > 0xfff8) return no("too many derivative values for 16-bit records");
-    if (32 * (nr + 1 + npq) > 0xffff) return no("too many reactions for 16-bit quad records");
-    // deal the trees to the wavefronts: per wave and level, task counts; rounds = sum of
-    // ceil(tasks / 64) over levels; cost = CQ quad rounds + CD d rounds
-    constexpr int CQ = 3, CD = 1, MAXLV = 8;
-    std::vector<std::array<std::array<int, MAXLV>, 2>> cnt(JS_WAVES);
-    for (auto &c : cnt)
-        for (auto &l : c) l.fill(0);
+    // deal the trees to the wavefronts: rounds = per level ceil(tasks / 64), plus one
+    // empty round before every level above 0; the makespan first, then the smallest
+    // increase (deep trees cluster where their levels already run), then the fewest tasks
+    constexpr int MAXLV = 8;
+    std::vector<std::array<int, MAXLV>> cnt(JS_WAVES);
+    for (auto &c : cnt) c.fill(0);
     auto rounds_of = [&](const std::array<int, MAXLV> &lv) {
         int r = 0;
-        for (int x : lv) r += (x + 63) / 64;
+        for (int l = 0; l < MAXLV; ++l)
+            if (lv[l]) r += (lv[l] + 63) / 64 + (l > 0 ? 1 : 0);
         return r;
     };
     std::vector<int> order(trees.size());
     for (size_t t = 0; t < trees.size(); ++t) order[t] = (int)t;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        if (trees[a].kind != trees[b].kind) return trees[a].kind < trees[b].kind;
         if (trees[a].depth != trees[b].depth) return trees[a].depth > trees[b].depth;
         return trees[a].tasks.size() > trees[b].tasks.size();
     });
-    // choice per tree: the smallest resulting makespan, then the smallest cost increase
-    // (deep trees cluster on the wavefronts that already run their levels), then the
-    // wavefront with the fewest tasks
-    std::vector<int> wave_of(trees.size(), -1), wtasks(JS_WAVES, 0), wcost(JS_WAVES, 0);
+    std::vector<int> wave_of(trees.size(), -1), wtasks(JS_WAVES, 0), wrounds(JS_WAVES, 0);
     for (int t : order) {
         const PlanTree &tr = trees[t];
         if (tr.depth > MAXLV) return no("reduction tree too deep");
-        const int span = *std::max_element(wcost.begin(), wcost.end());
+        const int span = *std::max_element(wrounds.begin(), wrounds.end());
         int best = -1, best_span = 0, best_inc = 0;
         for (int w = 0; w < JS_WAVES; ++w) {
-            auto lv = cnt[w][tr.kind];
+            auto lv = cnt[w];
             for (const auto &tk : tr.tasks) lv[tk.level]++;
-            const int rq = tr.kind == 0 ? rounds_of(lv) : rounds_of(cnt[w][0]);
-            const int rd = tr.kind == 1 ? rounds_of(lv) : rounds_of(cnt[w][1]);
-            if (rq > JS_QMAX || rd > JS_DMAX) continue;
-            const int cost = CQ * rq + CD * rd;
-            const int nspan = std::max(span, cost), inc = cost - wcost[w];
+            const int rd = rounds_of(lv);
+            if (rd > JS_DMAX) continue;
+            const int nspan = std::max(span, rd), inc = rd - wrounds[w];
             if (best < 0 || nspan < best_span || (nspan == best_span && inc < best_inc) ||
                 (nspan == best_span && inc == best_inc && wtasks[w] < wtasks[best])) {
                 best = w;
@@ -479,169 +469,224 @@ void build_jac_plan(HostMech &h) {
         }
         if (best < 0) return no("gather rounds exceed the per-wavefront register budget");
         wave_of[t] = best;
-        for (const auto &tk : tr.tasks) cnt[best][tr.kind][tk.level]++;
+        for (const auto &tk : tr.tasks) cnt[best][tk.level]++;
         wtasks[best] += (int)tr.tasks.size();
-        wcost[best] = CQ * rounds_of(cnt[best][0]) + CD * rounds_of(cnt[best][1]);
+        wrounds[best] = rounds_of(cnt[best]);
     }
+    // rounds per wavefront: level by level, an empty round between levels, padded to JS_DMAX
+    struct Slot { int tree, task; };
+    std::vector<std::vector<std::vector<Slot>>> rounds(JS_WAVES);
+    for (int w = 0; w < JS_WAVES; ++w) {
+        for (int lv = 0; lv < MAXLV; ++lv) {
+            std::vector<Slot> tasks;
+            for (size_t t = 0; t < trees.size(); ++t)
+                if (wave_of[t] == w)
+                    for (size_t q = 0; q < trees[t].tasks.size(); ++q)
+                        if (trees[t].tasks[q].level == lv) tasks.push_back({(int)t, (int)q});
+            if (tasks.empty()) continue;
+            if (lv > 0) rounds[w].emplace_back();
+            for (size_t c = 0; c < tasks.size(); c += 64)
+                rounds[w].emplace_back(tasks.begin() + c, tasks.begin() + std::min(c + 64, tasks.size()));
+        }
+        if ((int)rounds[w].size() > JS_DMAX) return no("gather rounds exceed the per-wavefront register budget");
+        rounds[w].resize(JS_DMAX);
+    }
+    // LDS slots of the partials, per wavefront with reuse: a partial lives from the round
+    // that stores it to the round that reads it (whose loads are issued in the round
+    // before); a slot is reused only from that reading round on
+    std::vector<int> slot_of(nsym, -1), wround(nsym, -1), rround(nsym, -1), pwave(nsym, -1);
+    for (int w = 0; w < JS_WAVES; ++w)
+        for (int r = 0; r < JS_DMAX; ++r)
+            for (const Slot &sl : rounds[w][r]) {
+                const PlanTask &tk = trees[sl.tree].tasks[sl.task];
+                if (tk.partial) {
+                    wround[tk.dest] = r;
+                    pwave[tk.dest] = w;
+                }
+                for (unsigned rec : tk.recs)
+                    if (rec & PARTIAL_REC) rround[rec & ~PARTIAL_REC] = r;
+            }
+    int npd = 0;
+    for (int w = 0; w < JS_WAVES; ++w) {
+        std::vector<int> free_slots;
+        std::vector<std::vector<int>> release(JS_DMAX + 1);
+        for (int r = 0; r < JS_DMAX; ++r) {
+            for (int slot : release[r]) free_slots.push_back(slot);
+            for (const Slot &sl : rounds[w][r]) {
+                const PlanTask &tk = trees[sl.tree].tasks[sl.task];
+                if (!tk.partial) continue;
+                const int p = tk.dest;
+                if (rround[p] <= r || pwave[p] != w) return no("plan: partial read before it is written");
+                int slot;
+                if (!free_slots.empty()) {
+                    slot = free_slots.back();
+                    free_slots.pop_back();
+                } else {
+                    slot = npd++;
+                }
+                slot_of[p] = slot;
+                release[rround[p]].push_back(slot);
+            }
+        }
+    }
+    auto resolve = [&](unsigned rec) -> unsigned {
+        return (rec & PARTIAL_REC) ? 8u * (unsigned)(pb + slot_of[rec & ~PARTIAL_REC]) | 1u : rec;
+    };
+    if (8 * (pb + npd) > 0xfff8) return no("too many derivative values for 16-bit records");
     // LDS layout (bytes)
     auto up = [](int b, int a) { return (b + a - 1) / a * a; };
     const int n_troe = (int)(h.troe.size() / 8);
-    int off = up(8 * (1 + nd + npd), 32);
-    h.jp_off_rdq = off;  off = up(off + 32 * (nr + 1 + npq), 32);
+    int off = up(8 * (pb + npd), 32);
     h.jp_off_a = off;    off = up(off + 8 * (ns * sr + 4), 16);
     h.jp_off_sp = off;   off = up(off + 2 * 32 * (ns + 1), 16);
     h.jp_off_row = off;  off = up(off + 16 * ns, 16);
     h.jp_off_p = off;    off = up(off + 8 * JS_PWAVES * sr, 16);
     h.jp_off_sc = off;   off = up(off + 8 * 32, 16);
     h.jp_off_tp = off;   off = up(off + 8 * JS_TP * n_troe, 16);
-    h.jp_off_tq = off;   off = up(off + 2 * 8 * JS_TQ * n_troe, 16);
+    h.jp_off_tq = off;   off = up(off + 8 * JS_TQ * n_troe, 16);
     h.jp_off_ns = off;   off = up(off + 8 * 16 * ns, 16);
     h.jp_off_iw = off;   off = up(off + 8 * ns, 16);
     h.jp_off_ex = off;   off = up(off + 12 * (int)h.eff_sp.size(), 16);
     h.jp_nm = (int)h.jp_mrx.size() / 2;
     h.jp_off_mx = off;   off = up(off + 8 * h.jp_nm, 16);
-    h.jp_off_mq = off;   off = up(off + 2 * 16 * h.jp_nm, 16);
+    h.jp_off_mq = off;   off = up(off + 16 * h.jp_nm, 16);
     h.jp_lds = off;
     if (off > JS_MAX_LDS) return no("LDS footprint " + std::to_string(off) + " B above the limit");
     const int a_trash = ns * sr;
-    auto dest_word = [&](const PlanTree &tr, const PlanTask &tk) -> unsigned {
-        if (tr.kind == 0)
-            return tk.partial ? (unsigned)((h.jp_off_rdq + 32 * (nr + 1 + tk.dest)) / 16)
-                              : (unsigned)((h.jp_off_a + 8 * tk.dest * sr) / 16);
-        return tk.partial ? (unsigned)(1 + nd + tk.dest) : (unsigned)(h.jp_off_a / 8 + tk.dest);
+    const unsigned trash = (unsigned)(h.jp_off_a / 8 + a_trash);
+    if (trash > 0xffff) return no("accumulator matrix beyond 16-bit destination words");
+    auto dest_word = [&](const PlanTask &tk) -> unsigned {
+        return tk.partial ? (unsigned)(pb + slot_of[tk.dest]) : (unsigned)(h.jp_off_a / 8 + tk.dest);
     };
-    const unsigned trash_q = (unsigned)((h.jp_off_a + 8 * a_trash) / 16), trash_d = (unsigned)(h.jp_off_a / 8 + a_trash);
-    if (trash_d > 0xffff) return no("accumulator matrix beyond 16-bit destination words");
-    // emit: per wave, quad rounds then d rounds, each kind level by level
+
     h.jp_prog.assign(8 * JS_WAVES, 0);
-    struct Slot { int tree, task; };
-    std::vector<std::array<std::vector<std::vector<Slot>>, 2>> rounds(JS_WAVES);   // [w][kind][round] -> lanes
-    std::vector<std::array<unsigned, 2>> syncm(JS_WAVES, {0u, 0u});
+    for (int w = 0; w < JS_WAVES; ++w) {
+        h.jp_prog[8 * w + 0] = wrounds[w];
+        h.jp_prog[8 * w + 1] = w * JS_DMAX * 128;   // first 32-bit word of the wavefront's rounds
+    }
+    constexpr int L = JS_LD, WPL = 2, RSZ = 64 * WPL;
+    h.jp_recs.assign((size_t)JS_WAVES * JS_DMAX * RSZ, 0u);
     for (int w = 0; w < JS_WAVES; ++w)
-        for (int kind = 0; kind < 2; ++kind)
-            for (int lv = 0; lv < MAXLV; ++lv) {
-                std::vector<Slot> tasks;
-                for (size_t t = 0; t < trees.size(); ++t)
-                    if (wave_of[t] == w && trees[t].kind == kind)
-                        for (size_t q = 0; q < trees[t].tasks.size(); ++q)
-                            if (trees[t].tasks[q].level == lv) tasks.push_back({(int)t, (int)q});
-                for (size_t c = 0; c < tasks.size(); c += 64) {
-                    if (c == 0 && lv > 0) syncm[w][kind] |= 1u << rounds[w][kind].size();
-                    rounds[w][kind].emplace_back(tasks.begin() + c, tasks.begin() + std::min(c + 64, tasks.size()));
+        for (int r = 0; r < JS_DMAX; ++r) {
+            // lanes and record order of this round's tasks, chosen so that in every LDS
+            // instruction of the round (one per record field, and the store) the lanes of
+            // each 16- and 32-lane group address different banks where possible
+            std::vector<std::array<unsigned, 1 + L>> lane_f(64);
+            std::array<std::array<std::array<std::array<int, 32>, 4>, 2>, 1 + L> cnt_b{};
+            auto key_of = [&](int x, unsigned v) { return (x == 0 ? 8u * v : (v & 0xfff8u)) / 8u; };
+            auto cost_of = [&](int l, const std::array<unsigned, 1 + L> &f) {
+                int c = 0;
+                for (int x = 0; x <= L; ++x) {
+                    if (x > 0 && (f[x] & 7u) == 0) continue;   // no-op records read one broadcast address
+                    const unsigned a = key_of(x, f[x]);
+                    c += cnt_b[x][0][l / 16][a % 16] + cnt_b[x][1][l / 32][a % 32];
+                }
+                return c;
+            };
+            std::vector<bool> used(64, false);
+            for (const Slot &sl : rounds[w][r]) {
+                const PlanTask &tk = trees[sl.tree].tasks[sl.task];
+                std::array<unsigned, 1 + L> f;
+                f.fill(0u);
+                f[0] = dest_word(tk);
+                for (size_t x = 0; x < tk.recs.size(); ++x) f[1 + x] = resolve(tk.recs[x]);
+                std::array<int, L> idx;
+                for (int x = 0; x < L; ++x) idx[x] = x;
+                int best_l = -1, best_c = 0;
+                std::array<unsigned, 1 + L> best_f = f, g = f;
+                do {
+                    for (int x = 0; x < L; ++x) g[1 + x] = f[1 + idx[x]];
+                    for (int l = 0; l < 64; ++l) {
+                        if (used[l]) continue;
+                        const int c = cost_of(l, g);
+                        if (best_l < 0 || c < best_c) {
+                            best_l = l;
+                            best_c = c;
+                            best_f = g;
+                        }
+                    }
+                } while (std::next_permutation(idx.begin(), idx.end()));
+                used[best_l] = true;
+                lane_f[best_l] = best_f;
+                for (int x = 0; x <= L; ++x) {
+                    if (x > 0 && (best_f[x] & 7u) == 0) continue;
+                    const unsigned a = key_of(x, best_f[x]);
+                    cnt_b[x][0][best_l / 16][a % 16]++;
+                    cnt_b[x][1][best_l / 32][a % 32]++;
                 }
             }
-    size_t words = 0;
-    std::vector<std::array<size_t, 2>> base(JS_WAVES);
-    for (int w = 0; w < JS_WAVES; ++w) {
-        base[w][0] = words;
-        words += rounds[w][0].size() * 256;
-        base[w][1] = words;
-        words += rounds[w][1].size() * 128;
-        h.jp_prog[8 * w + 0] = (int)rounds[w][0].size();
-        h.jp_prog[8 * w + 1] = (int)rounds[w][1].size();
-        h.jp_prog[8 * w + 2] = (int)base[w][0];
-        h.jp_prog[8 * w + 3] = (int)base[w][1];
-        h.jp_prog[8 * w + 4] = (int)syncm[w][0];
-        h.jp_prog[8 * w + 5] = (int)syncm[w][1];
-    }
-    h.jp_recs.assign(words ? words : 4, 0u);
-    const unsigned zero_q = 32u * (unsigned)nr, zero_d = 0u;
-    for (int w = 0; w < JS_WAVES; ++w)
-        for (int kind = 0; kind < 2; ++kind) {
-            const int L = kind == 0 ? JS_LQ : JS_LD, wpl = kind == 0 ? 4 : 2, rsz = 64 * wpl;
-            for (size_t r = 0; r < rounds[w][kind].size(); ++r)
-                for (int l = 0; l < 64; ++l) {
-                    std::vector<unsigned> f(1 + L, kind == 0 ? zero_q : zero_d);
-                    if (l < (int)rounds[w][kind][r].size()) {
-                        const Slot sl = rounds[w][kind][r][l];
-                        const PlanTask &tk = trees[sl.tree].tasks[sl.task];
-                        f[0] = dest_word(trees[sl.tree], tk);
-                        for (size_t x = 0; x < tk.recs.size(); ++x) f[1 + x] = tk.recs[x];
-                    } else {
-                        f[0] = kind == 0 ? trash_q : trash_d;
-                    }
-                    for (int x = 0; x <= L; ++x)
-                        h.jp_recs[base[w][kind] + r * rsz + (size_t)l * wpl + x / 2] |= (f[x] & 0xffffu) << (16 * (x & 1));
+            for (int l = 0; l < 64; ++l) {
+                if (!used[l]) {
+                    lane_f[l].fill(0u);
+                    lane_f[l][0] = trash;
                 }
+                for (int x = 0; x <= L; ++x)
+                    h.jp_recs[(size_t)w * JS_DMAX * RSZ + (size_t)r * RSZ + (size_t)l * WPL + x / 2] |=
+                        (lane_f[l][x] & 0xffffu) << (16 * (x & 1));
+            }
         }
-    // self-check: replay the rounds symbolically (LDS word -> multiset of leaf records with
-    // coefficients) and compare every final entry with its target's leaves
+    // self-check: replay the rounds symbolically (LDS word -> leaf records with their
+    // coefficients) in the kernel's order: the loads of round r are issued before the
+    // store of round r - 1, so they see the stores of rounds <= r - 2; compare every final
+    // entry with its target's leaves
     {
-        std::map<unsigned, std::map<unsigned, int>> slot_val;             // byte address -> leaf -> coef
-        std::map<unsigned, std::pair<int, int>> written;                  // byte address -> (wave, round)
-        std::map<unsigned, std::map<unsigned, int>> final_q, final_d;     // dest word -> value
-        const unsigned q_leaf_lim = 32u * (unsigned)nr, d_leaf_lim = 8u * (unsigned)(1 + nd);
-        for (int w = 0; w < JS_WAVES; ++w)
-            for (int kind = 0; kind < 2; ++kind) {
-                const int L = kind == 0 ? JS_LQ : JS_LD, wpl = kind == 0 ? 4 : 2, rsz = 64 * wpl;
-                int last_sync = -1;
-                for (size_t r = 0; r < rounds[w][kind].size(); ++r) {
-                    if (syncm[w][kind] >> r & 1u) last_sync = (int)r;
-                    std::vector<std::pair<unsigned, std::map<unsigned, int>>> stores;
+        std::map<unsigned, std::map<unsigned, int>> fin;
+        const unsigned leaf_lim = 8u * (unsigned)pb;
+        for (int w = 0; w < JS_WAVES; ++w) {
+            std::map<unsigned, std::map<unsigned, int>> val;           // partial slots of this wavefront
+            std::vector<std::pair<unsigned, std::map<unsigned, int>>> pending;   // stores of round r - 1
+            for (int r = 0; r <= JS_DMAX; ++r) {
+                std::vector<std::pair<unsigned, std::map<unsigned, int>>> stores;
+                if (r < JS_DMAX)
                     for (int l = 0; l < 64; ++l) {
                         auto field = [&](int x) {
-                            return (h.jp_recs[base[w][kind] + r * rsz + (size_t)l * wpl + x / 2] >> (16 * (x & 1))) & 0xffffu;
+                            return (h.jp_recs[(size_t)w * JS_DMAX * RSZ + (size_t)r * RSZ + (size_t)l * WPL + x / 2] >>
+                                    (16 * (x & 1))) & 0xffffu;
                         };
                         std::map<unsigned, int> v;
                         for (int x = 1; x <= L; ++x) {
-                            const unsigned rec = field(x);
-                            const unsigned amask = kind == 0 ? 0xffe0u : 0xfff8u;
-                            const unsigned addr = (kind == 0 ? (unsigned)h.jp_off_rdq : 0u) + (rec & amask);
-                            const int coef = ((int)(rec & 7u) ^ 4) - 4;
-                            if (kind == 0 && (rec & 0x18u)) return no("plan self-check: bad quad record");
-                            const bool leaf = kind == 0 ? (rec & amask) <= q_leaf_lim : (rec & amask) < d_leaf_lim;
+                            const unsigned rec = field(x), addr = rec & 0xfff8u;
+                            const int coef = coef_of(rec);
                             if (coef == 0) continue;
-                            if (kind == 1 && (rec & amask) == 0) return no("plan self-check: record on the zero entry");
-                            if (leaf) {
-                                v[rec & amask] += coef;
+                            if (addr == 0) return no("plan self-check: record on the zero entry");
+                            if (addr < leaf_lim) {
+                                v[addr] += coef;
                             } else {
-                                auto it = written.find(addr);
-                                if (it == written.end()) return no("plan self-check: partial read before written");
-                                if (it->second.first != w || it->second.second >= last_sync)
-                                    return no("plan self-check: partial read without a sync after its write");
-                                for (const auto &lv : slot_val[addr]) v[lv.first] += coef * lv.second;
+                                auto it = val.find(addr);
+                                if (it == val.end()) return no("plan self-check: partial read before written");
+                                for (const auto &lv : it->second) v[lv.first] += coef * lv.second;
                             }
                         }
-                        const unsigned dw = field(0);
-                        const unsigned daddr = kind == 0 ? 16u * dw : 8u * dw;
-                        stores.push_back({daddr, v});
+                        stores.push_back({8u * field(0), v});
                     }
-                    for (auto &st : stores) {
-                        const bool is_final = st.first >= (unsigned)h.jp_off_a;
-                        const bool is_trash = st.first == (kind == 0 ? 16u * trash_q : 8u * trash_d);
-                        if (is_trash) {
-                            for (const auto &lv : st.second)
-                                if (lv.second) return no("plan self-check: records on the trash target");
-                            continue;
-                        }
-                        auto &fin = kind == 0 ? final_q : final_d;
-                        if (is_final) {
-                            if (fin.count(st.first)) return no("plan self-check: final entry written twice");
-                            fin[st.first] = st.second;
-                        } else {
-                            if (written.count(st.first)) return no("plan self-check: partial written twice");
-                            written[st.first] = {w, (int)r};
-                            slot_val[st.first] = st.second;
-                        }
+                for (auto &st : pending) {   // round r - 1's stores land after round r's loads
+                    if (st.first == 8u * trash) {
+                        for (const auto &lv : st.second)
+                            if (lv.second) return no("plan self-check: records on the trash target");
+                        continue;
+                    }
+                    if (st.first >= (unsigned)h.jp_off_a) {
+                        if (fin.count(st.first)) return no("plan self-check: final entry written twice");
+                        fin[st.first] = st.second;
+                    } else {
+                        if (st.first < leaf_lim) return no("plan self-check: bad partial destination");
+                        val[st.first] = st.second;
                     }
                 }
+                pending = std::move(stores);
             }
-        size_t nq_targets = 0, nd_targets = 0;
+        }
         for (const auto &tr : trees) {
             std::map<unsigned, int> want;
-            for (unsigned rec : tr.leaves) want[rec & (tr.kind == 0 ? 0xffe0u : 0xfff8u)] += ((int)(rec & 7u) ^ 4) - 4;
+            for (unsigned rec : tr.leaves) want[rec & 0xfff8u] += coef_of(rec);
             for (auto it = want.begin(); it != want.end();) it = it->second == 0 ? want.erase(it) : std::next(it);
-            const unsigned daddr = tr.kind == 0 ? (unsigned)(h.jp_off_a + 8 * tr.final_dest * sr)
-                                                : (unsigned)(h.jp_off_a + 8 * tr.final_dest);
-            auto &fin = tr.kind == 0 ? final_q : final_d;
-            auto it = fin.find(daddr);
+            auto it = fin.find((unsigned)(h.jp_off_a + 8 * tr.final_dest));
             if (it == fin.end()) return no("plan self-check: target never written");
             std::map<unsigned, int> got = it->second;
             for (auto g = got.begin(); g != got.end();) g = g->second == 0 ? got.erase(g) : std::next(g);
             if (got != want) return no("plan self-check: target sum differs from the stoichiometry");
-            (tr.kind == 0 ? nq_targets : nd_targets)++;
         }
-        if (nq_targets != final_q.size() || nd_targets != final_d.size()) return no("plan self-check: stray final entries");
+        if (fin.size() != trees.size()) return no("plan self-check: stray final entries");
     }
     h.jp_ok = 1;
     h.jp_why.clear();
@@ -712,8 +757,9 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
     m.eff_m1 = (const double *)at(oEm);
     m.jp_thr = (const int *)at(oJt); m.jp_recs = (const unsigned *)at(oJr); m.jp_prog = (const int *)at(oJp);
     m.jp_mrx = (const int *)at(oJm); m.jp_nm = h.jp_nm; m.jp_off_mx = h.jp_off_mx; m.jp_off_mq = h.jp_off_mq;
+    m.jp_qb = h.jp_qb;
     m.jp_ok = h.jp_ok; m.jp_nd = h.jp_nd; m.jp_sr = h.jp_sr; m.jp_lds = h.jp_lds;
-    m.jp_off_rdq = h.jp_off_rdq; m.jp_off_a = h.jp_off_a; m.jp_off_sp = h.jp_off_sp;
+    m.jp_off_a = h.jp_off_a; m.jp_off_sp = h.jp_off_sp;
     m.jp_off_row = h.jp_off_row; m.jp_off_p = h.jp_off_p; m.jp_off_sc = h.jp_off_sc;
     m.jp_off_tp = h.jp_off_tp; m.jp_off_ex = h.jp_off_ex; m.jp_off_tq = h.jp_off_tq;
     m.jp_off_ns = h.jp_off_ns; m.jp_off_iw = h.jp_off_iw;
