@@ -37,10 +37,16 @@ def kernel_source_hash():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def recorded_traffic(prec):
-    """HBM bytes per launch of k_jac from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", f"k_jac_{prec}_c3_traffic.txt")
+def jac_kernel_name(plan, prec):
+    """Name (as rocprofv3 shows it, shortened) of the kernel crf_wdot_jac launches."""
+    base = "k_jac_seg" if plan.startswith("segmented") else "k_jac"
+    return "%s<%s>" % (base, "false" if prec == "fp64" else "true")
+
+
+def recorded_traffic(kernel, prec):
+    """HBM bytes per launch of the Jacobian kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{prec}_53sp_2p18_traffic.txt")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -94,7 +100,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--points", type=int, default=1 << 18)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--cpu-sample", type=int, default=10240,
+                    help="points of the oracle CPU baseline (about 10-30 s of host time)")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None, help="time one precision only")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (the reference for HBM byte counters)")
@@ -137,12 +144,14 @@ def main():
             J = torch.empty((n, ns + 1, ns + 1), dtype=torch.float64 if prec == "fp64" else torch.float32,
                             device=dev)
             ms = timed(lambda: crf.wdot_jac(m, T, p, Y, prec, out=J), args.steps, args.warmup, stream)
+            kname = jac_kernel_name(m.jac_plan, prec)
             bpp = jac_bytes_per_point(ns, prec)
             achieved = bpp * n / (ms * 1e-3) / 1e9
             res[prec] = {"value": n / (ms * 1e-3) / 1e6, "ms_per_step": ms,
                          "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(prec),
-                                      "bytes_per_point": bpp, "kernel": "k_jac<%s>" % ("false" if prec == "fp64" else "true")}}
+                                      "frac": achieved / HBM_PEAK_GBS,
+                                      "traffic": recorded_traffic(kname.split("<")[0], prec),
+                                      "bytes_per_point": bpp, "kernel": kname}}
             del J
             torch.cuda.empty_cache()
         path = {}

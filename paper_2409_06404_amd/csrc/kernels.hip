@@ -621,8 +621,8 @@ __global__ __launch_bounds__(64) void k_jac(DevMech m, int64_t n, const double *
 }
 
 // ------------------------------------------------------------------ Jacobian (segmented gather)
-// One workgroup of JS_THREADS threads (6 wavefronts) per point, persistent over a
-// strided sequence of points; thread t owns one reaction for the workgroup's lifetime
+// One workgroup of JS_THREADS threads (6 wavefronts) per point, persistent over an
+// XCD-aware strided sequence of points; thread t owns one reaction for the workgroup's lifetime
 // (its constants stay in registers).  The mechanism's Troe parameters and efficiency
 // exceptions are staged in LDS once.  Per point, separated by workgroup barriers:
 //   B  threads = reactions: rate of progress and all its derivatives into the per-point
@@ -908,12 +908,18 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
     const int rphase = JS_EWAVES * WAVE / npair;
     const int pc0 = 2 * (tid % npair), pr0 = tid / npair;
     const bool pon = tid < JS_EWAVES * WAVE && pr0 < rphase;
-    // state of the first point into buffer 0; prefetch of the second (indices clamped:
-    // a block always has a first point, and a repeat past the end is never used)
+    // this workgroup's points: i = slot, slot + G, ... (G = gridDim.x).  Workgroups are
+    // dispatched round-robin over the 8 XCDs, so the slots of one XCD's workgroups are a
+    // contiguous run of G/8 points: the 16 points of a 128-byte line of the species-major Y
+    // (and of w) are handled at the same time on one XCD and meet in its L2
+    const int64_t G = gridDim.x;
+    const int64_t slot = (G % 8 == 0) ? (int64_t)(blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : (int64_t)blockIdx.x;
+    // state of the first point into buffer 0; prefetch of the second (indices clamped; a
+    // repeat of the last point past the end is never used)
     double pf_T = 0.0, pf_p = 0.0, pf_Y = 0.0;
     __syncthreads();   // staged tables complete
     if (n > 0) {
-        const int64_t i0 = min((int64_t)blockIdx.x, n - 1), i1 = min(i0 + (int64_t)gridDim.x, n - 1);
+        const int64_t i0 = min(slot, n - 1), i1 = min(i0 + G, n - 1);
         const int ky = min(lane, ns - 1);
         if (wave >= WY - 1)
             jac_seg_state<MIXED>(ns, m.R, lnp0R, wave, WY, lane, T[i0], p[i0 * ps], Y[(int64_t)ky * ld + i0], NS,
@@ -926,7 +932,7 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
     }
     __syncthreads();
     int buf = 0;
-    for (int64_t i = blockIdx.x; i < n; i += gridDim.x, buf ^= 1) {
+    for (int64_t i = slot; i < n; i += G, buf ^= 1) {
         const double *SP = SP0 + buf * 4 * (ns + 1);
         double *SC = SC0 + buf * 16;
         // ---- B
@@ -992,13 +998,13 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
             if (lane == 0) SC[8] = cw;
             jac_seg_troe_fc<MIXED>(lane, n_troe, pf_T, TP, TQ0);
         } else {
-            // state of point i + gridDim.x (past the end: a repeat of the last point, unused)
+            // state of point i + G (past the end: a repeat of the last point, unused)
             double *SPn = SP0 + (buf ^ 1) * 4 * (ns + 1), *SCn = SC0 + (buf ^ 1) * 16;
             jac_seg_state<MIXED>(ns, m.R, lnp0R, wave, WY, lane, pf_T, pf_p, pf_Y, NS, IW, MX, n_m, EXm, EXs,
                                  n_troe, TP, SPn, SCn, MQ0, TQ0);
         }
-        {   // prefetch of point i + 2 gridDim.x, in straight-line code on every wavefront
-            const int64_t i2 = min(i + 2 * (int64_t)gridDim.x, n - 1);
+        {   // prefetch of point i + 2G, in straight-line code on every wavefront
+            const int64_t i2 = min(i + 2 * G, n - 1);
             pf_T = T[i2];
             pf_p = p[i2 * ps];
             pf_Y = Y[(int64_t)min(lane, ns - 1) * ld + i2];
