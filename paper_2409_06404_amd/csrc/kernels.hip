@@ -779,8 +779,21 @@ __device__ inline void jac_seg_state(int ns, double R, double lnp0R, int wave, i
                                      double *SP, double *SC, double *MQ, double *TQ) {
     if (wave == wy) {
         const bool has = lane < ns;
-        double yw = 0.0;
-        if (has) yw = yk * IW[lane];
+        // static tables first (their LDS latency then overlaps the mixture sums): 1/W of this
+        // lane's species and the efficiency exceptions of [M] slot `lane`, up to four of them
+        // (the unused ones point at the unit dummy species with a zero coefficient)
+        const double iw = has ? IW[lane] : 0.0;
+        int2 mx0 = make_int2(0, 0);
+        if (lane < n_m) mx0 = *(const int2 *)(MX + 2 * lane);
+        int ek[4];
+        double em[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const bool on = e < mx0.y;
+            ek[e] = on ? EXs[mx0.x + e] : ns;
+            em[e] = on ? EXm[mx0.x + e] : 0.0;
+        }
+        const double yw = has ? yk * iw : 0.0;
         const double wbar = 1.0 / wave_sum(yw);
         const double rho = pp * wbar / (R * Tt);
         const double cv = rho * yw;
@@ -796,8 +809,15 @@ __device__ inline void jac_seg_state(int ns, double R, double lnp0R, int wave, i
         // ln [M] of the falloff ones (slots 0 .. n_troe - 1)
         wave_lds_sync();
         for (int j = lane; j < n_m; j += WAVE) {
-            const int2 mx = *(const int2 *)(MX + 2 * j);
             double M = ct;
+            if (j == lane && mx0.y <= 4) {
+                M += em[0] * SP[4 * ek[0]] + em[1] * SP[4 * ek[1]] + em[2] * SP[4 * ek[2]] + em[3] * SP[4 * ek[3]];
+                double lnM = 0.0;
+                if (j < n_troe) lnM = MIXED ? (double)__logf((float)M) : log(M);
+                *(double2 *)(MQ + 2 * j) = double2{M, lnM};
+                continue;
+            }
+            const int2 mx = *(const int2 *)(MX + 2 * j);
             int e = 0;
             for (; e + 4 <= mx.y; e += 4) {   // the exceptions' loads issued together
                 const int k0 = EXs[mx.x + e], k1 = EXs[mx.x + e + 1], k2 = EXs[mx.x + e + 2], k3 = EXs[mx.x + e + 3];
@@ -810,13 +830,19 @@ __device__ inline void jac_seg_state(int ns, double R, double lnp0R, int wave, i
             *(double2 *)(MQ + 2 * j) = double2{M, lnM};
         }
     } else if (wave == wy - 1) {
-        const double lnT = log(Tt), invT = 1.0 / Tt;
+        // both ranges' coefficients are requested at once, then one is selected
+        double c15[15];
         if (lane < ns) {
             const double *c16 = NS + 16 * lane;
-            const double *a = c16 + (Tt <= c16[0] ? 1 : 8);   // the temperature range's 7 coefficients
+#pragma unroll
+            for (int q = 0; q < 15; ++q) c15[q] = c16[q];
+        }
+        const double lnT = log(Tt), invT = 1.0 / Tt;
+        if (lane < ns) {
+            const bool low = Tt <= c15[0];   // the temperature range's 7 coefficients
             double b[7];
 #pragma unroll
-            for (int q = 0; q < 7; ++q) b[q] = a[q];
+            for (int q = 0; q < 7; ++q) b[q] = low ? c15[1 + q] : c15[8 + q];
             const double cp = b[0] + Tt * (b[1] + Tt * (b[2] + Tt * (b[3] + Tt * b[4])));
             const double hh = b[0] + Tt * (b[1] * 0.5 + Tt * (b[2] * (1.0 / 3.0) + Tt * (b[3] * 0.25 + Tt * (b[4] * 0.2)))) +
                               b[5] * invT;
@@ -902,8 +928,8 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
     const uint2 *drec = (const uint2 *)(m.jp_recs + __builtin_amdgcn_readfirstlane(prog[1]));
     const int qb = m.jp_qb;
     // emission mapping: a pair of columns (c0, c0 + 1) and a row phase per thread, on
-    // wavefronts 0..JS_EWAVES-1 (the falloff and third-body wavefronts, which take longest
-    // in the rate phase that follows, and the state wavefronts do not emit)
+    // wavefronts 0..JS_EWAVES-1, whose rate phase that follows is the shortest (the
+    // third-body and falloff reactions sit on the last wavefronts)
     const int npair = (n1 + 1) / 2;
     const int rphase = JS_EWAVES * WAVE / npair;
     const int pc0 = 2 * (tid % npair), pr0 = tid / npair;

@@ -386,14 +386,27 @@ void build_jac_plan(HostMech &h) {
         c.troe = info_kind(info) == RXN_TROE ? (h.ri[i].v[7] >> 8) & 0xffff : 0xffff;
         c.dnu = h.dnu_sum[i];
     }
-    // [M] slots, formed with the state: falloff reactions first (only they need ln [M])
+    // [M] slots, formed with the state: falloff reactions first (only they need ln [M]);
+    // reactions with the same efficiency exceptions share a slot
+    std::map<std::vector<std::pair<int, double>>, int> mslot_of;
     for (int pass = 0; pass < 2; ++pass)
         for (int i = 0; i < nr; ++i) {
             const int kind = info_kind(h.info[i]);
             if (kind == RXN_ELEMENTARY || (kind == RXN_TROE) != (pass == 0)) continue;
-            h.jp_thr[thr_of[i]].troe |= ((int)h.jp_mrx.size() / 2) << 16;
-            h.jp_mrx.push_back(h.ri[i].v[6]);
-            h.jp_mrx.push_back(h.ri[i].v[7] & 255);
+            std::vector<std::pair<int, double>> key;
+            for (int e = 0; e < (h.ri[i].v[7] & 255); ++e)
+                key.emplace_back(h.eff_sp[h.ri[i].v[6] + e], h.eff_m1[h.ri[i].v[6] + e]);
+            auto it = mslot_of.find(key);
+            int slot;
+            if (it != mslot_of.end()) {
+                slot = it->second;
+            } else {
+                slot = (int)h.jp_mrx.size() / 2;
+                mslot_of.emplace(key, slot);
+                h.jp_mrx.push_back(h.ri[i].v[6]);
+                h.jp_mrx.push_back(h.ri[i].v[7] & 255);
+            }
+            h.jp_thr[thr_of[i]].troe |= slot << 16;
         }
     for (int i = 0; i < nr; ++i)
         if (info_kind(h.info[i]) == RXN_ELEMENTARY) h.jp_thr[thr_of[i]].troe |= 0xffff << 16;
