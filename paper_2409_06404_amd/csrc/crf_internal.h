@@ -62,14 +62,15 @@ struct DevMech {
     const int *jp_mrx;        // [jp_nm][2]: first efficiency exception, exception count of each [M] slot
     const int *jp_prog;       // [JS_WAVES][8]: gather rounds in use, first 32-bit word of the rounds
     int jp_ok, jp_nd, jp_sr, jp_lds;
+    int jp_rmax;              // most gather rounds of a wavefront (at most JS_DMAX)
     int jp_off_a, jp_off_sp, jp_off_row, jp_off_p, jp_off_sc, jp_off_tp, jp_off_ex;  // LDS bytes
     int jp_off_tq, jp_off_ns, jp_off_iw, jp_off_mx, jp_off_mq, jp_nm;
     int jp_qb;                // first per-reaction (dT, q, d[M], sum) value among the d values
 };
 
 // Segmented Jacobian kernel (k_jac_seg): six wavefronts per workgroup, one reaction per
-// thread, JS_DMAX gather rounds of JS_LD records per lane (streamed through registers,
-// JS_DW rounds ahead).
+// thread, at most JS_DMAX gather rounds of JS_LD records per lane (streamed through
+// registers, JS_DW rounds ahead).
 constexpr int JS_WAVES = 6;
 constexpr int JS_THREADS = 64 * JS_WAVES;
 constexpr int JS_LD = 3;
@@ -116,7 +117,7 @@ struct HostMech {
     std::vector<JsThr> jp_thr;
     std::vector<unsigned> jp_recs;
     std::vector<int> jp_prog;
-    int jp_ok = 0, jp_nd = 0, jp_sr = 0, jp_lds = 0;
+    int jp_ok = 0, jp_nd = 0, jp_sr = 0, jp_lds = 0, jp_rmax = 0;
     int jp_off_a = 0, jp_off_sp = 0, jp_off_row = 0, jp_off_p = 0, jp_off_sc = 0;
     int jp_off_tp = 0, jp_off_ex = 0, jp_off_tq = 0, jp_off_ns = 0, jp_off_iw = 0, jp_off_mx = 0, jp_off_mq = 0;
     int jp_nm = 0, jp_qb = 0;

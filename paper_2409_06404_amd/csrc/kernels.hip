@@ -861,7 +861,7 @@ __device__ inline void jac_seg_state(int ns, double R, double lnp0R, int wave, i
     }
 }
 
-template <bool MIXED>
+template <bool MIXED, int DMAX>
 __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n, const double *__restrict__ T,
                                                           const double *__restrict__ p, int64_t ps,
                                                           const double *__restrict__ Y, int64_t ld,
@@ -967,12 +967,12 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
                                     TQ0, MQ0, EXm, RDd, qb);
         const double Tt = SC[0], rho = SC[2], wbar = SC[3], invT = SC[6];
         // this wavefront's gather records (the same for every point; L1/L2 resident); every
-        // wavefront runs JS_DMAX rounds (the plan pads with no-op rounds), so the gather
+        // wavefront runs DMAX rounds (the plan pads with no-op rounds), so the gather
         // below is straight-line code
-        uint2 dr[JS_DMAX];
+        uint2 dr[DMAX];
 #pragma unroll
-        for (int q = 0; q < JS_DW; ++q) dr[q] = drec[q * 64 + lane];   // the first window; the
-        __syncthreads();                                                 // rest streams in below
+        for (int q = 0; q < (JS_DW < DMAX ? JS_DW : DMAX); ++q) dr[q] = drec[q * 64 + lane];   // the first window;
+        __syncthreads();                                                 // the rest streams in below
         // ---- C: software-pipelined without branches: round q + 1's values are read before
         // round q's store; the plan puts an empty round between levels, so a level's reads
         // follow the previous level's stores in program order (LDS executes a wavefront's
@@ -983,12 +983,12 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
             double v1 = lds_ld(dr[0].y & 0xfff8u);
             double v2 = lds_ld((dr[0].y >> 16) & 0xfff8u);
 #pragma unroll
-            for (int q = 0; q < JS_DMAX; ++q) {
-                if (q + JS_DW < JS_DMAX) dr[q + JS_DW < JS_DMAX ? q + JS_DW : q] = drec[(q + JS_DW) * 64 + lane];
+            for (int q = 0; q < DMAX; ++q) {
+                if (q + JS_DW < DMAX) dr[q + JS_DW < DMAX ? q + JS_DW : q] = drec[(q + JS_DW) * 64 + lane];
                 const uint2 w = dr[q];
                 const double acc = fma(cf(w.y >> 16), v2, fma(cf(w.y), v1, cf(w.x >> 16) * v0));
-                if (q + 1 < JS_DMAX) {
-                    const uint2 wn = dr[q + 1 < JS_DMAX ? q + 1 : q];
+                if (q + 1 < DMAX) {
+                    const uint2 wn = dr[q + 1 < DMAX ? q + 1 : q];
                     v0 = lds_ld((wn.x >> 16) & 0xfff8u);
                     v1 = lds_ld(wn.y & 0xfff8u);
                     v2 = lds_ld((wn.y >> 16) & 0xfff8u);
@@ -1239,19 +1239,36 @@ hipError_t launch_vjp(const DevMech &m, int mixed, int64_t n, const double *T, c
     return hipGetLastError();
 }
 
+template <int DMAX>
+hipError_t launch_jac_seg(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
+                          const double *Y, int64_t ld, void *J, double *wdot, hipStream_t st) {
+    const dim3 grid(grid_for(n, 1, 2)), block(JS_THREADS);
+    const void *fn = mixed ? (const void *)k_jac_seg<true, DMAX> : (const void *)k_jac_seg<false, DMAX>;
+    // more than 64 KB of dynamic LDS per workgroup has to be allowed explicitly
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, m.jp_lds);
+    if (e != hipSuccess) return e;
+    if (mixed)
+        hipLaunchKernelGGL((k_jac_seg<true, DMAX>), grid, block, m.jp_lds, st, m, n, T, p, ps, Y, ld, J, wdot);
+    else
+        hipLaunchKernelGGL((k_jac_seg<false, DMAX>), grid, block, m.jp_lds, st, m, n, T, p, ps, Y, ld, J, wdot);
+    return hipGetLastError();
+}
+
 hipError_t launch_jac(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
                       const double *Y, int64_t ld, void *J, double *wdot, hipStream_t st) {
     if (m.jp_ok && m.jp_lds <= JS_MAX_LDS) {
-        const dim3 grid(grid_for(n, 1, 2)), block(JS_THREADS);
-        const void *fn = mixed ? (const void *)k_jac_seg<true> : (const void *)k_jac_seg<false>;
-        // more than 64 KB of dynamic LDS per workgroup has to be allowed explicitly
-        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, m.jp_lds);
-        if (e != hipSuccess) return e;
-        if (mixed)
-            hipLaunchKernelGGL((k_jac_seg<true>), grid, block, m.jp_lds, st, m, n, T, p, ps, Y, ld, J, wdot);
-        else
-            hipLaunchKernelGGL((k_jac_seg<false>), grid, block, m.jp_lds, st, m, n, T, p, ps, Y, ld, J, wdot);
-        return hipGetLastError();
+        // the instance with the fewest gather rounds that covers the plan (every wavefront
+        // runs that many rounds in straight-line code; the plan pads with no-op rounds)
+        const int r = m.jp_rmax;
+        if (r <= 6) return launch_jac_seg<6>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 9) return launch_jac_seg<9>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 12) return launch_jac_seg<12>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 14) return launch_jac_seg<14>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 16) return launch_jac_seg<16>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 18) return launch_jac_seg<18>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 20) return launch_jac_seg<20>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 22) return launch_jac_seg<22>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        return launch_jac_seg<JS_DMAX>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
     }
     const int nsp = pad_odd(m.ns);
     const int n1 = m.ns + 1;

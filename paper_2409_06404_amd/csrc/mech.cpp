@@ -573,8 +573,10 @@ void build_jac_plan(HostMech &h) {
     };
 
     h.jp_prog.assign(8 * JS_WAVES, 0);
+    h.jp_rmax = 0;
     for (int w = 0; w < JS_WAVES; ++w) {
         h.jp_prog[8 * w + 0] = wrounds[w];
+        h.jp_rmax = std::max(h.jp_rmax, wrounds[w]);
         h.jp_prog[8 * w + 1] = w * JS_DMAX * 128;   // first 32-bit word of the wavefront's rounds
     }
     constexpr int L = JS_LD, WPL = 2, RSZ = 64 * WPL;
@@ -771,7 +773,7 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
     m.jp_thr = (const int *)at(oJt); m.jp_recs = (const unsigned *)at(oJr); m.jp_prog = (const int *)at(oJp);
     m.jp_mrx = (const int *)at(oJm); m.jp_nm = h.jp_nm; m.jp_off_mx = h.jp_off_mx; m.jp_off_mq = h.jp_off_mq;
     m.jp_qb = h.jp_qb;
-    m.jp_ok = h.jp_ok; m.jp_nd = h.jp_nd; m.jp_sr = h.jp_sr; m.jp_lds = h.jp_lds;
+    m.jp_ok = h.jp_ok; m.jp_nd = h.jp_nd; m.jp_sr = h.jp_sr; m.jp_lds = h.jp_lds; m.jp_rmax = h.jp_rmax;
     m.jp_off_a = h.jp_off_a; m.jp_off_sp = h.jp_off_sp;
     m.jp_off_row = h.jp_off_row; m.jp_off_p = h.jp_off_p; m.jp_off_sc = h.jp_off_sc;
     m.jp_off_tp = h.jp_off_tp; m.jp_off_ex = h.jp_off_ex; m.jp_off_tq = h.jp_off_tq;
