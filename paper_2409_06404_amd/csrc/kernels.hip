@@ -1261,9 +1261,13 @@ hipError_t launch_jac(const DevMech &m, int mixed, int64_t n, const double *T, c
         // runs that many rounds in straight-line code; the plan pads with no-op rounds)
         const int r = m.jp_rmax;
         if (r <= 6) return launch_jac_seg<6>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
-        if (r <= 9) return launch_jac_seg<9>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 8) return launch_jac_seg<8>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 10) return launch_jac_seg<10>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 11) return launch_jac_seg<11>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
         if (r <= 12) return launch_jac_seg<12>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 13) return launch_jac_seg<13>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
         if (r <= 14) return launch_jac_seg<14>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 15) return launch_jac_seg<15>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
         if (r <= 16) return launch_jac_seg<16>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
         if (r <= 18) return launch_jac_seg<18>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
         if (r <= 20) return launch_jac_seg<20>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);

@@ -255,11 +255,13 @@ crf_status parse_mechanism(const char *path, HostMech &h) {
 // round: it adds at most JS_LD records (byte offset of a value | dnu or +1 as a signed
 // 3-bit field) and stores the sum to its destination word (the first 16-bit field of the
 // lane's round: the LDS index of the destination in 8-byte units).  A target's tasks run
-// on one wavefront, level by level, with one empty round between levels: the kernel
-// reads a round's values during the round before, so a level's reads follow the
-// previous level's stores.  Trees are dealt to the wavefronts to balance their rounds;
-// within a round, tasks are placed on lanes (and their records ordered) so that the
-// lanes of each 16- and 32-lane group address different LDS banks where possible.
+// on one wavefront.  The kernel reads a round's values during the round before, so a task
+// that reads a partial runs at least two rounds after the task that stores it; within
+// that rule the tasks are list-scheduled (longest remaining chain first, at most 64 per
+// round), so levels of different trees share rounds.  Trees are dealt to the wavefronts
+// to balance their tasks; within a round, tasks are placed on lanes (and their records
+// ordered) so that the lanes of each 16- and 32-lane group address different LDS banks
+// where possible.
 namespace {
 
 struct PlanTask {
@@ -443,17 +445,20 @@ void build_jac_plan(HostMech &h) {
         build_tree(t, kv.second, JS_LD, nsym);
         trees.push_back(std::move(t));
     }
-    // deal the trees to the wavefronts: rounds = per level ceil(tasks / 64), plus one
-    // empty round before every level above 0; the makespan first, then the smallest
-    // increase (deep trees cluster where their levels already run), then the fewest tasks
+    // deal the trees to the wavefronts: estimated rounds = the larger of ceil(tasks / 64)
+    // and the longest chain (2 depth - 1 rounds); the makespan first, then the fewest
+    // tasks, then the smallest increase
     constexpr int MAXLV = 8;
     std::vector<std::array<int, MAXLV>> cnt(JS_WAVES);
     for (auto &c : cnt) c.fill(0);
     auto rounds_of = [&](const std::array<int, MAXLV> &lv) {
-        int r = 0;
+        int n = 0, deep = 0;
         for (int l = 0; l < MAXLV; ++l)
-            if (lv[l]) r += (lv[l] + 63) / 64 + (l > 0 ? 1 : 0);
-        return r;
+            if (lv[l]) {
+                n += lv[l];
+                deep = l + 1;
+            }
+        return std::max((n + 63) / 64, 2 * deep - 1);
     };
     std::vector<int> order(trees.size());
     for (size_t t = 0; t < trees.size(); ++t) order[t] = (int)t;
@@ -473,8 +478,8 @@ void build_jac_plan(HostMech &h) {
             const int rd = rounds_of(lv);
             if (rd > JS_DMAX) continue;
             const int nspan = std::max(span, rd), inc = rd - wrounds[w];
-            if (best < 0 || nspan < best_span || (nspan == best_span && inc < best_inc) ||
-                (nspan == best_span && inc == best_inc && wtasks[w] < wtasks[best])) {
+            if (best < 0 || nspan < best_span || (nspan == best_span && wtasks[w] < wtasks[best]) ||
+                (nspan == best_span && wtasks[w] == wtasks[best] && inc < best_inc)) {
                 best = w;
                 best_span = nspan;
                 best_inc = inc;
@@ -486,23 +491,47 @@ void build_jac_plan(HostMech &h) {
         wtasks[best] += (int)tr.tasks.size();
         wrounds[best] = rounds_of(cnt[best]);
     }
-    // rounds per wavefront: level by level, an empty round between levels, padded to JS_DMAX
+    // rounds per wavefront by list scheduling: a task is ready two rounds after the last
+    // store of a partial it reads; the ready tasks with the longest remaining chain go
+    // first, at most 64 per round; the rounds are padded to JS_DMAX
     struct Slot { int tree, task; };
     std::vector<std::vector<std::vector<Slot>>> rounds(JS_WAVES);
-    for (int w = 0; w < JS_WAVES; ++w) {
-        for (int lv = 0; lv < MAXLV; ++lv) {
-            std::vector<Slot> tasks;
+    {
+        std::vector<int> producer_round(nsym, -1);
+        for (int w = 0; w < JS_WAVES; ++w) {
+            std::vector<Slot> todo;
             for (size_t t = 0; t < trees.size(); ++t)
                 if (wave_of[t] == w)
-                    for (size_t q = 0; q < trees[t].tasks.size(); ++q)
-                        if (trees[t].tasks[q].level == lv) tasks.push_back({(int)t, (int)q});
-            if (tasks.empty()) continue;
-            if (lv > 0) rounds[w].emplace_back();
-            for (size_t c = 0; c < tasks.size(); c += 64)
-                rounds[w].emplace_back(tasks.begin() + c, tasks.begin() + std::min(c + 64, tasks.size()));
+                    for (size_t q = 0; q < trees[t].tasks.size(); ++q) todo.push_back({(int)t, (int)q});
+            auto height = [&](const Slot &sl) { return trees[sl.tree].depth - 1 - trees[sl.tree].tasks[sl.task].level; };
+            std::stable_sort(todo.begin(), todo.end(), [&](const Slot &a, const Slot &b) { return height(a) > height(b); });
+            std::vector<char> done(todo.size(), 0);
+            size_t left = todo.size();
+            for (int r = 0; left > 0; ++r) {
+                if (r >= JS_DMAX) return no("gather rounds exceed the per-wavefront register budget");
+                rounds[w].emplace_back();
+                for (size_t x = 0; x < todo.size() && rounds[w][r].size() < 64; ++x) {
+                    if (done[x]) continue;
+                    const PlanTask &tk = trees[todo[x].tree].tasks[todo[x].task];
+                    bool ready = true;
+                    for (unsigned rec : tk.recs)
+                        if (rec & PARTIAL_REC) {
+                            const int pr = producer_round[rec & ~PARTIAL_REC];
+                            ready = ready && pr >= 0 && pr <= r - 2;
+                        }
+                    if (!ready) continue;
+                    rounds[w][r].push_back(todo[x]);
+                    done[x] = 1;
+                    --left;
+                }
+                for (const Slot &sl : rounds[w][r]) {
+                    const PlanTask &tk = trees[sl.tree].tasks[sl.task];
+                    if (tk.partial) producer_round[tk.dest] = r;
+                }
+            }
+            wrounds[w] = (int)rounds[w].size();
+            rounds[w].resize(JS_DMAX);
         }
-        if ((int)rounds[w].size() > JS_DMAX) return no("gather rounds exceed the per-wavefront register budget");
-        rounds[w].resize(JS_DMAX);
     }
     // LDS slots of the partials, per wavefront with reuse: a partial lives from the round
     // that stores it to the round that reads it (whose loads are issued in the round
