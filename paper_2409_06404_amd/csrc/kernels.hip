@@ -1057,17 +1057,27 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
                 }
             };
             if (pr0 == 0) {   // the heat-release row: sum of the partial rows
-                double t0 = 0.0, tau0 = 0.0, R0 = 0.0, a0 = 0.0, a1 = 0.0;
-#pragma unroll 1
+                double pv[JS_PWAVES][5];
+#pragma unroll
                 for (int w = 0; w < JS_PWAVES; ++w) {
                     const double *Pw = P + w * sr;
-                    t0 += Pw[0];
-                    tau0 += Pw[2];
-                    R0 += Pw[3];
-                    a0 += Pw[4 + pc0];
-                    if (pc0 + 1 < n1) a1 += Pw[5 + pc0];
+                    pv[w][0] = Pw[0];
+                    pv[w][1] = Pw[2];
+                    pv[w][2] = Pw[3];
+                    pv[w][3] = Pw[4 + pc0];
+                    pv[w][4] = pc0 + 1 < n1 ? Pw[5 + pc0] : 0.0;
                 }
-                emit(0, a0, a1, rho * tau0 - wbar * R0, t0 - SC[8] - R0 * invT);
+                const double cw = SC[8];
+                double t0 = 0.0, tau0 = 0.0, R0 = 0.0, a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                for (int w = 0; w < JS_PWAVES; ++w) {
+                    t0 += pv[w][0];
+                    tau0 += pv[w][1];
+                    R0 += pv[w][2];
+                    a0 += pv[w][3];
+                    a1 += pv[w][4];
+                }
+                emit(0, a0, a1, rho * tau0 - wbar * R0, t0 - cw - R0 * invT);
             }
 #pragma unroll 2
             for (int q = 0; q < JS_EROWS; ++q) {
