@@ -48,6 +48,12 @@ struct DevMech {
     const double *wilke_c;    // [j][k]: (1/sqrt 8) (1 + W_k/W_j)^(-1/2)
     const double *dif_fit;    // [pair][4], pairs j<k in lexicographic order
     const int *pair_jk;       // [pair]: j | k << 16
+    // binary-diffusion pairs as a round-robin schedule: each of tr_rounds rounds is a
+    // perfect matching of the species (plus the dummy species ns when ns is odd), tr_slots
+    // pairs per round; tr_ok == 0 if a round does not fit half a wavefront
+    const int *tr_jk;         // [round][slot]: j | k << 16
+    const double *tr_fit;     // [round][slot][4]: the pair's ln D fit (zeros for the dummy pair)
+    int tr_rounds, tr_slots, tr_ok;
     // reactions
     const double *lnA, *b, *theta;
     const int *info;          // packed info word

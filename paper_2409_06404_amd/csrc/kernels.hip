@@ -335,7 +335,7 @@ __global__ __launch_bounds__(256) void k_thermo(DevMech m, int64_t n, const doub
 // ------------------------------------------------------------------ wdot
 // LDS per wave: PPW points x {C, g/RT, h/RT, w} x nsp doubles.
 template <bool MIXED, int PPW>
-__global__ __launch_bounds__(256) void k_wdot(DevMech m, int64_t n, const double *__restrict__ T,
+__global__ __launch_bounds__(256, 3) void k_wdot(DevMech m, int64_t n, const double *__restrict__ T,
                                               const double *__restrict__ p, int64_t ps,
                                               const double *__restrict__ Y, int64_t ld,
                                               double *__restrict__ wdot, double *__restrict__ hrr,
@@ -1093,7 +1093,7 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
 }
 
 // ------------------------------------------------------------------ transport
-// LDS per wave: PPW points x {X, mu, smu, isum} x nsp doubles (isum: sum_j X_j / D_jk).
+// LDS per wave: PPW points x {X, mu, W^(1/4)/sqrt(mu), isum} x nsp doubles (isum: sum_j X_j / D_jk).
 template <bool MIXED, int PPW>
 __global__ __launch_bounds__(256) void k_transport(DevMech m, int64_t n, const double *__restrict__ T,
                                                    const double *__restrict__ p, int64_t ps,
@@ -1132,18 +1132,41 @@ __global__ __launch_bounds__(256) void k_transport(DevMech m, int64_t n, const d
                 const double lk = (double)exp_r<Rt>((Rt)b[0] + L * ((Rt)b[1] + L * ((Rt)b[2] + L * (Rt)b[3])));
                 X[k] = x;
                 MU[k] = muk;
-                SMU[k] = sqrt(muk);
+                SMU[k] = m.w4[k] / sqrt(muk);   // W_k^(1/4) / sqrt(mu_k)
                 IS[k] = 0.0;
                 sxl += x * lk;
                 sxil += x / lk;
+            }
+            if (lane == 0) {   // the dummy species of the pair schedule
+                X[ns] = 0.0;
+                IS[ns] = 0.0;
             }
             sxl = wave_sum(sxl);
             sxil = wave_sum(sxil);
             lam_out[q] = 0.5 * (sxl + 1.0 / sxil);
         }
         wave_lds_sync();
-        // binary diffusion: lanes = pairs; sum_j X_j / D_jk by LDS scatter
-        if (Dmix) {
+        // binary diffusion, sum_j X_j / D_jk.  With the round-robin schedule, half a
+        // wavefront per point takes one round (a perfect matching of the species) at a
+        // time: every species is touched once per round, so plain read-modify-writes
+        // suffice, in a fixed order.  Otherwise lanes = pairs with LDS atomics.
+        if (Dmix && PPW == 2 && m.tr_ok) {
+            const int q = lane >> 5, sl = lane & 31;
+            double *X = base + (4 * q) * nsp, *IS = X + 3 * nsp;
+            const Rt L = (Rt)(q ? lnT[PPW - 1] : lnT[0]), lp = (Rt)(q ? lnp0p[PPW - 1] : lnp0p[0]);
+            if (sl < m.tr_slots)
+                for (int r = 0; r < m.tr_rounds; ++r) {
+                    const int e = r * m.tr_slots + sl;
+                    const int jk = m.tr_jk[e];
+                    const int j = jk & 0xffff, k = jk >> 16;
+                    const double *c = m.tr_fit + 4 * e;
+                    const Rt c0 = (Rt)c[0], c1 = (Rt)c[1], c2 = (Rt)c[2], c3 = (Rt)c[3];
+                    const double invD = (double)exp_r<Rt>(-(c0 + L * (c1 + L * (c2 + L * c3))) - lp);
+                    const double xj = X[j], xk = X[k];
+                    IS[k] += xj * invD;
+                    IS[j] += xk * invD;
+                }
+        } else if (Dmix) {
             for (int pr = lane; pr < m.n_pairs; pr += WAVE) {
                 const int jk = m.pair_jk[pr];
                 const int j = jk & 0xffff, k = jk >> 16;
@@ -1166,12 +1189,14 @@ __global__ __launch_bounds__(256) void k_transport(DevMech m, int64_t n, const d
             double *X = base + (4 * q) * nsp, *MU = X + nsp, *SMU = MU + nsp, *IS = SMU + nsp;
             double num = 0.0;
             if (mu) {
-                // Wilke: denominator_k = sum_j X_j Phi_kj, Phi_kj = c_jk (1 + sqrt(mu_k/mu_j) (W_j/W_k)^(1/4))^2
+                // Wilke: denominator_k = sum_j X_j Phi_kj, Phi_kj = c_jk (1 + sqrt(mu_k/mu_j) (W_j/W_k)^(1/4))^2,
+                // with the factor written as 1 + a_k b_j, a_k = sqrt(mu_k) / W_k^(1/4), b_j = SMU[j]
                 for (int k = lane; k < ns; k += WAVE) {
-                    const Rt smk = (Rt)SMU[k], iw4k = (Rt)m.iw4[k];
+                    const Rt ak = (Rt)(sqrt(MU[k]) * m.iw4[k]);
                     Rt den = 0;
+#pragma unroll 4
                     for (int j = 0; j < ns; ++j) {
-                        const Rt f = (Rt)1 + smk / (Rt)SMU[j] * (Rt)m.w4[j] * iw4k;
+                        const Rt f = (Rt)1 + ak * (Rt)SMU[j];
                         den += (Rt)X[j] * (Rt)m.wilke_c[(size_t)j * ns + k] * f * f;
                     }
                     num += X[k] * MU[k] / (double)den;
@@ -1307,7 +1332,7 @@ hipError_t launch_transport(const DevMech &m, int mixed, int64_t n, const double
                             int64_t ps, const double *Y, int64_t ld, double *mu, double *lam, double *Dmix,
                             hipStream_t st) {
     constexpr int PPW = 2, WPB = 4;
-    const int nsp = pad_odd(m.ns);
+    const int nsp = pad_odd(m.ns + 1);   // room for the dummy species of the pair schedule
     const size_t shm = (size_t)WPB * PPW * 4 * nsp * sizeof(double);
     const int64_t groups = (n + PPW - 1) / PPW;
     const dim3 grid(grid_for(groups, WPB, 16)), block(WPB * WAVE);

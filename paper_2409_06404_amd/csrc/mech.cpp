@@ -772,12 +772,29 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
             for (int q = 0; q < 4; ++q) dif.push_back(h.dif_full[((size_t)j * ns + k) * 4 + q]);
             pjk.push_back(j | (k << 16));
         }
+    // round-robin schedule of the species pairs (circle method): round r pairs the
+    // positions of a circle of n2 (even) entries, fixed entry 0, the others rotated
+    const int n2 = ns + (ns & 1), tr_slots = n2 / 2, tr_rounds = n2 - 1;
+    std::vector<int> tr_jk;
+    std::vector<double> tr_fit;
+    for (int r = 0; r < tr_rounds; ++r) {
+        std::vector<int> circ(n2);
+        circ[0] = 0;
+        for (int q = 1; q < n2; ++q) circ[q] = 1 + (q - 1 + r) % (n2 - 1);
+        for (int q = 0; q < tr_slots; ++q) {
+            int j = circ[q], k = circ[n2 - 1 - q];
+            if (j > k) std::swap(j, k);
+            tr_jk.push_back(j | k << 16);
+            for (int c = 0; c < 4; ++c) tr_fit.push_back(k < ns ? h.dif_full[((size_t)j * ns + k) * 4 + c] : 0.0);
+        }
+    }
     Packer P;
     size_t oW = P.add(h.W), oInvW = P.add(invW), oNasa = P.add(h.nasa), oMu = P.add(h.mu_fit),
            oLam = P.add(h.lam_fit), oW4 = P.add(w4), oIw4 = P.add(iw4), oWc = P.add(wc), oDif = P.add(dif),
            oPjk = P.add(pjk), oLnA = P.add(h.lnA), oB = P.add(h.b), oTh = P.add(h.theta), oInfo = P.add(h.info),
            oDs = P.add(h.dnu_sum), oRi = P.add(h.ri), oTroe = P.add(h.troe), oEs = P.add(h.eff_sp),
-           oEm = P.add(h.eff_m1), oJt = P.add(h.jp_thr), oJr = P.add(h.jp_recs), oJp = P.add(h.jp_prog), oJm = P.add(h.jp_mrx);
+           oEm = P.add(h.eff_m1), oJt = P.add(h.jp_thr), oJr = P.add(h.jp_recs), oJp = P.add(h.jp_prog), oJm = P.add(h.jp_mrx),
+           oTj = P.add(tr_jk), oTf = P.add(tr_fit);
     int prev = -1;
     if (hipGetDevice(&prev) != hipSuccess) return fail(CRF_E_DEVICE, "hipGetDevice failed (no HIP device?)");
     if (hipSetDevice(device) != hipSuccess) return fail(CRF_E_DEVICE, "hipSetDevice(" + std::to_string(device) + ") failed");
@@ -795,7 +812,10 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
     m.W = (const double *)at(oW); m.invW = (const double *)at(oInvW); m.nasa = (const double *)at(oNasa);
     m.mu_fit = (const double *)at(oMu); m.lam_fit = (const double *)at(oLam); m.w4 = (const double *)at(oW4);
     m.iw4 = (const double *)at(oIw4); m.wilke_c = (const double *)at(oWc); m.dif_fit = (const double *)at(oDif);
-    m.pair_jk = (const int *)at(oPjk); m.lnA = (const double *)at(oLnA); m.b = (const double *)at(oB);
+    m.pair_jk = (const int *)at(oPjk);
+    m.tr_jk = (const int *)at(oTj); m.tr_fit = (const double *)at(oTf);
+    m.tr_rounds = tr_rounds; m.tr_slots = tr_slots; m.tr_ok = tr_slots <= 32;
+    m.lnA = (const double *)at(oLnA); m.b = (const double *)at(oB);
     m.theta = (const double *)at(oTh); m.info = (const int *)at(oInfo); m.dnu_sum = (const int *)at(oDs);
     m.ri = (const RxnInts *)at(oRi); m.troe = (const double *)at(oTroe); m.eff_sp = (const int *)at(oEs);
     m.eff_m1 = (const double *)at(oEm);
