@@ -1183,32 +1183,47 @@ __global__ __launch_bounds__(256) void k_transport(DevMech m, int64_t n, const d
             }
         }
         wave_lds_sync();
+        // Wilke: denominator_k = sum_j X_j Phi_kj, Phi_kj = c_jk (1 + sqrt(mu_k/mu_j) (W_j/W_k)^(1/4))^2,
+        // with the factor written as 1 + a_k b_j, a_k = sqrt(mu_k) / W_k^(1/4), b_j = SMU[j]; the
+        // wavefront's points share each c_jk load
+        double num[PPW];
+#pragma unroll
+        for (int q = 0; q < PPW; ++q) num[q] = 0.0;
+        if (mu) {
+            for (int k = lane; k < ns; k += WAVE) {
+                const double iw4k = m.iw4[k];
+                Rt ak[PPW], den[PPW];
+#pragma unroll
+                for (int q = 0; q < PPW; ++q) {
+                    ak[q] = (Rt)(sqrt(base[(4 * q + 1) * nsp + k]) * iw4k);
+                    den[q] = 0;
+                }
+#pragma unroll 2
+                for (int j = 0; j < ns; ++j) {
+                    const Rt c = (Rt)m.wilke_c[(size_t)j * ns + k];
+#pragma unroll
+                    for (int q = 0; q < PPW; ++q) {
+                        const Rt f = (Rt)1 + ak[q] * (Rt)base[(4 * q + 2) * nsp + j];
+                        den[q] += (Rt)base[(4 * q) * nsp + j] * c * f * f;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < PPW; ++q)
+                    num[q] += base[(4 * q) * nsp + k] * base[(4 * q + 1) * nsp + k] / (double)den[q];
+            }
+#pragma unroll
+            for (int q = 0; q < PPW; ++q) num[q] = wave_sum(num[q]);
+        }
 #pragma unroll
         for (int q = 0; q < PPW; ++q) {
             const int64_t i = g * PPW + q;
-            double *X = base + (4 * q) * nsp, *MU = X + nsp, *SMU = MU + nsp, *IS = SMU + nsp;
-            double num = 0.0;
-            if (mu) {
-                // Wilke: denominator_k = sum_j X_j Phi_kj, Phi_kj = c_jk (1 + sqrt(mu_k/mu_j) (W_j/W_k)^(1/4))^2,
-                // with the factor written as 1 + a_k b_j, a_k = sqrt(mu_k) / W_k^(1/4), b_j = SMU[j]
-                for (int k = lane; k < ns; k += WAVE) {
-                    const Rt ak = (Rt)(sqrt(MU[k]) * m.iw4[k]);
-                    Rt den = 0;
-#pragma unroll 4
-                    for (int j = 0; j < ns; ++j) {
-                        const Rt f = (Rt)1 + ak * (Rt)SMU[j];
-                        den += (Rt)X[j] * (Rt)m.wilke_c[(size_t)j * ns + k] * f * f;
-                    }
-                    num += X[k] * MU[k] / (double)den;
-                }
-                num = wave_sum(num);
-            }
+            const double *IS = base + (4 * q + 3) * nsp;
             if (!valid[q]) continue;
             if (Dmix)
                 for (int k = lane; k < ns; k += WAVE)
                     Dmix[(int64_t)k * ld + i] = (1.0 - Y[(int64_t)k * ld + i]) / IS[k];
             if (lane == 0) {
-                if (mu) mu[i] = num;
+                if (mu) mu[i] = num[q];
                 if (lam) lam[i] = lam_out[q];
             }
         }
