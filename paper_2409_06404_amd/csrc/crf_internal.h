@@ -57,6 +57,7 @@ struct DevMech {
     // reactions
     const double *lnA, *b, *theta;
     const int *info;          // packed info word
+    const int *rxn_order;     // processing order of the lane-per-reaction kernels: falloff, third-body, elementary
     const int *dnu_sum;       // sum_k (nu''_k - nu'_k)
     const RxnInts *ri;
     const double *troe;       // [n_troe][8]: lnA0, b0, theta0, alpha, 1/T3, 1/T1, T2, 0

@@ -267,7 +267,7 @@ __device__ inline void eval_reaction(const DevMech &m, int r, const PointState &
         }
         if (s < MAX_SIDE) pf *= Ps[s]; else pr *= Ps[s];
     }
-    const double invKc = MIXED ? exp_split(-lnKc) : exp(-lnKc);
+    const double invKc = MIXED ? exp_split(-lnKc) : exp_fast(-lnKc);
     const double kfd = (double)kf;
     const double fac = kind == RXN_THREEBODY ? M : 1.0;
     const double krd = kfd * invKc;
@@ -356,7 +356,8 @@ __global__ __launch_bounds__(256, 3) void k_wdot(DevMech m, int64_t n, const dou
             for (int k = lane; k < m.ns; k += WAVE) Wd[k] = 0.0;
         }
         wave_lds_sync();
-        for (int r = lane; r < m.nr; r += WAVE) {
+        for (int x = lane; x < m.nr; x += WAVE) {
+            const int r = m.rxn_order[x];
             const int info = m.info[r];
             const RxnInts ri = m.ri[r];
             const double lnA = m.lnA[r], bb = m.b[r], th = m.theta[r];
@@ -401,7 +402,7 @@ __global__ __launch_bounds__(256, 3) void k_wdot(DevMech m, int64_t n, const dou
 // ------------------------------------------------------------------ VJP
 // LDS per wave: {C, g/RT, h/RT, cp/R, u, gC, w} x nsp doubles (one point at a time).
 template <bool MIXED>
-__global__ __launch_bounds__(256) void k_vjp(DevMech m, int64_t n, const double *__restrict__ T,
+__global__ __launch_bounds__(256, 3) void k_vjp(DevMech m, int64_t n, const double *__restrict__ T,
                                              const double *__restrict__ p, int64_t ps,
                                              const double *__restrict__ Y, int64_t ld,
                                              const double *__restrict__ u, const double *__restrict__ uh,
@@ -423,7 +424,8 @@ __global__ __launch_bounds__(256) void k_vjp(DevMech m, int64_t n, const double 
         wave_lds_sync();
         double a_tau = 0.0, a_t = 0.0, a_sig = 0.0;
         const double RT = m.R * st.T;
-        for (int r = lane; r < m.nr; r += WAVE) {
+        for (int x = lane; x < m.nr; x += WAVE) {
+            const int r = m.rxn_order[x];
             const int info = m.info[r];
             const RxnInts ri = m.ri[r];
             RxnEval o;
@@ -509,7 +511,8 @@ __global__ __launch_bounds__(64) void k_jac(DevMech m, int64_t n, const double *
             const bool first = r0 == 0;
             for (int e = lane; e < (r1 - r0) * sr; e += WAVE) S[e] = (Acc)0;
             wave_lds_sync();
-            for (int r = lane; r < m.nr; r += WAVE) {
+            for (int x = lane; x < m.nr; x += WAVE) {
+                const int r = m.rxn_order[x];
                 const int info = m.info[r];
                 const RxnInts ri = m.ri[r];
                 RxnEval o;
@@ -1039,8 +1042,8 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
         // ---- E
         Out *Jp = J + (size_t)i * n1 * n1;
         if (pon) {
+            const double iw0 = pc0 >= 1 ? IW[pc0 - 1] : 0.0, iw1 = pc0 < ns ? IW[pc0] : 0.0;
             auto emit = [&](int row, double a0, double a1, double al, double jt) {
-                const double iw0 = pc0 >= 1 ? IW[pc0 - 1] : 0.0, iw1 = pc0 < ns ? IW[pc0] : 0.0;
                 const Out v0 = (Out)(pc0 == 0 ? jt : (rho * a0 + al) * iw0);
                 const Out v1 = (Out)((rho * a1 + al) * iw1);
                 Out *dst = Jp + row * n1 + pc0;

@@ -788,13 +788,20 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
             for (int c = 0; c < 4; ++c) tr_fit.push_back(k < ns ? h.dif_full[((size_t)j * ns + k) * 4 + c] : 0.0);
         }
     }
+    // the lane-per-reaction kernels take 64 reactions at a time, and a wavefront pays for a
+    // branch once if any of its lanes takes it: falloff reactions first, then third-body
+    // ones, so that the longest branches run in as few groups of 64 as possible
+    std::vector<int> rxn_order;
+    for (int kind : {RXN_TROE, RXN_THREEBODY, RXN_ELEMENTARY})
+        for (int i = 0; i < nr; ++i)
+            if (info_kind(h.info[i]) == kind) rxn_order.push_back(i);
     Packer P;
     size_t oW = P.add(h.W), oInvW = P.add(invW), oNasa = P.add(h.nasa), oMu = P.add(h.mu_fit),
            oLam = P.add(h.lam_fit), oW4 = P.add(w4), oIw4 = P.add(iw4), oWc = P.add(wc), oDif = P.add(dif),
            oPjk = P.add(pjk), oLnA = P.add(h.lnA), oB = P.add(h.b), oTh = P.add(h.theta), oInfo = P.add(h.info),
            oDs = P.add(h.dnu_sum), oRi = P.add(h.ri), oTroe = P.add(h.troe), oEs = P.add(h.eff_sp),
            oEm = P.add(h.eff_m1), oJt = P.add(h.jp_thr), oJr = P.add(h.jp_recs), oJp = P.add(h.jp_prog), oJm = P.add(h.jp_mrx),
-           oTj = P.add(tr_jk), oTf = P.add(tr_fit);
+           oTj = P.add(tr_jk), oTf = P.add(tr_fit), oRo = P.add(rxn_order);
     int prev = -1;
     if (hipGetDevice(&prev) != hipSuccess) return fail(CRF_E_DEVICE, "hipGetDevice failed (no HIP device?)");
     if (hipSetDevice(device) != hipSuccess) return fail(CRF_E_DEVICE, "hipSetDevice(" + std::to_string(device) + ") failed");
@@ -816,7 +823,7 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
     m.tr_jk = (const int *)at(oTj); m.tr_fit = (const double *)at(oTf);
     m.tr_rounds = tr_rounds; m.tr_slots = tr_slots; m.tr_ok = tr_slots <= 32;
     m.lnA = (const double *)at(oLnA); m.b = (const double *)at(oB);
-    m.theta = (const double *)at(oTh); m.info = (const int *)at(oInfo); m.dnu_sum = (const int *)at(oDs);
+    m.theta = (const double *)at(oTh); m.info = (const int *)at(oInfo); m.rxn_order = (const int *)at(oRo); m.dnu_sum = (const int *)at(oDs);
     m.ri = (const RxnInts *)at(oRi); m.troe = (const double *)at(oTroe); m.eff_sp = (const int *)at(oEs);
     m.eff_m1 = (const double *)at(oEm);
     m.jp_thr = (const int *)at(oJt); m.jp_recs = (const unsigned *)at(oJr); m.jp_prog = (const int *)at(oJp);
