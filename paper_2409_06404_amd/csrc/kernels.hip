@@ -125,6 +125,13 @@ __device__ inline double lds_ld(unsigned off) { return *(const lds_f64 *)(uintpt
 __device__ inline f64x2 lds_ld2(unsigned off) { return *(const lds_f64x2 *)(uintptr_t)off; }
 __device__ inline void lds_st(unsigned off, double v) { *(lds_f64 *)(uintptr_t)off = v; }
 __device__ inline void lds_st2(unsigned off, f64x2 v) { *(lds_f64x2 *)(uintptr_t)off = v; }
+typedef __attribute__((address_space(3))) float lds_f32;
+__device__ inline float lds_ldf(unsigned off) { return *(const lds_f32 *)(uintptr_t)off; }
+__device__ inline void lds_stf(unsigned off, float v) { *(lds_f32 *)(uintptr_t)off = v; }
+// Gather values of k_jac_seg: FP64, or FP32 in the mixed mode (half the LDS bytes; a
+// value's byte offset is then half the FP64 one)
+template <bool MIXED> struct GatherT { typedef double type; };
+template <> struct GatherT<true> { typedef float type; };
 
 struct PointState {
     double T, lnT, invT, lnp0RT, rho, Wbar, Ctot, p;
@@ -649,7 +656,7 @@ template <bool MIXED>
 __device__ inline void jac_seg_reaction(int r, unsigned sp03, unsigned sp45, int dpos, int xpos, int n_exc,
                                         int exc0, int troe, int dnu, double lnA, double bb, double th,
                                         const double *SP, const double *SC, const double *TQ, const double *MQ,
-                                        const double *EXm, double *RDd, int qb) {
+                                        const double *EXm, typename GatherT<MIXED>::type *RDd, int qb) {
     using Rt = typename std::conditional<MIXED, float, double>::type;
     const int nfm = (sp45 >> 16) & 7, nrm = (sp45 >> 19) & 7, kind = (sp45 >> 22) & 3;
     const double lnT = SC[5], invT = SC[6], lnp0RT = SC[7];
@@ -717,13 +724,18 @@ __device__ inline void jac_seg_reaction(int r, unsigned sp03, unsigned sp45, int
     const double t = fac * (double)dkf_dT * bracket + fr * pr * dlnKc;
     const double mf = kind == RXN_THREEBODY ? kfd * bracket : kind == RXN_TROE ? (double)dkf_dM * bracket : 0.0;
     const double sig = (double)nfm * qf - (double)nrm * qr + mf * M;
-    double2 *qd = (double2 *)(RDd + qb + 4 * r);   // 16-byte aligned (qb even)
-    qd[0] = double2{t, qf - qr};
-    qd[1] = double2{mf, sig};
+    if constexpr (MIXED) {   // 16-byte aligned (qb a multiple of 4)
+        typedef float f32x4 __attribute__((ext_vector_type(4)));
+        *(f32x4 *)(RDd + qb + 4 * r) = f32x4{(float)t, (float)(qf - qr), (float)mf, (float)sig};
+    } else {
+        double2 *qd = (double2 *)(RDd + qb + 4 * r);
+        qd[0] = double2{t, qf - qr};
+        qd[1] = double2{mf, sig};
+    }
     // dq/dC of each molecule slot: the product of the other slots of its side
     const double dv[SLOTS] = {fk * c[1] * c[2], fk * c[0] * c[2], fk * c[0] * c[1],
                               -fr * c[4] * c[5], -fr * c[3] * c[5], -fr * c[3] * c[4]};
-    double *pos = RDd + 1 + dpos;
+    typename GatherT<MIXED>::type *pos = RDd + 1 + dpos;
 #pragma unroll
     for (int s = 0; s < MAX_SIDE; ++s)
         if (s < nfm) pos[s] = dv[s];
@@ -876,8 +888,10 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
     const int ns = m.ns, n1 = ns + 1, sr = m.jp_sr, n_troe = m.n_troe;
     constexpr int WY = JS_WAVES - 1;        // wavefront that forms the mixture state
     constexpr int WT = JS_PWAVES;           // wavefront that forms the falloff temperature terms
-    double *RDd = (double *)lds_b;
-    double *A = (double *)(lds_b + m.jp_off_a);
+    using Acc = typename GatherT<MIXED>::type;
+    constexpr unsigned VB = sizeof(Acc);                // bytes per gather value
+    Acc *RDd = (Acc *)lds_b;
+    Acc *A = (Acc *)(lds_b + m.jp_off_a / (8 / VB));  // the accumulators' index space
     double *SP0 = (double *)(lds_b + m.jp_off_sp);
     double *ROW = (double *)(lds_b + m.jp_off_row);
     double *P = (double *)(lds_b + m.jp_off_p);
@@ -981,22 +995,28 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
         // follow the previous level's stores in program order (LDS executes a wavefront's
         // operations in order)
         {
-            auto cf = [](unsigned rec) { return (double)(int)__builtin_amdgcn_sbfe((int)rec, 0, 3); };
-            double v0 = lds_ld((dr[0].x >> 16) & 0xfff8u);
-            double v1 = lds_ld(dr[0].y & 0xfff8u);
-            double v2 = lds_ld((dr[0].y >> 16) & 0xfff8u);
+            // a record holds 8 x the value's index (FP64 byte offset) over its 3-bit coefficient
+            auto cf = [](unsigned rec) { return (Acc)(int)__builtin_amdgcn_sbfe((int)rec, 0, 3); };
+            auto ld = [](unsigned rec8) -> Acc {
+                if constexpr (MIXED) return lds_ldf(rec8 >> 1);
+                else return lds_ld(rec8);
+            };
+            Acc v0 = ld((dr[0].x >> 16) & 0xfff8u);
+            Acc v1 = ld(dr[0].y & 0xfff8u);
+            Acc v2 = ld((dr[0].y >> 16) & 0xfff8u);
 #pragma unroll
             for (int q = 0; q < DMAX; ++q) {
                 if (q + JS_DW < DMAX) dr[q + JS_DW < DMAX ? q + JS_DW : q] = drec[(q + JS_DW) * 64 + lane];
                 const uint2 w = dr[q];
-                const double acc = fma(cf(w.y >> 16), v2, fma(cf(w.y), v1, cf(w.x >> 16) * v0));
+                const Acc acc = fma(cf(w.y >> 16), v2, fma(cf(w.y), v1, cf(w.x >> 16) * v0));
                 if (q + 1 < DMAX) {
                     const uint2 wn = dr[q + 1 < DMAX ? q + 1 : q];
-                    v0 = lds_ld((wn.x >> 16) & 0xfff8u);
-                    v1 = lds_ld(wn.y & 0xfff8u);
-                    v2 = lds_ld((wn.y >> 16) & 0xfff8u);
+                    v0 = ld((wn.x >> 16) & 0xfff8u);
+                    v1 = ld(wn.y & 0xfff8u);
+                    v2 = ld((wn.y >> 16) & 0xfff8u);
                 }
-                lds_st(8u * (w.x & 0xffffu), acc);
+                if constexpr (MIXED) lds_stf(4u * (w.x & 0xffffu), acc);
+                else lds_st(8u * (w.x & 0xffffu), acc);
                 __builtin_amdgcn_sched_barrier(0);   // keeps the record stream JS_DW rounds ahead
             }
         }
@@ -1018,7 +1038,16 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
         } else if (wave == JS_PWAVES) {
             double cwp = 0.0;
             for (int k = lane; k < ns; k += WAVE) {
-                const double2 q01 = *(const double2 *)(A + k * sr), q23 = *(const double2 *)(A + k * sr + 2);
+                double2 q01, q23;
+                if constexpr (MIXED) {   // 8-byte aligned pairs (sr even)
+                    typedef float f32x2 __attribute__((ext_vector_type(2)));
+                    const f32x2 a01 = *(const f32x2 *)(A + k * sr), a23 = *(const f32x2 *)(A + k * sr + 2);
+                    q01 = double2{a01.x, a01.y};
+                    q23 = double2{a23.x, a23.y};
+                } else {
+                    q01 = *(const double2 *)(A + k * sr);
+                    q23 = *(const double2 *)(A + k * sr + 2);
+                }
                 *(double2 *)(ROW + 2 * k) = double2{rho * q23.x - wbar * q23.y, q01.x - q23.y * invT};
                 cwp += SP[4 * k + 3] * q01.y;
                 if (wdot) wdot[(int64_t)k * ld + i] = q01.y;
@@ -1086,7 +1115,8 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
             for (int q = 0; q < JS_EROWS; ++q) {
                 const int row = pr0 + q * rphase;
                 if (row >= 1 && row < n1) {
-                    const f64x2 av = *(const f64x2 *)(A + (row - 1) * sr + 4 + pc0);   // 16-byte aligned
+                    typedef Acc Acc2 __attribute__((ext_vector_type(2)));
+                    const Acc2 av = *(const Acc2 *)(A + (row - 1) * sr + 4 + pc0);   // aligned pair
                     const f64x2 rw = *(const f64x2 *)(ROW + 2 * (row - 1));
                     emit(row, av.x, av.y, rw.x, rw.y);
                 }

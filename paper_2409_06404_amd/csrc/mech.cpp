@@ -246,7 +246,7 @@ crf_status parse_mechanism(const char *path, HostMech &h) {
 //                          a species with coefficient nu fills nu slots)
 //   x = 1 + xpos_i + e     dq_i/d[M] (eps - 1) for efficiency exception e of reaction i
 //   x = qb + 4 i + c       c = 0: dq_i/dT at fixed C, 1: q_i, 2: dq_i/d[M],
-//                          3: sum_j C_j dq_i/dC_j  (qb even: 16-byte aligned pairs)
+//                          3: sum_j C_j dq_i/dC_j  (qb a multiple of 4: aligned quads)
 //   x = pb + p             partial sums of the gather
 // The accumulator matrix A (species rows k, stride sr, FP64) is plain sums of these:
 //   A[k][c]     = sum_i dnu_ki value(qb + 4 i + c),  c = 0..3
@@ -366,7 +366,7 @@ void build_jac_plan(HostMech &h) {
         xpos[i] = nd;
         nd += h.ri[i].v[7] & 255;
     }
-    const int qb = (1 + nd + 1) / 2 * 2;          // first quad value (even index)
+    const int qb = (1 + nd + 3) / 4 * 4;          // first quad value (a multiple of 4: 16-byte quads in FP32)
     const int pb = qb + 4 * nr;                   // first partial
     const int sr = (ns + 5 + 1) / 2 * 2;
     h.jp_nd = nd;
