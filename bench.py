@@ -75,6 +75,48 @@ def timed(fn, steps, warmup, stream):
     return start.elapsed_time(stop) / steps      # ms per call
 
 
+def supporting_c4(crf, steps):
+    """Supporting figures on the 200-species / 1500-reaction mechanism (300 third-body,
+    150 Troe) at 40 atm: one launch of 1000 spectral elements of 8^3 points with flame
+    fronts (512 000 points): production rates, transport and VJP in both modes, and the
+    mixed-mode Jacobian (FP32, 201 x 201 per point) on a chunk of 2^15 points."""
+    import numpy as np
+    import torch
+
+    import synth
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    with tempfile.TemporaryDirectory() as d:
+        path = synth.write_mechanism(synth.MECH_C4, os.path.join(d, "c4.mech"))
+        m = crf.Mechanism(path, device=0)
+        ns = m.n_species
+        st = synth.state_c4_launch(ns, 1000, seed=4, launch=0)
+        n = st["T"].shape[0]
+        T = torch.from_numpy(st["T"]).to(dev)
+        p = torch.from_numpy(st["p"]).to(dev)
+        Y = torch.from_numpy(np.ascontiguousarray(st["Y"])).to(dev).t()
+        u = torch.randn((ns, n), dtype=torch.float64, device=dev).t()
+        out = {"workload": "200 species / 1500 reactions (300 third-body, 150 Troe), 40 atm, "
+                           "1000 elements x 8^3 points", "n_points": n, "unit": "Mpoints/s"}
+        for prec in ("fp64", "mixed"):
+            out[prec] = {
+                "wdot": n / (timed(lambda: crf.wdot(m, T, p, Y, prec, hrr=True), steps, 1, stream) * 1e-3) / 1e6,
+                "transport": n / (timed(lambda: crf.transport(m, T, p, Y, prec), steps, 1, stream) * 1e-3) / 1e6,
+                "vjp": n / (timed(lambda: crf.wdot_vjp(m, T, p, Y, u, None, prec), steps, 1, stream) * 1e-3) / 1e6,
+            }
+        nj = 1 << 15
+        J = torch.empty((nj, ns + 1, ns + 1), dtype=torch.float32, device=dev)
+        Tj, pj, Yj = T[:nj], p[:nj], Y[:nj]
+        ms = timed(lambda: crf.wdot_jac(m, Tj, pj, Yj, "mixed", out=J), steps, 1, stream)
+        out["mixed"]["jac_chunk"] = nj / (ms * 1e-3) / 1e6
+        out["jac_chunk_points"] = nj
+        out["jac_plan"] = m.jac_plan
+        del J
+        m.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(mech_path, st, n_sample):
     """The FP64 numpy oracle (production rates + analytic Jacobian) on a bounded sample."""
     import numpy as np
@@ -106,6 +148,7 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (the reference for HBM byte counters)")
     ap.add_argument("--no-path", action="store_true", help="time the fused wdot+Jacobian call only")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 200-species supporting figures")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -179,6 +222,8 @@ def main():
         if "mixed" in res and head != "mixed":
             out["mixed"] = dict(res["mixed"], dtype="f32+f64")
         out["path_mpoints_per_s"] = path
+        if not (args.no_path or args.no_c4):
+            out["supporting"] = {"c4_200sp": supporting_c4(crf, max(3, args.steps // 4))}
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline(mech_path, st, args.cpu_sample)
     print(json.dumps(out), flush=True)

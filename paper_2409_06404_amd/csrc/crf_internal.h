@@ -36,7 +36,7 @@ struct alignas(16) RxnInts { int v[8]; };
 
 // Device tables of one mechanism; pointers into a single device allocation.
 struct DevMech {
-    int ns, nr, n_troe, n_exc, n_pairs;
+    int ns, nr, n_troe, n_exc;
     double R, p0;
     // species
     const double *W, *invW;
@@ -46,14 +46,12 @@ struct DevMech {
     const double *w4;         // W^(1/4)
     const double *iw4;        // W^(-1/4)
     const double *wilke_c;    // [j][k]: (1/sqrt 8) (1 + W_k/W_j)^(-1/2)
-    const double *dif_fit;    // [pair][4], pairs j<k in lexicographic order
-    const int *pair_jk;       // [pair]: j | k << 16
     // binary-diffusion pairs as a round-robin schedule: each of tr_rounds rounds is a
     // perfect matching of the species (plus the dummy species ns when ns is odd), tr_slots
-    // pairs per round; tr_ok == 0 if a round does not fit half a wavefront
+    // pairs per round
     const int *tr_jk;         // [round][slot]: j | k << 16
     const double *tr_fit;     // [round][slot][4]: the pair's ln D fit (zeros for the dummy pair)
-    int tr_rounds, tr_slots, tr_ok;
+    int tr_rounds, tr_slots;
     // reactions
     const double *lnA, *b, *theta;
     const int *info;          // packed info word

@@ -1179,17 +1179,18 @@ __global__ __launch_bounds__(256) void k_transport(DevMech m, int64_t n, const d
             lam_out[q] = 0.5 * (sxl + 1.0 / sxil);
         }
         wave_lds_sync();
-        // binary diffusion, sum_j X_j / D_jk.  With the round-robin schedule, half a
-        // wavefront per point takes one round (a perfect matching of the species) at a
-        // time: every species is touched once per round, so plain read-modify-writes
-        // suffice, in a fixed order.  Otherwise lanes = pairs with LDS atomics.
-        if (Dmix && PPW == 2 && m.tr_ok) {
+        // binary diffusion, sum_j X_j / D_jk, on the round-robin schedule: half a wavefront
+        // per point takes one round (a perfect matching of the species) at a time, 32 pairs
+        // at a time; every species is touched once per round, so plain read-modify-writes
+        // suffice, in a fixed order
+        static_assert(PPW == 2, "one point per half wavefront");
+        if (Dmix) {
             const int q = lane >> 5, sl = lane & 31;
             double *X = base + (4 * q) * nsp, *IS = X + 3 * nsp;
             const Rt L = (Rt)(q ? lnT[PPW - 1] : lnT[0]), lp = (Rt)(q ? lnp0p[PPW - 1] : lnp0p[0]);
-            if (sl < m.tr_slots)
-                for (int r = 0; r < m.tr_rounds; ++r) {
-                    const int e = r * m.tr_slots + sl;
+            for (int r = 0; r < m.tr_rounds; ++r)
+                for (int sc = sl; sc < m.tr_slots; sc += 32) {
+                    const int e = r * m.tr_slots + sc;
                     const int jk = m.tr_jk[e];
                     const int j = jk & 0xffff, k = jk >> 16;
                     const double *c = m.tr_fit + 4 * e;
@@ -1199,21 +1200,6 @@ __global__ __launch_bounds__(256) void k_transport(DevMech m, int64_t n, const d
                     IS[k] += xj * invD;
                     IS[j] += xk * invD;
                 }
-        } else if (Dmix) {
-            for (int pr = lane; pr < m.n_pairs; pr += WAVE) {
-                const int jk = m.pair_jk[pr];
-                const int j = jk & 0xffff, k = jk >> 16;
-                const double *c = m.dif_fit + 4 * pr;
-                const Rt c0 = (Rt)c[0], c1 = (Rt)c[1], c2 = (Rt)c[2], c3 = (Rt)c[3];
-#pragma unroll
-                for (int q = 0; q < PPW; ++q) {
-                    double *X = base + (4 * q) * nsp, *IS = X + 3 * nsp;
-                    const Rt L = (Rt)lnT[q];
-                    const double invD = (double)exp_r<Rt>(-(c0 + L * (c1 + L * (c2 + L * c3))) - (Rt)lnp0p[q]);
-                    atomicAdd(&IS[k], X[j] * invD);
-                    atomicAdd(&IS[j], X[k] * invD);
-                }
-            }
         }
         wave_lds_sync();
         // Wilke: denominator_k = sum_j X_j Phi_kj, Phi_kj = c_jk (1 + sqrt(mu_k/mu_j) (W_j/W_k)^(1/4))^2,

@@ -765,13 +765,6 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
     for (int j = 0; j < ns; ++j)
         for (int k = 0; k < ns; ++k)
             wc[(size_t)j * ns + k] = 1.0 / std::sqrt(8.0 * (1.0 + h.W[k] / h.W[j]));
-    std::vector<double> dif;
-    std::vector<int> pjk;
-    for (int j = 0; j < ns; ++j)
-        for (int k = j + 1; k < ns; ++k) {
-            for (int q = 0; q < 4; ++q) dif.push_back(h.dif_full[((size_t)j * ns + k) * 4 + q]);
-            pjk.push_back(j | (k << 16));
-        }
     // round-robin schedule of the species pairs (circle method): round r pairs the
     // positions of a circle of n2 (even) entries, fixed entry 0, the others rotated
     const int n2 = ns + (ns & 1), tr_slots = n2 / 2, tr_rounds = n2 - 1;
@@ -797,8 +790,8 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
             if (info_kind(h.info[i]) == kind) rxn_order.push_back(i);
     Packer P;
     size_t oW = P.add(h.W), oInvW = P.add(invW), oNasa = P.add(h.nasa), oMu = P.add(h.mu_fit),
-           oLam = P.add(h.lam_fit), oW4 = P.add(w4), oIw4 = P.add(iw4), oWc = P.add(wc), oDif = P.add(dif),
-           oPjk = P.add(pjk), oLnA = P.add(h.lnA), oB = P.add(h.b), oTh = P.add(h.theta), oInfo = P.add(h.info),
+           oLam = P.add(h.lam_fit), oW4 = P.add(w4), oIw4 = P.add(iw4), oWc = P.add(wc),
+           oLnA = P.add(h.lnA), oB = P.add(h.b), oTh = P.add(h.theta), oInfo = P.add(h.info),
            oDs = P.add(h.dnu_sum), oRi = P.add(h.ri), oTroe = P.add(h.troe), oEs = P.add(h.eff_sp),
            oEm = P.add(h.eff_m1), oJt = P.add(h.jp_thr), oJr = P.add(h.jp_recs), oJp = P.add(h.jp_prog), oJm = P.add(h.jp_mrx),
            oTj = P.add(tr_jk), oTf = P.add(tr_fit), oRo = P.add(rxn_order);
@@ -815,13 +808,12 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
     auto at = [&](size_t off) { return (const void *)((const unsigned char *)d + off); };
     DevMech &m = mm->dev;
     m.ns = ns; m.nr = nr; m.n_troe = (int)(h.troe.size() / 8); m.n_exc = (int)h.eff_sp.size();
-    m.n_pairs = (int)pjk.size(); m.R = h.R; m.p0 = h.p0;
+    m.R = h.R; m.p0 = h.p0;
     m.W = (const double *)at(oW); m.invW = (const double *)at(oInvW); m.nasa = (const double *)at(oNasa);
     m.mu_fit = (const double *)at(oMu); m.lam_fit = (const double *)at(oLam); m.w4 = (const double *)at(oW4);
-    m.iw4 = (const double *)at(oIw4); m.wilke_c = (const double *)at(oWc); m.dif_fit = (const double *)at(oDif);
-    m.pair_jk = (const int *)at(oPjk);
+    m.iw4 = (const double *)at(oIw4); m.wilke_c = (const double *)at(oWc);
     m.tr_jk = (const int *)at(oTj); m.tr_fit = (const double *)at(oTf);
-    m.tr_rounds = tr_rounds; m.tr_slots = tr_slots; m.tr_ok = tr_slots <= 32;
+    m.tr_rounds = tr_rounds; m.tr_slots = tr_slots;
     m.lnA = (const double *)at(oLnA); m.b = (const double *)at(oB);
     m.theta = (const double *)at(oTh); m.info = (const int *)at(oInfo); m.rxn_order = (const int *)at(oRo); m.dnu_sum = (const int *)at(oDs);
     m.ri = (const RxnInts *)at(oRi); m.troe = (const double *)at(oTroe); m.eff_sp = (const int *)at(oEs);
