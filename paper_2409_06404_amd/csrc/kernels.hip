@@ -12,8 +12,10 @@
 // reaction constants are read from the mechanism tables (the same addresses for
 // every wave, so they stay in L1/L2), and the sparse stoichiometric reductions
 // (w_k = sum_i dnu_ki q_i and the Jacobian assembly) are scatters into LDS with
-// native ds_add_f64 / ds_add_f32.  Every LDS address is owned by one wave, so the
-// order of additions is fixed by the program and results are reproducible.
+// native ds_add_f64 / ds_add_f32.  In the production-rate and VJP kernels every LDS
+// address is owned by one wave, so the order of additions is fixed by the program and
+// results are reproducible; the row-block Jacobian shares a point's rows between four
+// wavefronts, so its sums are reproducible to rounding only.
 //
 // Thermodynamics (crf_thermo) is point-parallel instead: lane = point, species
 // loop uniform, coefficients via scalar loads, fully coalesced stores.
@@ -153,7 +155,7 @@ __device__ inline void nasa7(const double *c16, double T, double lnT, double inv
 template <bool NEED_H, bool NEED_CP>
 __device__ inline PointState load_point(const DevMech &m, int64_t i, int64_t n, const double *T,
                                         const double *p, int64_t ps, const double *Y, int64_t ld,
-                                        double *C, double *gRT, double *hRT, double *cpR) {
+                                        double *C, double *gRT, double *hRT, double *cpR, bool store = true) {
     const int lane = threadIdx.x & (WAVE - 1);
     PointState s;
     s.valid = i < n;
@@ -173,10 +175,12 @@ __device__ inline PointState load_point(const DevMech &m, int64_t i, int64_t n, 
         const double c = s.rho * Y[(int64_t)k * ld + ii] * m.invW[k];
         double cp, h, sr;
         nasa7(m.nasa + 16 * k, s.T, s.lnT, s.invT, cp, h, sr);
-        C[k] = c;
-        gRT[k] = h - sr;
-        if (NEED_H) hRT[k] = h;
-        if (NEED_CP) cpR[k] = cp;
+        if (store) {
+            C[k] = c;
+            gRT[k] = h - sr;
+            if (NEED_H) hRT[k] = h;
+            if (NEED_CP) cpR[k] = cp;
+        }
         ct += c;
     }
     s.Ctot = wave_sum(ct);
@@ -489,17 +493,23 @@ __global__ __launch_bounds__(256, 3) void k_vjp(DevMech m, int64_t n, const doub
 // R = sum_i dnu_i sum_j C_j dq_i/dC_j, jtc = sum_i dnu_i dq_i/dT at fixed C.
 // With 53 species the whole matrix is one block; larger mechanisms repeat the
 // reaction pass per block instead of exceeding one wavefront's LDS.
-// LDS per wave: {C, g/RT, h/RT, cp/R} x nsp and {tau, jtc, R, w} x (nsp+1)
-// doubles, plus rb x sr FP64 accumulators (the mixed mode stores J in FP32).
+// One workgroup of KJ_WAVES wavefronts per point shares the LDS: {C, g/RT, h/RT, cp/R} x nsp
+// and {tau, jtc, R, w} x (nsp+1) doubles, plus rb x sr FP64 accumulators (the mixed mode
+// stores J in FP32).  The wavefronts split the reactions of every pass; the rows of a
+// block accumulate through LDS atomics.
+constexpr int KJ_WAVES = 4;
 template <bool MIXED>
-__global__ __launch_bounds__(64) void k_jac(DevMech m, int64_t n, const double *__restrict__ T,
-                                            const double *__restrict__ p, int64_t ps,
-                                            const double *__restrict__ Y, int64_t ld, void *__restrict__ Jv,
-                                            double *__restrict__ wdot, int nsp, int sr, int rb) {
+__global__ __launch_bounds__(KJ_WAVES * 64) void k_jac(DevMech m, int64_t n, const double *__restrict__ T,
+                                                       const double *__restrict__ p, int64_t ps,
+                                                       const double *__restrict__ Y, int64_t ld,
+                                                       void *__restrict__ Jv, double *__restrict__ wdot, int nsp,
+                                                       int sr, int rb) {
     using Out = typename std::conditional<MIXED, float, double>::type;
     using Acc = double;     // accumulate in FP64 in both modes; the mixed mode stores FP32
     extern __shared__ double lds[];
-    const int lane = threadIdx.x & (WAVE - 1);
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    constexpr int NT = KJ_WAVES * WAVE;
     const int ns = m.ns, n1 = ns + 1;
     double *C = lds, *G = C + nsp, *H = G + nsp, *CP = H + nsp;
     double *TAU = CP + nsp, *JTC = TAU + (nsp + 1), *RC = JTC + (nsp + 1), *Wd = RC + (nsp + 1);
@@ -507,18 +517,18 @@ __global__ __launch_bounds__(64) void k_jac(DevMech m, int64_t n, const double *
     Out *J = (Out *)Jv;
     const float inv_n1 = 1.0f / (float)n1;
     for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
-        wave_lds_sync();
-        const PointState st = load_point<true, true>(m, i, n, T, p, ps, Y, ld, C, G, H, CP);
-        for (int k = lane; k <= ns; k += WAVE) { TAU[k] = 0.0; JTC[k] = 0.0; RC[k] = 0.0; Wd[k] = 0.0; }
+        __syncthreads();
+        // every wavefront forms the point scalars; wavefront 0 stores the species arrays
+        const PointState st = load_point<true, true>(m, i, n, T, p, ps, Y, ld, C, G, H, CP, wave == 0);
+        for (int k = tid; k <= ns; k += NT) { TAU[k] = 0.0; JTC[k] = 0.0; RC[k] = 0.0; Wd[k] = 0.0; }
         const double RT = m.R * st.T;
-        double cw = 0.0;
         Out *Jp = J + (size_t)i * n1 * n1;
         for (int r0 = 0; r0 < n1; r0 += rb) {
             const int r1 = r0 + rb < n1 ? r0 + rb : n1;
             const bool first = r0 == 0;
-            for (int e = lane; e < (r1 - r0) * sr; e += WAVE) S[e] = (Acc)0;
-            wave_lds_sync();
-            for (int x = lane; x < m.nr; x += WAVE) {
+            for (int e = tid; e < (r1 - r0) * sr; e += NT) S[e] = (Acc)0;
+            __syncthreads();
+            for (int x = tid; x < m.nr; x += NT) {
                 const int r = m.rxn_order[x];
                 const int info = m.info[r];
                 const RxnInts ri = m.ri[r];
@@ -573,10 +583,10 @@ __global__ __launch_bounds__(64) void k_jac(DevMech m, int64_t n, const double *
                     }
                 }
             }
-            wave_lds_sync();
-            if (first) {
-                // row 0 scalars: tau_0, jtc_0, R_0 = -sum_k h_k (...)_k ; sum cp_k w_k
-                double t0 = 0.0, j0 = 0.0, q0 = 0.0;
+            __syncthreads();
+            if (first && wave == 0) {
+                // row 0 scalars: tau_0, jtc_0, R_0 = -sum_k h_k (...)_k; sum cp_k w_k (in Wd[0])
+                double t0 = 0.0, j0 = 0.0, q0 = 0.0, cw = 0.0;
                 for (int k = lane; k < ns; k += WAVE) {
                     const double hk = RT * H[k];
                     t0 -= hk * TAU[1 + k];
@@ -585,14 +595,14 @@ __global__ __launch_bounds__(64) void k_jac(DevMech m, int64_t n, const double *
                     cw += m.R * CP[k] * Wd[1 + k];
                 }
                 t0 = wave_sum(t0); j0 = wave_sum(j0); q0 = wave_sum(q0); cw = wave_sum(cw);
-                if (lane == 0) { TAU[0] = t0; JTC[0] = j0; RC[0] = q0; }
-                wave_lds_sync();
+                if (lane == 0) { TAU[0] = t0; JTC[0] = j0; RC[0] = q0; Wd[0] = cw; }
             }
-            // emission of rows r0..r1-1: two consecutive entries per lane, 128 per pass
+            if (first) __syncthreads();
+            // emission of rows r0..r1-1: two consecutive entries per thread, 2 NT per pass
             const int e_lo = r0 * n1, e_hi = r1 * n1;
             // paired stores need a 2-element-aligned address (e0 has the parity of e_lo)
             const bool vec_ok = (((uintptr_t)(Jp + e_lo)) & (2 * sizeof(Out) - 1)) == 0;
-            for (int e0 = e_lo + 2 * lane; e0 < e_hi; e0 += 2 * WAVE) {
+            for (int e0 = e_lo + 2 * tid; e0 < e_hi; e0 += 2 * NT) {
                 Out v[2];
 #pragma unroll
                 for (int t = 0; t < 2; ++t) {
@@ -607,7 +617,7 @@ __global__ __launch_bounds__(64) void k_jac(DevMech m, int64_t n, const double *
                         const double Rr = RC[row];
                         if (c == 0) {
                             x = JTC[row] - Rr * st.invT;
-                            if (row == 0) x -= cw;
+                            if (row == 0) x -= Wd[0];
                         } else {
                             x = (st.rho * ((double)S[(row - r0) * sr + c - 1] + TAU[row]) - st.Wbar * Rr) * m.invW[c - 1];
                         }
@@ -623,10 +633,10 @@ __global__ __launch_bounds__(64) void k_jac(DevMech m, int64_t n, const double *
                     if (e0 + 1 < e_hi) Jp[e0 + 1] = v[1];
                 }
             }
-            wave_lds_sync();
+            __syncthreads();
         }
         if (wdot)
-            for (int k = lane; k < ns; k += WAVE) wdot[(int64_t)k * ld + i] = Wd[1 + k];
+            for (int k = tid; k < ns; k += NT) wdot[(int64_t)k * ld + i] = Wd[1 + k];
     }
 }
 
@@ -1348,13 +1358,16 @@ hipError_t launch_jac(const DevMech &m, int mixed, int64_t n, const double *T, c
     const int sr = pad_odd(n1);
     const size_t acc = sizeof(double);
     const size_t fixed = (size_t)(4 * nsp + 4 * (nsp + 1)) * sizeof(double);
-    // rows per block: the whole matrix when it fits in ~48 KB, else as many rows as fit
-    const size_t budget = 48 * 1024;
+    // rows per block: as many as fit one compute unit's LDS (one workgroup per point)
+    const size_t budget = 160 * 1024 - 256;
     int rb = (int)((budget > fixed ? budget - fixed : 0) / ((size_t)sr * acc));
     if (rb >= n1) rb = n1;
     if (rb < 1) return hipErrorInvalidValue;
     const size_t shm = fixed + (size_t)rb * sr * acc;
-    const dim3 grid(grid_for(n, 1, 8)), block(WAVE);
+    const void *fn = mixed ? (const void *)k_jac<true> : (const void *)k_jac<false>;
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    const dim3 grid(grid_for(n, 1, 1)), block(KJ_WAVES * WAVE);
     if (mixed)
         hipLaunchKernelGGL((k_jac<true>), grid, block, shm, st, m, n, T, p, ps, Y, ld, J, wdot, nsp, sr, rb);
     else

@@ -113,3 +113,19 @@ def test_c4_transport(c4):
     assert np.max(np.abs(mu.cpu().numpy() / ref["mu"] - 1)) <= 1e-12
     assert np.max(np.abs(lam.cpu().numpy() / ref["lambda"] - 1)) <= 1e-12
     assert np.max(np.abs(D.cpu().numpy() / ref["Dmix"] - 1)) <= 1e-12
+
+
+def test_c4_jacobian_run_to_run(c4):
+    """The row-block Jacobian sums a point's rows over four wavefronts with LDS atomics:
+    two runs agree to FP64 rounding (1e-13 of each row's largest entry)."""
+    crf, g, om = c4
+    st = synth.state_c4_launch(200, 1, seed=4, launch=7)
+    idx = np.arange(0, 512, 16)
+    s = _sub(st, idx)
+    T, p, Y = _dev(s)
+    Ja = crf.wdot_jac(g, T, p, Y, "fp64")[0].clone()
+    Jb = crf.wdot_jac(g, T, p, Y, "fp64")[0].clone()
+    torch.cuda.synchronize()
+    a, b = Ja.cpu().numpy(), Jb.cpu().numpy()
+    scale = np.abs(a).max(axis=2, keepdims=True)
+    assert np.max(np.abs(a - b) / np.where(scale > 0, scale, 1.0)) <= 1e-13
