@@ -89,7 +89,7 @@ int crf_device(const crf_mech *m);        /* device the tables live on, -1 for h
 
 /* Which kernel crf_wdot_jac runs for this mechanism: "segmented" (one workgroup per
  * point, one reaction per thread, lockstep gather of the derivative sums; needs at
- * most 384 reactions, 64 species, 3 molecules per side and 64 KB of LDS) or
+ * most 384 reactions, 64 species, 3 molecules per side and 80 KB of LDS) or
  * "row-block (<reason>)" for the general kernel.  Informational; the string is owned
  * by the mechanism and valid until the next call on it or crf_free_mech. "" for NULL. */
 const char *crf_jac_plan(const crf_mech *m);
@@ -146,7 +146,10 @@ crf_status crf_wdot_vjp(const crf_mech *m, crf_precision prec, int64_t n, const 
  * row-major per point: with N1 = Ns + 1, entry (r, c) of point i is
  * J[i * N1 * N1 + r * N1 + c]; row 0 = hrr, row 1 + k = w_k; column 0 = T,
  * column 1 + j = Y_j.  J holds doubles for CRF_FP64 and floats for CRF_MIXED.
- * wdot (nullable) receives the production rates of the same evaluation, [k*ld + i]. */
+ * wdot (nullable) receives the production rates of the same evaluation, [k*ld + i]
+ * (with CRF_MIXED and the segmented kernel, summed in FP32).  Results are bitwise
+ * reproducible run to run with the segmented kernel; the row-block kernel sums a
+ * point's rows over several wavefronts with LDS atomics, reproducible to rounding. */
 crf_status crf_wdot_jac(const crf_mech *m, crf_precision prec, int64_t n, const double *T,
                         const double *p, int64_t p_stride, const double *Y, int64_t ld,
                         void *J, double *wdot, crf_stream stream);
