@@ -6,9 +6,11 @@ Workload: the 53-species / 325-reaction mechanism (40 three-body, 25 Troe fallof
 One step = one fused crf_wdot_jac call (state, thermo, rate constants, falloff,
 equilibrium constants, rates of progress, production rates and the dense Jacobian)
 over the whole batch.  The rest of the per-point path (thermo, transport, VJP) is
-timed in the same run and reported under "path".
+timed in the same run and reported under "path_mpoints_per_s"; "supporting" holds the
+200-species figures (one launch of 1000 spectral elements of 8^3 points at 40 atm; the
+mixed Jacobian on a chunk of 2^15 points).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-path] [--no-c4]
 
 Prints one JSON line.
 """
