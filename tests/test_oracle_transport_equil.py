@@ -53,6 +53,64 @@ def test_identical_species_mixture(tmp_path):
     assert tp["lambda"][0] == pytest.approx(math.exp(-3.0 + 0.8 * L), rel=1e-14)
 
 
+def test_binary_wilke_and_mathur_saxena_unequal_masses(tmp_path):
+    """Hand-worked binary mixture: W_B = 4 W_A, mu_A = 4 mu_B, lambda_A = 4 lambda_B, and
+    Y = (0.2, 0.8), which gives X = (1/2, 1/2), so X differs from Y.
+
+    Wilke, with (mu_A/mu_B)^(1/2) = 2 and (W_B/W_A)^(1/4) = 2^(1/2):
+      Phi_AB = 8^(-1/2) (1 + 1/4)^(-1/2) (1 + 2 2^(1/2))^2 = (9 + 4 2^(1/2)) / 10^(1/2)
+      Phi_BA = 8^(-1/2) (1 + 4)^(-1/2) (1 + 2^(-3/2))^2   = (9/8 + 2^(-1/2)) / 40^(1/2)
+      mu = X_A mu_A / (X_A + X_B Phi_AB) + X_B mu_B / (X_B + X_A Phi_BA)
+         = mu_A / (1 + Phi_AB) + mu_B / (1 + Phi_BA)          (X_A = X_B)
+    Mathur-Saxena, lambda_A = 0.1, lambda_B = 0.025:
+      sum X lambda = 0.0625, sum X / lambda = 25, lambda = (0.0625 + 1/25) / 2 = 0.05125.
+    Swapping W_j/W_k inside Phi, or weighting by Y instead of X, changes both values.
+    """
+    mu_a, mu_b = 4e-5, 1e-5
+    mu = [[math.log(mu_a), 0.0, 0.0, 0.0], [math.log(mu_b), 0.0, 0.0, 0.0]]
+    lam = [[math.log(0.1), 0.0, 0.0, 0.0], [math.log(0.025), 0.0, 0.0, 0.0]]
+    dif = {(0, 1): np.array([math.log(5e-5), 0.0, 0.0, 0.0])}
+    sp = [("H", (1,), nasa_const(), None), ("H4", (4,), nasa_const(), None)]
+    m = oracle.read_mechanism(tiny_mechanism(tmp_path / "wilke.mech", sp, [], elements=("H",),
+                                             transport=(mu, lam, dif)))
+    assert m.W[1] / m.W[0] == pytest.approx(4.0, rel=1e-15)
+    T = np.array([700.0, 1800.0])            # constant fits: no temperature dependence
+    Y = np.array([[0.2, 0.8], [0.2, 0.8]])
+    tp = oracle.transport_properties(m, T, np.full(2, P0), Y)
+    _, _, X, _ = oracle.mixture_state(m, T, np.full(2, P0), Y)
+    np.testing.assert_allclose(X, 0.5, rtol=1e-15)
+    s2 = math.sqrt(2.0)
+    phi_ab = (9.0 + 4.0 * s2) / math.sqrt(10.0)
+    phi_ba = (9.0 / 8.0 + 1.0 / s2) / math.sqrt(40.0)
+    mu_ref = mu_a / (1.0 + phi_ab) + mu_b / (1.0 + phi_ba)
+    np.testing.assert_allclose(tp["mu"], mu_ref, rtol=1e-14)
+    np.testing.assert_allclose(tp["lambda"], 0.05125, rtol=1e-14)
+
+
+def test_wilke_ternary_permutation_and_scaling(tmp_path):
+    """Three species of unequal mass: relabelling the species leaves mu and lambda unchanged,
+    and scaling every pure viscosity by s scales mu by s (Phi depends on ratios only)."""
+    base = [math.log(3e-5), math.log(1.2e-5), math.log(2.5e-5)]
+    lams = [math.log(0.08), math.log(0.03), math.log(0.15)]
+    comps = [(1, 0), (0, 2), (2, 1)]
+
+    def build(order, shift, name):
+        mu = [[base[i] + shift, 0.0, 0.0, 0.0] for i in order]
+        lam = [[lams[i], 0.0, 0.0, 0.0] for i in order]
+        dif = {(j, k): np.array([math.log(5e-5), 0.0, 0.0, 0.0]) for j in range(3) for k in range(j + 1, 3)}
+        sp = [(f"S{i}", comps[i], nasa_const(), None) for i in order]
+        return oracle.read_mechanism(tiny_mechanism(tmp_path / name, sp, [], transport=(mu, lam, dif)))
+    Y = np.array([[0.5, 0.3, 0.2]])
+    a = oracle.transport_properties(build([0, 1, 2], 0.0, "a.mech"), np.array([1000.0]), np.array([P0]), Y)
+    b = oracle.transport_properties(build([2, 0, 1], 0.0, "b.mech"), np.array([1000.0]), np.array([P0]),
+                                    Y[:, [2, 0, 1]])
+    c = oracle.transport_properties(build([0, 1, 2], math.log(3.0), "c.mech"), np.array([1000.0]),
+                                    np.array([P0]), Y)
+    assert b["mu"][0] == pytest.approx(a["mu"][0], rel=1e-14)
+    assert b["lambda"][0] == pytest.approx(a["lambda"][0], rel=1e-14)
+    assert c["mu"][0] == pytest.approx(3.0 * a["mu"][0], rel=1e-14)
+
+
 def test_binary_and_trace_diffusion(tmp_path):
     sp = [("H", (1, 0), nasa_const(), None), ("O", (0, 1), nasa_const(), None)]
     m = oracle.read_mechanism(tiny_mechanism(tmp_path / "bin.mech", sp, []))
