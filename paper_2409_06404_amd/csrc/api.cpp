@@ -65,7 +65,10 @@ crf_status crf_load_mech(const char *path, int device, crf_mech **out) {
     crf_mech *m = new (std::nothrow) crf_mech();
     if (!m) return fail(CRF_E_NOMEM, "crf_load_mech: out of host memory");
     crf_status s = parse_mechanism(path, m->host);
-    if (s == CRF_OK) build_jac_plan(m->host);
+    if (s == CRF_OK) {
+        build_jac_plan(m->host);
+        m->plan_text = m->host.jp_ok ? std::string("segmented") : "row-block (" + m->host.jp_why + ")";
+    }
     if (s == CRF_OK && device >= 0) s = upload_mechanism(m, device);
     if (s != CRF_OK) { delete m; return s; }
     *out = m;
@@ -88,12 +91,7 @@ int crf_n_species(const crf_mech *m) { return m ? m->host.ns() : -1; }
 int crf_n_reactions(const crf_mech *m) { return m ? m->host.nr() : -1; }
 int crf_device(const crf_mech *m) { return m ? m->device : -1; }
 
-const char *crf_jac_plan(const crf_mech *m) {
-    if (!m) return "";
-    if (m->host.jp_ok) return "segmented";
-    m->plan_text = "row-block (" + m->host.jp_why + ")";
-    return m->plan_text.c_str();
-}
+const char *crf_jac_plan(const crf_mech *m) { return m ? m->plan_text.c_str() : ""; }
 
 const char *crf_last_error(void) { return crf::g_last_error.c_str(); }
 

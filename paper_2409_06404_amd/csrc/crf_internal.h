@@ -23,6 +23,14 @@ enum : int { RXN_ELEMENTARY = 0, RXN_THREEBODY = 1, RXN_TROE = 2 };
 constexpr int MAX_SIDE = 3;
 constexpr int SLOTS = 6;
 
+// Largest mechanism the kernels evaluate: the lane-per-reaction kernels keep a few
+// per-species arrays of every point in flight in LDS (at least 64 x ns bytes for one
+// wavefront), and the row-block Jacobian one row of accumulators besides its species
+// state.  Larger files are refused at load with CRF_E_UNSUPPORTED.
+constexpr int MAX_SPECIES = 2048;
+// LDS of one compute unit (gfx950), the most one workgroup may request.
+constexpr int CU_LDS_BYTES = 160 * 1024;
+
 __host__ __device__ inline int info_kind(int w) { return w & 3; }
 __host__ __device__ inline int info_nreac(int w) { return (w >> 2) & 3; }
 __host__ __device__ inline int info_nprod(int w) { return (w >> 4) & 3; }
@@ -139,7 +147,7 @@ struct crf_mech {
     crf::DevMech dev{};
     int device = -1;
     void *dev_buf = nullptr;
-    mutable std::string plan_text;   // storage for crf_jac_plan
+    std::string plan_text;   // what crf_jac_plan returns, fixed at load
 };
 
 namespace crf {

@@ -106,17 +106,6 @@ template <class R> __device__ inline R log_r(R x);
 template <> __device__ inline double log_r<double>(double x) { return log(x); }
 template <> __device__ inline float log_r<float>(float x) { return __logf(x); }
 
-// e^x with FP64 range reduction (x = k ln2 + f, |f| <= ln2/2) and an FP32 core:
-// relative error ~2^-23 independent of |x|.  Used for the equilibrium factor in
-// the mixed mode, where ln K_c itself is formed in FP64.
-__device__ inline double exp_split(double x) {
-    const double k = rint(x * 1.4426950408889634074);
-    double f = fma(-k, 6.93147180369123816490e-01, x);
-    f = fma(-k, 1.90821492927058770002e-10, f);
-    const float e = __expf((float)f);
-    return ldexp((double)e, (int)fmax(fmin(k, 2000.0), -2000.0));
-}
-
 // LDS access by byte offset from the start of the workgroup's LDS allocation (the
 // kernels that use these declare no static LDS, so dynamic LDS starts at offset 0);
 // saves the base-address add the compiler emits for the dynamic-LDS symbol.
@@ -278,7 +267,9 @@ __device__ inline void eval_reaction(const DevMech &m, int r, const PointState &
         }
         if (s < MAX_SIDE) pf *= Ps[s]; else pr *= Ps[s];
     }
-    const double invKc = MIXED ? exp_split(-lnKc) : exp_fast(-lnKc);
+    // 1/K_c in FP64 in both modes: near equilibrium q = k_f (prod_f - prod_r / K_c) is
+    // decided by this factor, so its relative error becomes the error of q
+    const double invKc = exp_fast(-lnKc);
     const double kfd = (double)kf;
     const double fac = kind == RXN_THREEBODY ? M : 1.0;
     const double krd = kfd * invKc;
@@ -724,7 +715,7 @@ __device__ inline void jac_seg_reaction(int r, unsigned sp03, unsigned sp45, int
     // equilibrium constant and rates of progress (FP64)
     const double lnKc = (double)dnu * lnp0RT - ((g[3] + g[4] + g[5]) - (g[0] + g[1] + g[2]));
     const double dlnKc = ((h[3] + h[4] + h[5]) - (h[0] + h[1] + h[2]) - (double)dnu) * invT;
-    const double invKc = MIXED ? exp_split(-lnKc) : exp_r<double>(-lnKc);
+    const double invKc = exp_fast(-lnKc);   // FP64 in both modes (it decides q near equilibrium)
     const double kfd = (double)kf;
     const double fac = kind == RXN_THREEBODY ? M : 1.0;
     const double fk = fac * kfd, fr = fk * invKc;
@@ -1280,6 +1271,19 @@ inline unsigned grid_for(int64_t work_items, int per_block, int blocks_per_cu) {
 
 inline int pad_odd(int x) { return x | 1; }
 
+// Wavefronts per workgroup (up to 4) of a kernel whose wavefronts each need `per_wave`
+// bytes of dynamic LDS: as many as one compute unit's LDS holds.  Raises the kernel's
+// dynamic-LDS limit (64 KB by default) to what the workgroup uses.  The loader refuses
+// mechanisms for which even one wavefront would not fit.
+hipError_t lds_waves(const void *fn, size_t per_wave, int &wpb, size_t &shm) {
+    wpb = 4;
+    while (wpb > 1 && (size_t)wpb * per_wave > (size_t)CU_LDS_BYTES) --wpb;
+    shm = (size_t)wpb * per_wave;
+    if (shm > (size_t)CU_LDS_BYTES) return hipErrorInvalidValue;
+    if (shm > 64 * 1024) return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    return hipSuccess;
+}
+
 }  // namespace
 
 hipError_t launch_thermo(const DevMech &m, int64_t n, const double *T, const double *p, int64_t ps,
@@ -1292,9 +1296,13 @@ hipError_t launch_thermo(const DevMech &m, int64_t n, const double *T, const dou
 
 hipError_t launch_wdot(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
                        const double *Y, int64_t ld, double *wdot, double *hrr, double *rmass, hipStream_t st) {
-    constexpr int PPW = 2, WPB = 4;
+    constexpr int PPW = 2;
     const int nsp = pad_odd(m.ns);
-    const size_t shm = (size_t)WPB * PPW * 4 * nsp * sizeof(double);
+    const void *fn = mixed ? (const void *)k_wdot<true, PPW> : (const void *)k_wdot<false, PPW>;
+    int WPB = 4;
+    size_t shm = 0;
+    const hipError_t e = lds_waves(fn, (size_t)PPW * 4 * nsp * sizeof(double), WPB, shm);
+    if (e != hipSuccess) return e;
     const int64_t groups = (n + PPW - 1) / PPW;
     const dim3 grid(grid_for(groups, WPB, 16)), block(WPB * WAVE);
     if (mixed)
@@ -1307,9 +1315,12 @@ hipError_t launch_wdot(const DevMech &m, int mixed, int64_t n, const double *T, 
 hipError_t launch_vjp(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
                       const double *Y, int64_t ld, const double *u, const double *uh, double *gT, double *gY,
                       hipStream_t st) {
-    constexpr int WPB = 4;
     const int nsp = pad_odd(m.ns);
-    const size_t shm = (size_t)WPB * 7 * nsp * sizeof(double);
+    const void *fn = mixed ? (const void *)k_vjp<true> : (const void *)k_vjp<false>;
+    int WPB = 4;
+    size_t shm = 0;
+    const hipError_t e = lds_waves(fn, (size_t)7 * nsp * sizeof(double), WPB, shm);
+    if (e != hipSuccess) return e;
     const dim3 grid(grid_for(n, WPB, 16)), block(WPB * WAVE);
     if (mixed)
         hipLaunchKernelGGL((k_vjp<true>), grid, block, shm, st, m, n, T, p, ps, Y, ld, u, uh, gT, gY, nsp);
@@ -1359,7 +1370,7 @@ hipError_t launch_jac(const DevMech &m, int mixed, int64_t n, const double *T, c
     const size_t acc = sizeof(double);
     const size_t fixed = (size_t)(4 * nsp + 4 * (nsp + 1)) * sizeof(double);
     // rows per block: as many as fit one compute unit's LDS (one workgroup per point)
-    const size_t budget = 160 * 1024 - 256;
+    const size_t budget = CU_LDS_BYTES - 256;
     int rb = (int)((budget > fixed ? budget - fixed : 0) / ((size_t)sr * acc));
     if (rb >= n1) rb = n1;
     if (rb < 1) return hipErrorInvalidValue;
@@ -1378,9 +1389,13 @@ hipError_t launch_jac(const DevMech &m, int mixed, int64_t n, const double *T, c
 hipError_t launch_transport(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
                             int64_t ps, const double *Y, int64_t ld, double *mu, double *lam, double *Dmix,
                             hipStream_t st) {
-    constexpr int PPW = 2, WPB = 4;
+    constexpr int PPW = 2;
     const int nsp = pad_odd(m.ns + 1);   // room for the dummy species of the pair schedule
-    const size_t shm = (size_t)WPB * PPW * 4 * nsp * sizeof(double);
+    const void *fn = mixed ? (const void *)k_transport<true, PPW> : (const void *)k_transport<false, PPW>;
+    int WPB = 4;
+    size_t shm = 0;
+    const hipError_t e = lds_waves(fn, (size_t)PPW * 4 * nsp * sizeof(double), WPB, shm);
+    if (e != hipSuccess) return e;
     const int64_t groups = (n + PPW - 1) / PPW;
     const dim3 grid(grid_for(groups, WPB, 16)), block(WPB * WAVE);
     if (mixed)

@@ -91,7 +91,10 @@ crf_status parse_mechanism(const char *path, HostMech &h) {
         h.elements.push_back(sym); h.aw.push_back(w);
     }
     int ns = 0;
-    if (!L.next(ss) || !(ss >> kw >> ns) || kw != "species" || ns <= 0 || ns > 4096) return perr(lineno(), "bad species header");
+    if (!L.next(ss) || !(ss >> kw >> ns) || kw != "species" || ns <= 0) return perr(lineno(), "bad species header");
+    if (ns > MAX_SPECIES)
+        return fail(CRF_E_UNSUPPORTED, std::to_string(ns) + " species; at most " + std::to_string(MAX_SPECIES) +
+                                           " are supported (per-point species arrays live in LDS)");
     h.names.resize(ns); h.comp.assign((size_t)ns * ne, 0); h.W.assign(ns, 0.0);
     h.nasa.assign((size_t)ns * 16, 0.0);
     for (int k = 0; k < ns; ++k) {

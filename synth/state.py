@@ -55,7 +55,8 @@ def state_c1(ns, n=1 << 20, seed=1, anchors=None, near_eq_fraction=0.10):
     90 % of the points: T ~ U[300, 2500] K, Y ~ Dirichlet(0.3).  10 %: near-equilibrium
     states obtained by cycling the stored equilibrium anchors, perturbing every
     Y_k by a factor (1 + 1e-3 N(0,1)), renormalising and jittering T by up to 0.1 K.
-    p is 1 atm or 10 atm with probability 1/2 each.  Rows are shuffled.
+    p is 1 atm or 10 atm with probability 1/2 each.  Rows are shuffled; "near_eq" marks the
+    near-equilibrium rows.
     """
     rng = np.random.default_rng(seed)
     if anchors is None:
@@ -76,7 +77,8 @@ def state_c1(ns, n=1 << 20, seed=1, anchors=None, near_eq_fraction=0.10):
         T[n_rand:] = anchors["T"][a] + rng.uniform(-0.1, 0.1, size=n_eq)
         p[n_rand:] = anchors["p"][a]
     perm = rng.permutation(n)
-    return {"T": T[perm], "p": p[perm], "Y": np.ascontiguousarray(Y[perm].T)}
+    near_eq = np.arange(n) >= n_rand
+    return {"T": T[perm], "p": p[perm], "Y": np.ascontiguousarray(Y[perm].T), "near_eq": near_eq[perm]}
 
 
 def state_c3_cotangent(ns, n=1 << 20, seed=3):

@@ -76,6 +76,19 @@ def test_malformed_files(L, c0_path, tmp_path, edit, status, msg):
     assert not h.value
 
 
+def test_species_limit(L, c0_path, tmp_path):
+    """Mechanisms above 2048 species are refused at load (CRF_E_UNSUPPORTED), before the
+    rest of the file is read: the per-point species arrays of the kernels live in LDS."""
+    text = open(c0_path).read()
+    bad = tmp_path / "big.mech"
+    bad.write_text(text.replace("\nspecies 9\n", "\nspecies 2049\n"))
+    assert "species 2049" in bad.read_text()
+    s, h = _load(L, bad)
+    assert s == 6, (s, L.crf_last_error())
+    assert b"at most 2048" in L.crf_last_error()
+    assert not h.value
+
+
 def test_unbalanced_reaction_rejected(L, c0_path, tmp_path):
     lines = open(c0_path).read().splitlines()
     i = next(k for k, ln in enumerate(lines) if ln.startswith("reaction "))

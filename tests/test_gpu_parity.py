@@ -107,6 +107,32 @@ def test_wdot_mixed_c1(crf, mechs):
     assert np.max(np.abs(r.cpu().numpy()) / (ref["turnover"] @ om.W)) <= 1e-13
 
 
+@pytest.mark.parametrize("call", ["wdot", "jac"])
+def test_mixed_near_equilibrium(crf, mechs, call):
+    """Mixed mode on the near-equilibrium share of the 53-species state alone: there
+    q_f and q_r cancel to about three digits, so the equilibrium constant (FP64 in both
+    modes) decides q.  Bound: E_norm <= 1e-5 on significant species."""
+    g, om = mechs["c1"]
+    st = synth.state_c1(53, n=4000, seed=2)
+    ne = st["near_eq"]
+    sub = {"T": st["T"][ne], "p": st["p"][ne], "Y": np.ascontiguousarray(st["Y"][:, ne])}
+    T, p, Y = to_dev(sub)
+    if call == "wdot":
+        w = crf.wdot(g, T, p, Y, "mixed", hrr=False)[0]
+    else:
+        w = crf.wdot_jac(g, T, p, Y, "mixed")[1]
+    torch.cuda.synchronize()
+    ref = oracle.production_rates(om, sub["T"], sub["p"], sub["Y"].T)
+    q = oracle.rates_of_progress(om, sub["T"], sub["p"], sub["Y"].T)
+    assert np.median(np.abs(q["q"]) / np.abs(q["qf"])) < 1e-2      # the share is near equilibrium
+    w = w.cpu().numpy()
+    sig = significant_species(ref["wdot"], om.W)
+    en = e_norm(w, ref["wdot"])
+    et = e_turn(w, ref["wdot"], ref["turnover"])
+    log(f"mixed near-eq {call} ({int(ne.sum())} points): E_norm max {en[sig].max():.2e}  E_turn max {et.max():.2e}")
+    assert en[sig].max() <= 1e-5
+
+
 # ------------------------------------------------------------------ thermo / transport
 def test_thermo_fp64(crf, mechs):
     g, om = mechs["c1"]
