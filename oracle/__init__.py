@@ -20,11 +20,13 @@ from .mechfile import OracleMech, read_mechanism
 from .thermo import mixture_state, nasa7, thermo_properties
 from .kinetics import rates_of_progress, production_rates
 from .transport import transport_properties
-from .jacobian import jacobian, vjp, complex_step_jacobian, central_fd_jacobian
+from .jacobian import jacobian, vjp, jvp, complex_step_jacobian, complex_step_jvp, central_fd_jacobian
+from .source import chemistry_source
 from .equil import equilibrate
 
 __all__ = [
     "OracleMech", "read_mechanism", "mixture_state", "nasa7", "thermo_properties",
-    "rates_of_progress", "production_rates", "transport_properties", "jacobian", "vjp",
-    "complex_step_jacobian", "central_fd_jacobian", "equilibrate",
+    "rates_of_progress", "production_rates", "transport_properties", "jacobian", "vjp", "jvp",
+    "complex_step_jacobian", "complex_step_jvp", "central_fd_jacobian", "equilibrate",
+    "chemistry_source",
 ]

@@ -186,6 +186,27 @@ def vjp(m, T, p, Y, u, u_hrr=None):
     return g[:, 0], g[:, 1:]
 
 
+def jvp(m, T, p, Y, vT, vY):
+    """(jv_hrr [n], jv_w [n, Ns]) = J v for the tangent v = (vT [n], vY [n, Ns]) of (T, Y).
+
+    The forward-mode derivative of (hrr, w) along v: the plain product of the
+    analytic Jacobian with v.  Pinned by complex-step differentiation of the
+    forward oracle along v (complex_step_jvp).
+    """
+    J = jacobian(m, T, p, Y)
+    v = np.concatenate([np.asarray(vT)[:, None], np.asarray(vY)], axis=1)
+    jv = np.einsum("nrc,nc->nr", J, v)
+    return jv[:, 0], jv[:, 1:]
+
+
+def complex_step_jvp(m, T, p, Y, vT, vY, h=1e-30):
+    """J v by one complex step of the forward oracle along v: Im f(x + i h v) / h."""
+    T = np.asarray(T, dtype=float)
+    Y = np.asarray(Y, dtype=float)
+    f = _forward_vector(m, T + 1j * h * np.asarray(vT), p, Y + 1j * h * np.asarray(vY)).imag / h
+    return f[:, 0], f[:, 1:]
+
+
 def _forward_vector(m, T, p, Y):
     r = production_rates(m, T, p, Y)
     return np.concatenate([r["hrr"][:, None], r["wdot"]], axis=1)

@@ -83,3 +83,37 @@ def test_isomer_jacobian_by_hand(tmp_path):
     # (C is homogeneous of degree 0 in Y, so the Y columns dotted with Y vanish)
     assert J[0, 1, 2] == pytest.approx(0.75 * rho / W, rel=1e-14)
     assert abs(J[0, 1, 1:] @ np.array([0.5, 0.5])) <= 1e-15 * rho / W
+
+
+@pytest.mark.parametrize("which", ["c0", "c1"])
+def test_jvp_matches_complex_step_along_v(which, c0_path, c1_path):
+    """J v of the oracle against one complex step of the forward oracle along v (exact
+    to rounding, independent of the analytic chain rule); scale of row k:
+    sum_c G_kc |v_c| with G the gross Jacobian."""
+    m = oracle.read_mechanism(c0_path if which == "c0" else c1_path)
+    T, p, Y = _states(m, 8, 21, with_anchors=(which == "c1"))
+    rng = np.random.default_rng(5)
+    n = T.shape[0]
+    vT = rng.standard_normal(n) * T * 1e-2
+    vY = rng.standard_normal((n, m.n_species)) * Y
+    jh, jw = oracle.jvp(m, T, p, Y, vT, vY)
+    ch, cw = oracle.complex_step_jvp(m, T, p, Y, vT, vY)
+    _, G = oracle.jacobian(m, T, p, Y, return_gross=True)
+    scale = np.einsum("nrc,nc->nr", G, np.abs(np.concatenate([vT[:, None], vY], axis=1)))
+    err = np.abs(np.concatenate([(jh - ch)[:, None], jw - cw], axis=1)) / scale
+    assert err.max() <= 1e-12
+
+
+def test_jvp_of_a_single_column_is_that_column(c0_path):
+    """v = e_c gives column c of the Jacobian (and the T column for v = e_T)."""
+    m = oracle.read_mechanism(c0_path)
+    T, p, Y = _states(m, 3, 22)
+    J = oracle.jacobian(m, T, p, Y)
+    for c in (0, 1, m.n_species):
+        vT = np.full(3, 1.0 if c == 0 else 0.0)
+        vY = np.zeros((3, m.n_species))
+        if c > 0:
+            vY[:, c - 1] = 1.0
+        jh, jw = oracle.jvp(m, T, p, Y, vT, vY)
+        np.testing.assert_array_equal(jh, J[:, 0, c])
+        np.testing.assert_array_equal(jw, J[:, 1:, c])
