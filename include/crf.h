@@ -141,6 +141,34 @@ crf_status crf_wdot_vjp(const crf_mech *m, crf_precision prec, int64_t n, const 
                         const double *u, const double *u_hrr, double *gT, double *gY,
                         crf_stream stream);
 
+/* Jacobian-vector product (forward mode) of (hrr, w_1..w_Ns) with respect to
+ * (T, Y_1..Y_Ns) at fixed p, along the tangent v = (vT, vY): the directional
+ * derivative that the paper's Newton-GMRES iteration approximates by difference
+ * quotients (Section 2), formed analytically:
+ *   jv_w[k*ld + i] = dw_k/dT vT[i] + sum_j dw_k/dY_j vY[j*ld + i],
+ *   jv_hrr[i]      = dhrr/dT vT[i] + sum_j dhrr/dY_j vY[j*ld + i].
+ * vT nullable (treated as zero); vY required, same layout as Y.  jv_hrr and wdot
+ * (the production rates of the same evaluation) nullable; jv_w required.  The
+ * tangent sums over reactions are FP64 in both modes (the rates of progress and
+ * their derivatives follow the precision mode). */
+crf_status crf_wdot_jvp(const crf_mech *m, crf_precision prec, int64_t n, const double *T,
+                        const double *p, int64_t p_stride, const double *Y, int64_t ld,
+                        const double *vT, const double *vY, double *jv_hrr, double *jv_w,
+                        double *wdot, crf_stream stream);
+
+/* Point-wise chemistry source terms of the thermochemistry subsystem (Section 2,
+ * Eq. (1a)-(1b)) and the point-wise part of the divergence constraint (Eq. (3)),
+ * for a homogeneous mixture at each point (no transport terms):
+ *   dYdt[k*ld + i] = W_k w_k / rho                        [1/s]
+ *   dTdt[i]        = (hrr + dp0dt) / (rho c_p)            [K/s], c_p per unit mass
+ *   QT[i]          = dTdt/T + sum_k (Wbar/W_k) dYdt_k - dp0dt/p   [1/s]
+ *   hrr[i]         = -sum_k h_k w_k                       [W/m^3]
+ * dp0dt is the rate of the (spatially uniform) thermodynamic pressure, 0 for an open
+ * domain.  Every output nullable; at least one must be given. */
+crf_status crf_source(const crf_mech *m, crf_precision prec, int64_t n, const double *T,
+                      const double *p, int64_t p_stride, const double *Y, int64_t ld, double dp0dt,
+                      double *dYdt, double *dTdt, double *QT, double *hrr, crf_stream stream);
+
 /* Dense Jacobian of (hrr, w_1..w_Ns) with respect to (T, Y_1..Y_Ns) at fixed p,
  * for the Newton iteration of an implicit chemistry step (Section 2).  Point-major,
  * row-major per point: with N1 = Ns + 1, entry (r, c) of point i is

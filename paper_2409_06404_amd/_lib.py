@@ -7,7 +7,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcrf.so")
 EXPORTED = (
     "crf_load_mech", "crf_free_mech", "crf_n_species", "crf_n_reactions", "crf_device", "crf_jac_plan",
     "crf_last_error", "crf_status_str", "crf_thermo", "crf_wdot", "crf_transport",
-    "crf_wdot_vjp", "crf_wdot_jac",
+    "crf_wdot_vjp", "crf_wdot_jac", "crf_wdot_jvp", "crf_source",
 )
 
 CRF_OK, CRF_E_ARG, CRF_E_PARSE, CRF_E_MECH, CRF_E_NOMEM, CRF_E_DEVICE, CRF_E_UNSUPPORTED = range(7)
@@ -61,6 +61,10 @@ def lib():
     L.crf_wdot_vjp.restype = I
     L.crf_wdot_jac.argtypes = [P, I, I64, D, D, I64, D, I64, D, D, P]
     L.crf_wdot_jac.restype = I
+    L.crf_wdot_jvp.argtypes = [P, I, I64, D, D, I64, D, I64, D, D, D, D, D, P]
+    L.crf_wdot_jvp.restype = I
+    L.crf_source.argtypes = [P, I, I64, D, D, I64, D, I64, ctypes.c_double, D, D, D, D, P]
+    L.crf_source.restype = I
     _lib = L
     return L
 

@@ -167,6 +167,35 @@ def wdot_vjp(m, T, p, Y, u, u_hrr=None, precision="fp64"):
     return gT, gY
 
 
+def wdot_jvp(m, T, p, Y, vY, vT=None, precision="fp64", with_hrr=True, with_wdot=False):
+    """(jv_hrr [n] or None, jv_w [n, Ns], wdot [n, Ns] or None) = d(hrr, w)/d(T, Y) . (vT, vY).
+
+    vY in the same species-major layout as Y; vT [n] or None (zero)."""
+    n, p, ps, ld, dev = _state(m, T, p, Y)
+    ns = m.n_species
+    if vY.dtype != torch.float64 or vY.shape != (n, ns) or vY.device != dev or (n > 0 and ns > 1 and
+                                                                              (vY.stride(0) != 1 or vY.stride(1) != ld)):
+        raise ValueError("vY must be a float64 [n, Ns] tensor with the same species-major layout as Y")
+    if vT is not None and (vT.dtype != torch.float64 or vT.shape != (n,) or not vT.is_contiguous() or vT.device != dev):
+        raise ValueError("vT must be a contiguous float64 [n] tensor on the mechanism's device")
+    jh = torch.empty(n, dtype=torch.float64, device=dev) if with_hrr else None
+    jw = _species_out(ns, n, ld, dev)
+    w = _species_out(ns, n, ld, dev) if with_wdot else None
+    check(_lib.lib().crf_wdot_jvp(m.handle, _prec(precision), n, _ptr(T), _ptr(p), ps, _ptr(Y), ld,
+                                  _ptr(vT), _ptr(vY), _ptr(jh), _ptr(jw), _ptr(w), _stream(dev)))
+    return jh, jw, w
+
+
+def source(m, T, p, Y, precision="fp64", dp0dt=0.0):
+    """Point-wise chemistry source terms: dict(dYdt [n, Ns] 1/s, dTdt [n] K/s, QT [n] 1/s, hrr [n] W/m^3)."""
+    n, p, ps, ld, dev = _state(m, T, p, Y)
+    out = {"dYdt": _species_out(m.n_species, n, ld, dev)}
+    out.update({k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("dTdt", "QT", "hrr")})
+    check(_lib.lib().crf_source(m.handle, _prec(precision), n, _ptr(T), _ptr(p), ps, _ptr(Y), ld, float(dp0dt),
+                                *[_ptr(out[k]) for k in ("dYdt", "dTdt", "QT", "hrr")], _stream(dev)))
+    return out
+
+
 def wdot_jac(m, T, p, Y, precision="fp64", with_wdot=True, out=None):
     """(J [n, Ns+1, Ns+1] float64/float32, wdot [n, Ns] or None).
 
@@ -209,5 +238,5 @@ class WdotFn(torch.autograd.Function):
         return gT, gY, None, None, None
 
 
-__all__ = ["Mechanism", "species_major", "thermo", "wdot", "transport", "wdot_vjp", "wdot_jac", "WdotFn",
-           "CrfError"]
+__all__ = ["Mechanism", "species_major", "thermo", "wdot", "transport", "wdot_vjp", "wdot_jvp", "wdot_jac",
+           "source", "WdotFn", "CrfError"]

@@ -1,5 +1,6 @@
 // C ABI entry points: host-side argument validation, then kernel launch.
 
+#include <cmath>
 #include <string>
 
 #include "crf_internal.h"
@@ -29,7 +30,13 @@ crf_status check_state(const crf_mech *m, int64_t n, const double *T, const doub
     if (ps != 0 && ps != 1) return fail(CRF_E_ARG, f + ": p_stride must be 0 or 1");
     if (ld < n) return fail(CRF_E_ARG, f + ": ld must be >= n");
     if (n > 0 && (!T || !p || !Y)) return fail(CRF_E_ARG, f + ": T, p and Y must not be NULL");
-    if (m->device < 0 || !m->dev_buf) return fail(CRF_E_DEVICE, f + ": mechanism was loaded without a device");
+    return CRF_OK;
+}
+
+// The mechanism's tables are on a device (checked after every argument).
+crf_status check_device(const crf_mech *m, const char *fn) {
+    if (m->device < 0 || !m->dev_buf)
+        return fail(CRF_E_DEVICE, std::string(fn) + ": mechanism was loaded without a device");
     return CRF_OK;
 }
 
@@ -113,6 +120,7 @@ crf_status crf_thermo(const crf_mech *m, int64_t n, const double *T, const doubl
                       double *cp_mass, double *h_mass, double *rho, double *Wbar, crf_stream stream) {
     crf_status s = check_state(m, n, T, p, ps, Y, ld, "crf_thermo");
     if (s != CRF_OK) return s;
+    if (check_device(m, "crf_thermo") != CRF_OK) return CRF_E_DEVICE;
     if (n == 0) return CRF_OK;
     return on_device(m, "crf_thermo", [&] {
         return launch_thermo(m->dev, n, T, p, ps, Y, ld, cp_k, h_k, s_k, g_k, cp_mass, h_mass, rho, Wbar,
@@ -127,6 +135,7 @@ crf_status crf_wdot(const crf_mech *m, crf_precision prec, int64_t n, const doub
     if (s == CRF_OK) s = check_prec(prec, "crf_wdot");
     if (s != CRF_OK) return s;
     if (n > 0 && !wdot) return fail(CRF_E_ARG, "crf_wdot: wdot must not be NULL");
+    if (check_device(m, "crf_wdot") != CRF_OK) return CRF_E_DEVICE;
     if (n == 0) return CRF_OK;
     return on_device(m, "crf_wdot", [&] {
         return launch_wdot(m->dev, prec == CRF_MIXED, n, T, p, ps, Y, ld, wdot, hrr, mass_resid,
@@ -140,6 +149,7 @@ crf_status crf_transport(const crf_mech *m, crf_precision prec, int64_t n, const
     crf_status s = check_state(m, n, T, p, ps, Y, ld, "crf_transport");
     if (s == CRF_OK) s = check_prec(prec, "crf_transport");
     if (s != CRF_OK) return s;
+    if (check_device(m, "crf_transport") != CRF_OK) return CRF_E_DEVICE;
     if (n == 0 || (!mu && !lambda && !Dmix)) return CRF_OK;
     return on_device(m, "crf_transport", [&] {
         return launch_transport(m->dev, prec == CRF_MIXED, n, T, p, ps, Y, ld, mu, lambda, Dmix,
@@ -154,10 +164,42 @@ crf_status crf_wdot_vjp(const crf_mech *m, crf_precision prec, int64_t n, const 
     if (s == CRF_OK) s = check_prec(prec, "crf_wdot_vjp");
     if (s != CRF_OK) return s;
     if (n > 0 && (!u || !gT || !gY)) return fail(CRF_E_ARG, "crf_wdot_vjp: u, gT and gY must not be NULL");
+    if (check_device(m, "crf_wdot_vjp") != CRF_OK) return CRF_E_DEVICE;
     if (n == 0) return CRF_OK;
     return on_device(m, "crf_wdot_vjp", [&] {
         return launch_vjp(m->dev, prec == CRF_MIXED, n, T, p, ps, Y, ld, u, u_hrr, gT, gY,
                           (hipStream_t)stream);
+    });
+}
+
+crf_status crf_wdot_jvp(const crf_mech *m, crf_precision prec, int64_t n, const double *T,
+                        const double *p, int64_t ps, const double *Y, int64_t ld, const double *vT,
+                        const double *vY, double *jv_hrr, double *jv_w, double *wdot, crf_stream stream) {
+    crf_status s = check_state(m, n, T, p, ps, Y, ld, "crf_wdot_jvp");
+    if (s == CRF_OK) s = check_prec(prec, "crf_wdot_jvp");
+    if (s != CRF_OK) return s;
+    if (n > 0 && (!vY || !jv_w)) return fail(CRF_E_ARG, "crf_wdot_jvp: vY and jv_w must not be NULL");
+    if (check_device(m, "crf_wdot_jvp") != CRF_OK) return CRF_E_DEVICE;
+    if (n == 0) return CRF_OK;
+    return on_device(m, "crf_wdot_jvp", [&] {
+        return launch_jvp(m->dev, prec == CRF_MIXED, n, T, p, ps, Y, ld, vT, vY, jv_hrr, jv_w, wdot,
+                          (hipStream_t)stream);
+    });
+}
+
+crf_status crf_source(const crf_mech *m, crf_precision prec, int64_t n, const double *T, const double *p,
+                      int64_t ps, const double *Y, int64_t ld, double dp0dt, double *dYdt, double *dTdt,
+                      double *QT, double *hrr, crf_stream stream) {
+    crf_status s = check_state(m, n, T, p, ps, Y, ld, "crf_source");
+    if (s == CRF_OK) s = check_prec(prec, "crf_source");
+    if (s != CRF_OK) return s;
+    if (!dYdt && !dTdt && !QT && !hrr) return fail(CRF_E_ARG, "crf_source: no output given");
+    if (!std::isfinite(dp0dt)) return fail(CRF_E_ARG, "crf_source: dp0dt must be finite");
+    if (check_device(m, "crf_source") != CRF_OK) return CRF_E_DEVICE;
+    if (n == 0) return CRF_OK;
+    return on_device(m, "crf_source", [&] {
+        return launch_source(m->dev, prec == CRF_MIXED, n, T, p, ps, Y, ld, dp0dt, dYdt, dTdt, QT, hrr,
+                             (hipStream_t)stream);
     });
 }
 
@@ -168,6 +210,7 @@ crf_status crf_wdot_jac(const crf_mech *m, crf_precision prec, int64_t n, const 
     if (s == CRF_OK) s = check_prec(prec, "crf_wdot_jac");
     if (s != CRF_OK) return s;
     if (n > 0 && !J) return fail(CRF_E_ARG, "crf_wdot_jac: J must not be NULL");
+    if (check_device(m, "crf_wdot_jac") != CRF_OK) return CRF_E_DEVICE;
     if (n == 0) return CRF_OK;
     return on_device(m, "crf_wdot_jac", [&] {
         return launch_jac(m->dev, prec == CRF_MIXED, n, T, p, ps, Y, ld, J, wdot, (hipStream_t)stream);

@@ -175,6 +175,12 @@ hipError_t launch_transport(const DevMech &m, int mixed, int64_t n, const double
 hipError_t launch_vjp(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
                       int64_t ps, const double *Y, int64_t ld, const double *u, const double *uh,
                       double *gT, double *gY, hipStream_t st);
+hipError_t launch_jvp(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
+                      int64_t ps, const double *Y, int64_t ld, const double *vT, const double *vY,
+                      double *jh, double *jw, double *wdot, hipStream_t st);
+hipError_t launch_source(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
+                         int64_t ps, const double *Y, int64_t ld, double dp0dt, double *dYdt,
+                         double *dTdt, double *QT, double *hrr, hipStream_t st);
 hipError_t launch_jac(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
                       int64_t ps, const double *Y, int64_t ld, void *J, double *wdot, hipStream_t st);
 

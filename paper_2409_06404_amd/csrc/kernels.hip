@@ -335,26 +335,32 @@ __global__ __launch_bounds__(256) void k_thermo(DevMech m, int64_t n, const doub
 }
 
 // ------------------------------------------------------------------ wdot
-// LDS per wave: PPW points x {C, g/RT, h/RT, w} x nsp doubles.
-template <bool MIXED, int PPW>
+// LDS per wave: PPW points x {C, g/RT, h/RT, w} x nsp doubles, plus cp/R with SRC.
+// SRC: the point-wise chemistry source terms instead of w (outputs dYdt, dTdt, QT):
+//   dY_k/dt = W_k w_k / rho,  dT/dt = (hrr + dp0/dt) / (rho c_p),
+//   Q_T = (1/T) dT/dt + sum_k (Wbar/W_k) dY_k/dt - (dp0/dt)/p
+// with c_p = sum_k Y_k cp_k / W_k = (R/rho) sum_k C_k cp_k/R and
+// sum_k (Wbar/W_k) dY_k/dt = (Wbar/rho) sum_k w_k.
+template <bool MIXED, int PPW, bool SRC>
 __global__ __launch_bounds__(256, 3) void k_wdot(DevMech m, int64_t n, const double *__restrict__ T,
                                               const double *__restrict__ p, int64_t ps,
                                               const double *__restrict__ Y, int64_t ld,
                                               double *__restrict__ wdot, double *__restrict__ hrr,
-                                              double *__restrict__ rmass, int nsp) {
+                                              double *__restrict__ rmass, double *__restrict__ dTdt,
+                                              double *__restrict__ QT, double dp0dt, int nsp) {
+    constexpr int NA = SRC ? 5 : 4;
     extern __shared__ double lds[];
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
     const int wpb = blockDim.x / WAVE;
-    double *base = lds + (size_t)wave * PPW * 4 * nsp;
+    double *base = lds + (size_t)wave * PPW * NA * nsp;
     const int64_t n_groups = (n + PPW - 1) / PPW;
     for (int64_t g = (int64_t)blockIdx.x * wpb + wave; g < n_groups; g += (int64_t)gridDim.x * wpb) {
         PointState st[PPW];
         wave_lds_sync();
 #pragma unroll
         for (int q = 0; q < PPW; ++q) {
-            double *C = base + (4 * q + 0) * nsp, *G = base + (4 * q + 1) * nsp, *H = base + (4 * q + 2) * nsp,
-                   *Wd = base + (4 * q + 3) * nsp;
-            st[q] = load_point<true, false>(m, g * PPW + q, n, T, p, ps, Y, ld, C, G, H, nullptr);
+            double *C = base + (NA * q + 0) * nsp, *G = C + nsp, *H = G + nsp, *Wd = H + nsp, *CP = Wd + nsp;
+            st[q] = load_point<true, SRC>(m, g * PPW + q, n, T, p, ps, Y, ld, C, G, H, SRC ? CP : nullptr);
             for (int k = lane; k < m.ns; k += WAVE) Wd[k] = 0.0;
         }
         wave_lds_sync();
@@ -367,8 +373,7 @@ __global__ __launch_bounds__(256, 3) void k_wdot(DevMech m, int64_t n, const dou
             const int nre = info_nreac(info), npr = info_nprod(info);
 #pragma unroll
             for (int q = 0; q < PPW; ++q) {
-                double *C = base + (4 * q + 0) * nsp, *G = base + (4 * q + 1) * nsp,
-                       *Wd = base + (4 * q + 3) * nsp;
+                double *C = base + (NA * q + 0) * nsp, *G = C + nsp, *Wd = C + 3 * nsp;
                 RxnEval o;
                 eval_reaction<MIXED, false>(m, r, st[q], C, G, nullptr, info, ri, lnA, bb, th, dsum, o);
 #pragma unroll
@@ -383,17 +388,34 @@ __global__ __launch_bounds__(256, 3) void k_wdot(DevMech m, int64_t n, const dou
         for (int q = 0; q < PPW; ++q) {
             if (!st[q].valid) continue;
             const int64_t i = g * PPW + q;
-            const double *H = base + (4 * q + 2) * nsp, *Wd = base + (4 * q + 3) * nsp;
-            double hs = 0.0, ms = 0.0;
+            const double *C = base + (NA * q) * nsp, *H = C + 2 * nsp, *Wd = C + 3 * nsp, *CP = C + 4 * nsp;
+            double hs = 0.0, ms = 0.0, cs = 0.0;
+            const double irho = SRC ? 1.0 / st[q].rho : 0.0;
             for (int k = lane; k < m.ns; k += WAVE) {
                 const double w = Wd[k];
-                wdot[(int64_t)k * ld + i] = w;
+                if (SRC) {
+                    if (wdot) wdot[(int64_t)k * ld + i] = m.W[k] * w * irho;
+                    cs += C[k] * CP[k];
+                    ms += w;
+                } else {
+                    wdot[(int64_t)k * ld + i] = w;
+                    ms += m.W[k] * w;
+                }
                 hs += H[k] * w;
-                ms += m.W[k] * w;
             }
             hs = wave_sum(hs);
             ms = wave_sum(ms);
-            if (lane == 0) {
+            if (SRC) {
+                cs = wave_sum(cs);
+                if (lane == 0) {
+                    const double hr = -m.R * st[q].T * hs;
+                    const double cpm = m.R * cs * irho;                       // J/(kg K)
+                    const double dt = (hr + dp0dt) * irho / cpm;
+                    if (hrr) hrr[i] = hr;
+                    if (dTdt) dTdt[i] = dt;
+                    if (QT) QT[i] = dt * st[q].invT + st[q].Wbar * irho * ms - dp0dt / st[q].p;
+                }
+            } else if (lane == 0) {
                 if (hrr) hrr[i] = -m.R * st[q].T * hs;
                 if (rmass) rmass[i] = ms;
             }
@@ -471,6 +493,113 @@ __global__ __launch_bounds__(256, 3) void k_vjp(DevMech m, int64_t n, const doub
         for (int k = lane; k < m.ns; k += WAVE)
             gY[(int64_t)k * ld + i] = (st.rho * (GC[k] + a_tau) - st.Wbar * Rsum) * m.invW[k];
         if (lane == 0) gT[i] = a_t - Rsum * st.invT - uhr * cpw;
+    }
+}
+
+// ------------------------------------------------------------------ JVP
+// Forward-mode derivative along v = (vT, vY): the tangent of the concentrations is
+//   dC_k = rho vY_k / W_k - C_k s,   s = vT / T + Wbar sum_j vY_j / W_j
+// (dC_k/dT = -C_k/T and dC_k/dY_j = delta_kj rho/W_k - C_k Wbar/W_j), that of [M] the
+// efficiency-weighted sum of dC; every reaction contributes
+//   dq = (dq/dT)_C vT + sum_slots (dq/dC_s) dC_s + (dq/d[M]) d[M]
+// to dw_k = sum_i dnu_ki dq_i, and d hrr = -sum_k h_k dw_k - vT sum_k cp_k w_k.
+// LDS per wave: PPW points x {C, g/RT, h/RT, cp/R, dC, dw, w} x nsp doubles.
+template <bool MIXED, int PPW>
+__global__ __launch_bounds__(256, 3) void k_jvp(DevMech m, int64_t n, const double *__restrict__ T,
+                                             const double *__restrict__ p, int64_t ps,
+                                             const double *__restrict__ Y, int64_t ld,
+                                             const double *__restrict__ vT, const double *__restrict__ vY,
+                                             double *__restrict__ jh, double *__restrict__ jw,
+                                             double *__restrict__ wdot, int nsp) {
+    constexpr int NA = 7;
+    extern __shared__ double lds[];
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    const int wpb = blockDim.x / WAVE;
+    const bool need_w = jh != nullptr || wdot != nullptr;
+    double *base = lds + (size_t)wave * PPW * NA * nsp;
+    const int64_t n_groups = (n + PPW - 1) / PPW;
+    for (int64_t g = (int64_t)blockIdx.x * wpb + wave; g < n_groups; g += (int64_t)gridDim.x * wpb) {
+        PointState st[PPW];
+        double dct[PPW], vt[PPW];
+        wave_lds_sync();
+#pragma unroll
+        for (int q = 0; q < PPW; ++q) {
+            double *C = base + (NA * q + 0) * nsp, *G = C + nsp, *H = G + nsp, *CP = H + nsp, *DC = CP + nsp,
+                   *DW = DC + nsp, *Wd = DW + nsp;
+            const int64_t i = g * PPW + q;
+            st[q] = load_point<true, true>(m, i, n, T, p, ps, Y, ld, C, G, H, CP);
+            const int64_t ii = st[q].valid ? i : 0;
+            vt[q] = vT ? vT[ii] : 0.0;
+            double sv = 0.0;
+            for (int k = lane; k < m.ns; k += WAVE) sv += vY[(int64_t)k * ld + ii] * m.invW[k];
+            const double s = vt[q] * st[q].invT + st[q].Wbar * wave_sum(sv);
+            double dsum = 0.0;
+            for (int k = lane; k < m.ns; k += WAVE) {
+                // C[k] was written by this lane (same k), so no synchronisation is needed
+                const double dc = st[q].rho * vY[(int64_t)k * ld + ii] * m.invW[k] - C[k] * s;
+                DC[k] = dc;
+                DW[k] = 0.0;
+                Wd[k] = 0.0;
+                dsum += dc;
+            }
+            dct[q] = wave_sum(dsum);
+        }
+        wave_lds_sync();
+        for (int x = lane; x < m.nr; x += WAVE) {
+            const int r = m.rxn_order[x];
+            const int info = m.info[r];
+            const RxnInts ri = m.ri[r];
+            const double lnA = m.lnA[r], bb = m.b[r], th = m.theta[r];
+            const int dsum = m.dnu_sum[r];
+            const int nre = info_nreac(info), npr = info_nprod(info);
+            const int n_exc = ri.v[7] & 255;
+#pragma unroll
+            for (int q = 0; q < PPW; ++q) {
+                double *C = base + (NA * q + 0) * nsp, *G = C + nsp, *H = G + nsp, *DC = H + 2 * nsp,
+                       *DW = DC + nsp, *Wd = DW + nsp;
+                RxnEval o;
+                eval_reaction<MIXED, true>(m, r, st[q], C, G, H, info, ri, lnA, bb, th, dsum, o);
+                double dq = o.t * vt[q];
+                if (o.mfac != 0.0) {
+                    double dM = dct[q];
+                    for (int e = 0; e < n_exc; ++e) dM += m.eff_m1[ri.v[6] + e] * DC[m.eff_sp[ri.v[6] + e]];
+                    dq += o.mfac * dM;
+                }
+#pragma unroll
+                for (int s = 0; s < SLOTS; ++s) {
+                    const bool used = s < MAX_SIDE ? s < nre : (s - MAX_SIDE) < npr;
+                    if (used) dq += o.d[s] * DC[ri.v[s]];
+                }
+#pragma unroll
+                for (int s = 0; s < SLOTS; ++s) {
+                    const bool used = s < MAX_SIDE ? s < nre : (s - MAX_SIDE) < npr;
+                    if (!used) continue;
+                    const double dn = (s < MAX_SIDE ? -1.0 : 1.0) * info_nu(info, s);
+                    atomicAdd(&DW[ri.v[s]], dn * dq);
+                    if (need_w) atomicAdd(&Wd[ri.v[s]], dn * o.q);
+                }
+            }
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int q = 0; q < PPW; ++q) {
+            if (!st[q].valid) continue;
+            const int64_t i = g * PPW + q;
+            const double *H = base + (NA * q + 2) * nsp, *CP = H + nsp, *DW = CP + 2 * nsp, *Wd = DW + nsp;
+            double hs = 0.0, cs = 0.0;
+            for (int k = lane; k < m.ns; k += WAVE) {
+                const double d = DW[k];
+                jw[(int64_t)k * ld + i] = d;
+                if (wdot) wdot[(int64_t)k * ld + i] = Wd[k];
+                hs += H[k] * d;
+                cs += CP[k] * Wd[k];
+            }
+            if (jh) {
+                hs = wave_sum(hs);
+                cs = wave_sum(cs);
+                if (lane == 0) jh[i] = -m.R * st[q].T * hs - vt[q] * m.R * cs;
+            }
+        }
     }
 }
 
@@ -1294,22 +1423,38 @@ hipError_t launch_thermo(const DevMech &m, int64_t n, const double *T, const dou
     return hipGetLastError();
 }
 
-hipError_t launch_wdot(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
-                       const double *Y, int64_t ld, double *wdot, double *hrr, double *rmass, hipStream_t st) {
+template <bool SRC>
+hipError_t launch_wdot_t(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
+                         const double *Y, int64_t ld, double *wdot, double *hrr, double *rmass, double *dTdt,
+                         double *QT, double dp0dt, hipStream_t st) {
     constexpr int PPW = 2;
+    constexpr int NA = SRC ? 5 : 4;
     const int nsp = pad_odd(m.ns);
-    const void *fn = mixed ? (const void *)k_wdot<true, PPW> : (const void *)k_wdot<false, PPW>;
+    const void *fn = mixed ? (const void *)k_wdot<true, PPW, SRC> : (const void *)k_wdot<false, PPW, SRC>;
     int WPB = 4;
     size_t shm = 0;
-    const hipError_t e = lds_waves(fn, (size_t)PPW * 4 * nsp * sizeof(double), WPB, shm);
+    const hipError_t e = lds_waves(fn, (size_t)PPW * NA * nsp * sizeof(double), WPB, shm);
     if (e != hipSuccess) return e;
     const int64_t groups = (n + PPW - 1) / PPW;
     const dim3 grid(grid_for(groups, WPB, 16)), block(WPB * WAVE);
     if (mixed)
-        hipLaunchKernelGGL((k_wdot<true, PPW>), grid, block, shm, st, m, n, T, p, ps, Y, ld, wdot, hrr, rmass, nsp);
+        hipLaunchKernelGGL((k_wdot<true, PPW, SRC>), grid, block, shm, st, m, n, T, p, ps, Y, ld, wdot, hrr, rmass,
+                           dTdt, QT, dp0dt, nsp);
     else
-        hipLaunchKernelGGL((k_wdot<false, PPW>), grid, block, shm, st, m, n, T, p, ps, Y, ld, wdot, hrr, rmass, nsp);
+        hipLaunchKernelGGL((k_wdot<false, PPW, SRC>), grid, block, shm, st, m, n, T, p, ps, Y, ld, wdot, hrr, rmass,
+                           dTdt, QT, dp0dt, nsp);
     return hipGetLastError();
+}
+
+hipError_t launch_wdot(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
+                       const double *Y, int64_t ld, double *wdot, double *hrr, double *rmass, hipStream_t st) {
+    return launch_wdot_t<false>(m, mixed, n, T, p, ps, Y, ld, wdot, hrr, rmass, nullptr, nullptr, 0.0, st);
+}
+
+hipError_t launch_source(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
+                         const double *Y, int64_t ld, double dp0dt, double *dYdt, double *dTdt, double *QT,
+                         double *hrr, hipStream_t st) {
+    return launch_wdot_t<true>(m, mixed, n, T, p, ps, Y, ld, dYdt, hrr, nullptr, dTdt, QT, dp0dt, st);
 }
 
 hipError_t launch_vjp(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
@@ -1326,6 +1471,36 @@ hipError_t launch_vjp(const DevMech &m, int mixed, int64_t n, const double *T, c
         hipLaunchKernelGGL((k_vjp<true>), grid, block, shm, st, m, n, T, p, ps, Y, ld, u, uh, gT, gY, nsp);
     else
         hipLaunchKernelGGL((k_vjp<false>), grid, block, shm, st, m, n, T, p, ps, Y, ld, u, uh, gT, gY, nsp);
+    return hipGetLastError();
+}
+
+hipError_t launch_jvp(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
+                      const double *Y, int64_t ld, const double *vT, const double *vY, double *jh, double *jw,
+                      double *wdot, hipStream_t st) {
+    const int nsp = pad_odd(m.ns);
+    const size_t per_point = (size_t)7 * nsp * sizeof(double);
+    // two points per wavefront while one wavefront's share fits the compute unit's LDS
+    const bool two = 2 * per_point <= (size_t)CU_LDS_BYTES;
+    const void *fn = two ? (mixed ? (const void *)k_jvp<true, 2> : (const void *)k_jvp<false, 2>)
+                         : (mixed ? (const void *)k_jvp<true, 1> : (const void *)k_jvp<false, 1>);
+    const int ppw = two ? 2 : 1;
+    int WPB = 4;
+    size_t shm = 0;
+    const hipError_t e = lds_waves(fn, ppw * per_point, WPB, shm);
+    if (e != hipSuccess) return e;
+    const int64_t groups = (n + ppw - 1) / ppw;
+    const dim3 grid(grid_for(groups, WPB, 16)), block(WPB * WAVE);
+    if (two) {
+        if (mixed)
+            hipLaunchKernelGGL((k_jvp<true, 2>), grid, block, shm, st, m, n, T, p, ps, Y, ld, vT, vY, jh, jw, wdot, nsp);
+        else
+            hipLaunchKernelGGL((k_jvp<false, 2>), grid, block, shm, st, m, n, T, p, ps, Y, ld, vT, vY, jh, jw, wdot, nsp);
+    } else {
+        if (mixed)
+            hipLaunchKernelGGL((k_jvp<true, 1>), grid, block, shm, st, m, n, T, p, ps, Y, ld, vT, vY, jh, jw, wdot, nsp);
+        else
+            hipLaunchKernelGGL((k_jvp<false, 1>), grid, block, shm, st, m, n, T, p, ps, Y, ld, vT, vY, jh, jw, wdot, nsp);
+    }
     return hipGetLastError();
 }
 

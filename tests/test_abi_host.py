@@ -127,7 +127,18 @@ def test_compute_calls_validate_before_launch(L, c0_path):
     # valid arguments on a host-only mechanism: device error, nothing launched
     assert L.crf_wdot(h, 0, 10, fake, fake, 1, fake, 10, fake, null, null, null) == 5
     assert b"without a device" in L.crf_last_error()
+    # J v: vY and jv_w are required; a host-only mechanism is a device error
+    assert L.crf_wdot_jvp(h, 0, 10, fake, fake, 1, fake, 10, null, null, null, fake, null, null) == 1
+    assert L.crf_wdot_jvp(h, 0, 10, fake, fake, 1, fake, 10, null, fake, null, null, null, null) == 1
+    assert L.crf_wdot_jvp(h, 0, 10, fake, fake, 1, fake, 10, null, fake, null, fake, null, null) == 5
+    # source terms: at least one output; dp0dt finite
+    assert L.crf_source(h, 0, 10, fake, fake, 1, fake, 10, ctypes.c_double(0.0), null, null, null, null, null) == 1
+    assert L.crf_source(h, 0, 10, fake, fake, 1, fake, 10, ctypes.c_double(float("inf")), fake, null, null, null,
+                        null) == 1
+    assert b"finite" in L.crf_last_error()
+    assert L.crf_source(h, 0, 10, fake, fake, 1, fake, 10, ctypes.c_double(0.0), fake, null, null, null, null) == 5
     # bad precision is checked after the state
+    assert L.crf_wdot_jvp(None, 0, 10, fake, fake, 1, fake, 10, null, fake, null, fake, null, null) == 1
     s2, h2 = _load(L, c0_path)
     L.crf_free_mech(h2)
     L.crf_free_mech(h)
