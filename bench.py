@@ -205,7 +205,15 @@ def main():
                 "wdot": n / (timed(lambda: crf.wdot(m, T, p, Y, prec, hrr=True), args.steps, 1, stream) * 1e-3) / 1e6,
                 "transport": n / (timed(lambda: crf.transport(m, T, p, Y, prec), max(2, args.steps // 4), 1, stream) * 1e-3) / 1e6,
                 "vjp": n / (timed(lambda: crf.wdot_vjp(m, T, p, Y, u, None, prec), args.steps, 1, stream) * 1e-3) / 1e6,
+                "jvp": n / (timed(lambda: crf.wdot_jvp(m, T, p, Y, u, T, prec), args.steps, 1, stream) * 1e-3) / 1e6,
+                "source": n / (timed(lambda: crf.source(m, T, p, Y, prec), args.steps, 1, stream) * 1e-3) / 1e6,
             }
+            work = crf.new_workspace(m, n, prec)
+            path[prec]["wdot_fwd_store"] = n / (timed(lambda: crf.wdot_fwd(m, T, p, Y, work, prec), args.steps, 1,
+                                                      stream) * 1e-3) / 1e6
+            path[prec]["vjp_stored"] = n / (timed(lambda: crf.wdot_vjp(m, T, p, Y, u, None, prec, work=work),
+                                                  args.steps, 1, stream) * 1e-3) / 1e6
+            del work
         if "fp64" in path:
             path["fp64"]["thermo"] = n / (timed(lambda: crf.thermo(m, T, p, Y), args.steps, 1, stream) * 1e-3) / 1e6
         m.close()

@@ -61,8 +61,12 @@ typedef enum {
     CRF_E_MECH = 3,         /* mechanism inconsistent (element balance, indices, ranges) */
     CRF_E_NOMEM = 4,        /* host or device allocation failed */
     CRF_E_DEVICE = 5,       /* device error, or a compute call on a host-only mechanism */
-    CRF_E_UNSUPPORTED = 6   /* valid file using a feature this library does not evaluate */
+    CRF_E_UNSUPPORTED = 6,  /* valid file using a feature this library does not evaluate */
+    CRF_E_WORKSPACE = 7     /* workspace missing, too small (crf_workspace_bytes) or misaligned */
 } crf_status;
+
+/* Operations that take a caller-allocated workspace (crf_workspace_bytes). */
+typedef enum { CRF_OP_VJP = 1 } crf_op;
 
 typedef enum { CRF_FP64 = 0, CRF_MIXED = 1 } crf_precision;
 
@@ -132,14 +136,37 @@ crf_status crf_transport(const crf_mech *m, crf_precision prec, int64_t n, const
 
 /* ---------------------------------------------------------------- derivatives */
 
+/* Bytes of workspace that operation `op` needs for n points (0 and CRF_E_ARG in
+ * crf_last_error for invalid arguments).  CRF_OP_VJP: the rate intermediates that
+ * crf_wdot_fwd stores and crf_wdot_vjp reuses, 32 bytes per reaction and point (k_f,
+ * 1/K_c, dk_f/dT, dk_f/d[M], FP64 in both modes).  Whether to store them or to let the
+ * VJP recompute them is the caller's choice against its memory budget; the Python
+ * binding stores them while they fit in CRF_HBM_BUDGET bytes (unset: recompute). */
+size_t crf_workspace_bytes(const crf_mech *m, crf_precision prec, int op, int64_t n);
+
+/* Production rates as crf_wdot (wdot required, hrr and mass_resid nullable) that also
+ * store, in the caller's workspace `work` (work_bytes >= crf_workspace_bytes(m, prec,
+ * CRF_OP_VJP, n), 16-byte aligned, else CRF_E_WORKSPACE), the rate constants and their
+ * derivatives of every reaction at every point, for a later crf_wdot_vjp at the same
+ * state: the forward half of a reverse-mode step that keeps its intermediates. */
+crf_status crf_wdot_fwd(const crf_mech *m, crf_precision prec, int64_t n, const double *T, const double *p,
+                        int64_t p_stride, const double *Y, int64_t ld,
+                        double *wdot, double *hrr, double *mass_resid, void *work, size_t work_bytes,
+                        crf_stream stream);
+
 /* Vector-Jacobian product of (hrr, w_1..w_Ns) with respect to (T, Y_1..Y_Ns) at
  * fixed p: gT[i] = u_hrr[i] dhrr/dT + sum_k u[k*ld+i] dw_k/dT and
  * gY[j*ld + i] = u_hrr[i] dhrr/dY_j + sum_k u[k*ld+i] dw_k/dY_j.
- * u_hrr nullable (treated as zero).  Rate intermediates are recomputed, never stored. */
+ * u_hrr nullable (treated as zero).
+ * work == NULL (work_bytes ignored): every rate intermediate is recomputed.
+ * Otherwise work must hold what crf_wdot_fwd stored for the same mechanism, precision,
+ * n, T, p and Y (not checked: other contents give meaningless results) and
+ * work_bytes >= crf_workspace_bytes(m, prec, CRF_OP_VJP, n), 16-byte aligned, else
+ * CRF_E_WORKSPACE; the rate constants are then read, not re-evaluated. */
 crf_status crf_wdot_vjp(const crf_mech *m, crf_precision prec, int64_t n, const double *T,
                         const double *p, int64_t p_stride, const double *Y, int64_t ld,
                         const double *u, const double *u_hrr, double *gT, double *gY,
-                        crf_stream stream);
+                        const void *work, size_t work_bytes, crf_stream stream);
 
 /* Jacobian-vector product (forward mode) of (hrr, w_1..w_Ns) with respect to
  * (T, Y_1..Y_Ns) at fixed p, along the tangent v = (vT, vY): the directional

@@ -7,11 +7,12 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcrf.so")
 EXPORTED = (
     "crf_load_mech", "crf_free_mech", "crf_n_species", "crf_n_reactions", "crf_device", "crf_jac_plan",
     "crf_last_error", "crf_status_str", "crf_thermo", "crf_wdot", "crf_transport",
-    "crf_wdot_vjp", "crf_wdot_jac", "crf_wdot_jvp", "crf_source",
+    "crf_wdot_vjp", "crf_wdot_jac", "crf_wdot_jvp", "crf_source", "crf_workspace_bytes", "crf_wdot_fwd",
 )
 
-CRF_OK, CRF_E_ARG, CRF_E_PARSE, CRF_E_MECH, CRF_E_NOMEM, CRF_E_DEVICE, CRF_E_UNSUPPORTED = range(7)
+CRF_OK, CRF_E_ARG, CRF_E_PARSE, CRF_E_MECH, CRF_E_NOMEM, CRF_E_DEVICE, CRF_E_UNSUPPORTED, CRF_E_WORKSPACE = range(8)
 CRF_FP64, CRF_MIXED = 0, 1
+CRF_OP_VJP = 1
 
 _lib = None
 
@@ -24,7 +25,7 @@ class CrfError(RuntimeError):
 
 def status_name(s):
     return ["CRF_OK", "CRF_E_ARG", "CRF_E_PARSE", "CRF_E_MECH", "CRF_E_NOMEM", "CRF_E_DEVICE",
-            "CRF_E_UNSUPPORTED"][s] if 0 <= s < 7 else f"status {s}"
+            "CRF_E_UNSUPPORTED", "CRF_E_WORKSPACE"][s] if 0 <= s < 8 else f"status {s}"
 
 
 def lib():
@@ -57,7 +58,8 @@ def lib():
     L.crf_wdot.restype = I
     L.crf_transport.argtypes = [P, I, I64, D, D, I64, D, I64, D, D, D, P]
     L.crf_transport.restype = I
-    L.crf_wdot_vjp.argtypes = [P, I, I64, D, D, I64, D, I64, D, D, D, D, P]
+    SZ = ctypes.c_size_t
+    L.crf_wdot_vjp.argtypes = [P, I, I64, D, D, I64, D, I64, D, D, D, D, D, SZ, P]
     L.crf_wdot_vjp.restype = I
     L.crf_wdot_jac.argtypes = [P, I, I64, D, D, I64, D, I64, D, D, P]
     L.crf_wdot_jac.restype = I
@@ -65,6 +67,10 @@ def lib():
     L.crf_wdot_jvp.restype = I
     L.crf_source.argtypes = [P, I, I64, D, D, I64, D, I64, ctypes.c_double, D, D, D, D, P]
     L.crf_source.restype = I
+    L.crf_workspace_bytes.argtypes = [P, I, I, I64]
+    L.crf_workspace_bytes.restype = SZ
+    L.crf_wdot_fwd.argtypes = [P, I, I64, D, D, I64, D, I64, D, D, D, D, SZ, P]
+    L.crf_wdot_fwd.restype = I
     _lib = L
     return L
 

@@ -10,11 +10,12 @@ same layout.
 from __future__ import annotations
 
 import ctypes
+import os
 
 import torch
 
 from . import _lib
-from ._lib import CRF_FP64, CRF_MIXED, CrfError, check
+from ._lib import CRF_FP64, CRF_MIXED, CRF_OP_VJP, CrfError, check
 
 _PREC = {"fp64": CRF_FP64, "mixed": CRF_MIXED}
 
@@ -151,8 +152,37 @@ def transport(m, T, p, Y, precision="fp64"):
     return mu, lam, D
 
 
-def wdot_vjp(m, T, p, Y, u, u_hrr=None, precision="fp64"):
-    """(gT [n], gY [n, Ns]) = u^T d(hrr, w)/d(T, Y); u in the same layout as Y."""
+def workspace_bytes(m, n, precision="fp64"):
+    """Bytes of the rate intermediates that wdot_fwd stores for a later wdot_vjp (n points)."""
+    b = _lib.lib().crf_workspace_bytes(m.handle, _prec(precision), CRF_OP_VJP, int(n))
+    if b == 0 and n > 0 and m.n_reactions > 0:
+        raise CrfError(1, _lib.lib().crf_last_error().decode())
+    return b
+
+
+def new_workspace(m, n, precision="fp64"):
+    """A device buffer of workspace_bytes(m, n) bytes (torch allocations are 512-byte aligned)."""
+    return torch.empty(max(workspace_bytes(m, n, precision), 1), dtype=torch.uint8,
+                       device=torch.device("cuda", m.device))
+
+
+def wdot_fwd(m, T, p, Y, work, precision="fp64", hrr=True):
+    """(wdot [n, Ns], hrr [n] or None), storing the rate intermediates in `work` for wdot_vjp."""
+    n, p, ps, ld, dev = _state(m, T, p, Y)
+    if work.dtype != torch.uint8 or work.device != dev or not work.is_contiguous():
+        raise ValueError("work must be a contiguous uint8 tensor on the mechanism's device")
+    w = _species_out(m.n_species, n, ld, dev)
+    h = torch.empty(n, dtype=torch.float64, device=dev) if hrr else None
+    check(_lib.lib().crf_wdot_fwd(m.handle, _prec(precision), n, _ptr(T), _ptr(p), ps, _ptr(Y), ld,
+                                  _ptr(w), _ptr(h), _ptr(None), _ptr(work), work.numel(), _stream(dev)))
+    return w, h
+
+
+def wdot_vjp(m, T, p, Y, u, u_hrr=None, precision="fp64", work=None):
+    """(gT [n], gY [n, Ns]) = u^T d(hrr, w)/d(T, Y); u in the same layout as Y.
+
+    work: the buffer a wdot_fwd call at the same state filled (the rate constants are
+    then reused), or None (recomputed)."""
     n, p, ps, ld, dev = _state(m, T, p, Y)
     ns = m.n_species
     if u.dtype != torch.float64 or u.shape != (n, ns) or u.device != dev or (n > 0 and ns > 1 and
@@ -160,11 +190,27 @@ def wdot_vjp(m, T, p, Y, u, u_hrr=None, precision="fp64"):
         raise ValueError("u must be a float64 [n, Ns] tensor with the same species-major layout as Y")
     if u_hrr is not None and (u_hrr.dtype != torch.float64 or u_hrr.shape != (n,) or not u_hrr.is_contiguous()):
         raise ValueError("u_hrr must be a contiguous float64 [n] tensor")
+    if work is not None and (work.dtype != torch.uint8 or work.device != dev or not work.is_contiguous()):
+        raise ValueError("work must be a contiguous uint8 tensor on the mechanism's device")
     gT = torch.empty(n, dtype=torch.float64, device=dev)
     gY = _species_out(ns, n, ld, dev)
     check(_lib.lib().crf_wdot_vjp(m.handle, _prec(precision), n, _ptr(T), _ptr(p), ps, _ptr(Y), ld,
-                                  _ptr(u), _ptr(u_hrr), _ptr(gT), _ptr(gY), _stream(dev)))
+                                  _ptr(u), _ptr(u_hrr), _ptr(gT), _ptr(gY), _ptr(work),
+                                  0 if work is None else work.numel(), _stream(dev)))
     return gT, gY
+
+
+def hbm_budget(dev):
+    """Bytes the autograd forward may keep for the backward: CRF_HBM_BUDGET if set (then
+    capped at the device memory free now), else 0.  The default recomputes: on MI355X the
+    VJP kernel is not limited by the rate constants' exponentials, and reading them back
+    (32 bytes per reaction and point) made it slower, not faster (53 species: 103.5
+    against 113 M points/s in FP64)."""
+    env = os.environ.get("CRF_HBM_BUDGET")
+    if not env:
+        return 0
+    free, _ = torch.cuda.mem_get_info(dev)
+    return min(int(float(env)), free)
 
 
 def wdot_jvp(m, T, p, Y, vY, vT=None, precision="fp64", with_hrr=True, with_wdot=False):
@@ -215,13 +261,24 @@ def wdot_jac(m, T, p, Y, precision="fp64", with_wdot=True, out=None):
 
 
 class WdotFn(torch.autograd.Function):
-    """(wdot, hrr) = WdotFn.apply(T, Y, p, mech, precision); backward = crf_wdot_vjp."""
+    """(wdot, hrr) = WdotFn.apply(T, Y, p, mech, precision); backward = crf_wdot_vjp.
+
+    The forward keeps the rate intermediates (crf_wdot_fwd) when they fit the HBM budget
+    (hbm_budget: CRF_HBM_BUDGET bytes, 0 when unset); otherwise the backward recomputes
+    them."""
 
     @staticmethod
     def forward(ctx, T, Y, p, mech, precision="fp64"):
-        w, h, _ = wdot(mech, T, p, Y, precision=precision, hrr=True)
+        n = T.shape[0]
+        need = workspace_bytes(mech, n, precision)
+        work = None
+        if 0 < need <= hbm_budget(T.device):
+            work = new_workspace(mech, n, precision)
+            w, h = wdot_fwd(mech, T, p, Y, work, precision=precision, hrr=True)
+        else:
+            w, h, _ = wdot(mech, T, p, Y, precision=precision, hrr=True)
         ctx.save_for_backward(T, Y)
-        ctx.mech, ctx.p, ctx.precision = mech, p, precision
+        ctx.mech, ctx.p, ctx.precision, ctx.work = mech, p, precision, work
         return w, h
 
     @staticmethod
@@ -234,9 +291,10 @@ class WdotFn(torch.autograd.Function):
             u2.copy_(u)
             u = u2
         uh = None if g_h is None else g_h.contiguous()
-        gT, gY = wdot_vjp(ctx.mech, T, ctx.p, Y, u, uh, precision=ctx.precision)
+        gT, gY = wdot_vjp(ctx.mech, T, ctx.p, Y, u, uh, precision=ctx.precision, work=ctx.work)
+        ctx.work = None
         return gT, gY, None, None, None
 
 
 __all__ = ["Mechanism", "species_major", "thermo", "wdot", "transport", "wdot_vjp", "wdot_jvp", "wdot_jac",
-           "source", "WdotFn", "CrfError"]
+           "wdot_fwd", "workspace_bytes", "new_workspace", "hbm_budget", "source", "WdotFn", "CrfError"]

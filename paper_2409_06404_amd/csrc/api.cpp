@@ -111,6 +111,7 @@ const char *crf_status_str(crf_status s) {
         case CRF_E_NOMEM: return "CRF_E_NOMEM";
         case CRF_E_DEVICE: return "CRF_E_DEVICE";
         case CRF_E_UNSUPPORTED: return "CRF_E_UNSUPPORTED";
+        case CRF_E_WORKSPACE: return "CRF_E_WORKSPACE";
     }
     return "CRF_UNKNOWN_STATUS";
 }
@@ -138,7 +139,7 @@ crf_status crf_wdot(const crf_mech *m, crf_precision prec, int64_t n, const doub
     if (check_device(m, "crf_wdot") != CRF_OK) return CRF_E_DEVICE;
     if (n == 0) return CRF_OK;
     return on_device(m, "crf_wdot", [&] {
-        return launch_wdot(m->dev, prec == CRF_MIXED, n, T, p, ps, Y, ld, wdot, hrr, mass_resid,
+        return launch_wdot(m->dev, prec == CRF_MIXED, n, T, p, ps, Y, ld, wdot, hrr, mass_resid, nullptr,
                            (hipStream_t)stream);
     });
 }
@@ -157,18 +158,56 @@ crf_status crf_transport(const crf_mech *m, crf_precision prec, int64_t n, const
     });
 }
 
+size_t crf_workspace_bytes(const crf_mech *m, crf_precision prec, int op, int64_t n) {
+    if (!m) { fail(CRF_E_ARG, "crf_workspace_bytes: mechanism is NULL"); return 0; }
+    if (check_prec(prec, "crf_workspace_bytes") != CRF_OK) return 0;
+    if (n < 0 || n > ((int64_t)1 << 40)) { fail(CRF_E_ARG, "crf_workspace_bytes: n out of range"); return 0; }
+    if (op != CRF_OP_VJP) { fail(CRF_E_ARG, "crf_workspace_bytes: unknown operation"); return 0; }
+    return (size_t)n * (size_t)m->host.nr() * VJP_WORK_PER_RXN;
+}
+
+namespace {
+crf_status check_work(const crf_mech *m, int64_t n, const void *work, size_t work_bytes, const char *fn) {
+    const size_t need = (size_t)n * (size_t)m->host.nr() * VJP_WORK_PER_RXN;
+    if (!work) return fail(CRF_E_WORKSPACE, std::string(fn) + ": work is NULL");
+    if (((uintptr_t)work & 15) != 0) return fail(CRF_E_WORKSPACE, std::string(fn) + ": work must be 16-byte aligned");
+    if (work_bytes < need)
+        return fail(CRF_E_WORKSPACE, std::string(fn) + ": work_bytes " + std::to_string(work_bytes) + " < " +
+                                         std::to_string(need) + " needed");
+    return CRF_OK;
+}
+}  // namespace
+
+crf_status crf_wdot_fwd(const crf_mech *m, crf_precision prec, int64_t n, const double *T, const double *p,
+                        int64_t ps, const double *Y, int64_t ld, double *wdot, double *hrr, double *mass_resid,
+                        void *work, size_t work_bytes, crf_stream stream) {
+    crf_status s = check_state(m, n, T, p, ps, Y, ld, "crf_wdot_fwd");
+    if (s == CRF_OK) s = check_prec(prec, "crf_wdot_fwd");
+    if (s != CRF_OK) return s;
+    if (n > 0 && !wdot) return fail(CRF_E_ARG, "crf_wdot_fwd: wdot must not be NULL");
+    if (n > 0 && check_work(m, n, work, work_bytes, "crf_wdot_fwd") != CRF_OK) return CRF_E_WORKSPACE;
+    if (check_device(m, "crf_wdot_fwd") != CRF_OK) return CRF_E_DEVICE;
+    if (n == 0) return CRF_OK;
+    return on_device(m, "crf_wdot_fwd", [&] {
+        return launch_wdot(m->dev, prec == CRF_MIXED, n, T, p, ps, Y, ld, wdot, hrr, mass_resid, (double *)work,
+                           (hipStream_t)stream);
+    });
+}
+
 crf_status crf_wdot_vjp(const crf_mech *m, crf_precision prec, int64_t n, const double *T,
                         const double *p, int64_t ps, const double *Y, int64_t ld, const double *u,
-                        const double *u_hrr, double *gT, double *gY, crf_stream stream) {
+                        const double *u_hrr, double *gT, double *gY, const void *work, size_t work_bytes,
+                        crf_stream stream) {
     crf_status s = check_state(m, n, T, p, ps, Y, ld, "crf_wdot_vjp");
     if (s == CRF_OK) s = check_prec(prec, "crf_wdot_vjp");
     if (s != CRF_OK) return s;
     if (n > 0 && (!u || !gT || !gY)) return fail(CRF_E_ARG, "crf_wdot_vjp: u, gT and gY must not be NULL");
+    if (n > 0 && work && check_work(m, n, work, work_bytes, "crf_wdot_vjp") != CRF_OK) return CRF_E_WORKSPACE;
     if (check_device(m, "crf_wdot_vjp") != CRF_OK) return CRF_E_DEVICE;
     if (n == 0) return CRF_OK;
     return on_device(m, "crf_wdot_vjp", [&] {
         return launch_vjp(m->dev, prec == CRF_MIXED, n, T, p, ps, Y, ld, u, u_hrr, gT, gY,
-                          (hipStream_t)stream);
+                          (const double *)work, (hipStream_t)stream);
     });
 }
 

@@ -28,6 +28,8 @@ constexpr int SLOTS = 6;
 // wavefront), and the row-block Jacobian one row of accumulators besides its species
 // state.  Larger files are refused at load with CRF_E_UNSUPPORTED.
 constexpr int MAX_SPECIES = 2048;
+// Workspace of the stored-intermediate VJP: k_f, 1/K_c, dk_f/dT, dk_f/d[M] per reaction and point.
+constexpr size_t VJP_WORK_PER_RXN = 4 * sizeof(double);
 // LDS of one compute unit (gfx950), the most one workgroup may request.
 constexpr int CU_LDS_BYTES = 160 * 1024;
 
@@ -168,13 +170,13 @@ hipError_t launch_thermo(const DevMech &m, int64_t n, const double *T, const dou
                          hipStream_t st);
 hipError_t launch_wdot(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
                        int64_t ps, const double *Y, int64_t ld, double *wdot, double *hrr,
-                       double *rmass, hipStream_t st);
+                       double *rmass, double *work, hipStream_t st);
 hipError_t launch_transport(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
                             int64_t ps, const double *Y, int64_t ld, double *mu, double *lam,
                             double *Dmix, hipStream_t st);
 hipError_t launch_vjp(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
                       int64_t ps, const double *Y, int64_t ld, const double *u, const double *uh,
-                      double *gT, double *gY, hipStream_t st);
+                      double *gT, double *gY, const double *work, hipStream_t st);
 hipError_t launch_jvp(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
                       int64_t ps, const double *Y, int64_t ld, const double *vT, const double *vY,
                       double *jh, double *jw, double *wdot, hipStream_t st);

@@ -183,25 +183,34 @@ struct RxnEval {
     double mfac;         // dq/d[M] (three-body and falloff), else 0
     double t;            // dq/dT at fixed concentrations
     double sigma;        // sum_j C_j dq/dC_j over all species (incl. efficiency part)
+    double invKc;        // 1 / K_c
 };
 
-// Rate of progress of reaction `r` (and, with DERIV, its derivatives).
-// MIXED: Arrhenius exponentials and Troe blending in FP32; everything else FP64.
-template <bool MIXED, bool DERIV>
-__device__ inline void eval_reaction(const DevMech &m, int r, const PointState &ps, const double *C,
-                                     const double *gRT, const double *hRT, int info, const RxnInts &ri,
-                                     double lnA, double bb, double th, int dnu_sum, RxnEval &o) {
-    using Rt = typename std::conditional<MIXED, float, double>::type;
-    const int kind = info_kind(info);
-    const int nre = info_nreac(info), npr = info_nprod(info);
-    // third-body concentration [M] = Ctot + sum_exc (eps - 1) C_k
-    double M = 0.0;
+// Rate constant of one reaction and its partial derivatives: the transcendental part
+// of a reaction's evaluation (what the forward pass stores for the VJP to reuse).
+struct RateK {
+    double M;            // third-body concentration [M] (0 for elementary reactions)
+    double kf;           // forward rate constant (falloff-blended), without the [M] factor
+    double dkfT;         // dk_f/dT at fixed [M]
+    double dkfM;         // dk_f/d[M] at fixed T (falloff only, else 0)
+};
+
+// [M] = Ctot + sum_exc (eps - 1) C_k of a third-body or falloff reaction.
+__device__ inline double third_body(const DevMech &m, const RxnInts &ri, double Ctot, const double *C) {
+    double M = Ctot;
     const int n_exc = ri.v[7] & 255;
-    if (kind != RXN_ELEMENTARY) {
-        M = ps.Ctot;
-        for (int e = 0; e < n_exc; ++e) M += m.eff_m1[ri.v[6] + e] * C[m.eff_sp[ri.v[6] + e]];
-    }
-    // forward rate constant
+    for (int e = 0; e < n_exc; ++e) M += m.eff_m1[ri.v[6] + e] * C[m.eff_sp[ri.v[6] + e]];
+    return M;
+}
+
+// Rate constant (with DERIV, its derivatives).  MIXED: Arrhenius exponentials and Troe
+// blending in FP32.
+template <bool MIXED, bool DERIV>
+__device__ inline RateK rate_constant(const DevMech &m, const PointState &ps, const double *C, int kind,
+                                      const RxnInts &ri, double lnA, double bb, double th) {
+    using Rt = typename std::conditional<MIXED, float, double>::type;
+    RateK k;
+    k.M = kind != RXN_ELEMENTARY ? third_body(m, ri, ps.Ctot, C) : 0.0;
     const Rt lnT = (Rt)ps.lnT, invT = (Rt)ps.invT, T = (Rt)ps.T;
     const Rt lnkinf = (Rt)lnA + (Rt)bb * lnT - (Rt)th * invT;
     const Rt kinf = exp_r<Rt>(lnkinf);
@@ -212,7 +221,7 @@ __device__ inline void eval_reaction(const DevMech &m, int r, const PointState &
         const Rt lnA0 = (Rt)tp[0], b0 = (Rt)tp[1], th0 = (Rt)tp[2], alpha = (Rt)tp[3];
         const Rt iT3 = (Rt)tp[4], iT1 = (Rt)tp[5], T2 = (Rt)tp[6];
         const Rt lnk0 = lnA0 + b0 * lnT - th0 * invT;
-        const Rt lnM = log_r<Rt>((Rt)M);
+        const Rt lnM = log_r<Rt>((Rt)k.M);
         const Rt lnPr = lnk0 - lnkinf + lnM;
         const Rt Pr = exp_r<Rt>(lnPr);
         const Rt e3 = exp_r<Rt>(-T * iT3), e1 = exp_r<Rt>(-T * iT1), e2 = exp_r<Rt>(-T2 * invT);
@@ -247,7 +256,23 @@ __device__ inline void eval_reaction(const DevMech &m, int r, const PointState &
             dkf_dM = k0 * F * ip1 * (ip1 + dlogF_dell);
         }
     }
-    // equilibrium constant: ln K_c = -sum dnu_k g_k/RT + dnu ln(p0/RT)   (always FP64)
+    k.kf = (double)kf;
+    k.dkfT = (double)dkf_dT;
+    k.dkfM = (double)dkf_dM;
+    return k;
+}
+
+// Rate of progress of a reaction from its rate constant (and, with DERIV, its
+// derivatives): equilibrium constant, concentration products, q, dq/dC of every slot,
+// dq/dT at fixed C, dq/d[M].  All FP64.  invKc_in >= 0 supplies 1/K_c (a stored value);
+// a negative value forms it from the Gibbs sums of the slots.
+template <bool DERIV>
+__device__ inline void reaction_rates(const PointState &ps, const double *C, const double *gRT, const double *hRT,
+                                      int info, const RxnInts &ri, int dnu_sum, const RateK &k, double invKc_in,
+                                      RxnEval &o) {
+    const int kind = info_kind(info);
+    const int nre = info_nreac(info), npr = info_nprod(info);
+    // equilibrium constant: ln K_c = -sum dnu_k g_k/RT + dnu ln(p0/RT)
     double lnKc = (double)dnu_sum * ps.lnp0RT;
     double dlnKc = -(double)dnu_sum;
     double pf = 1.0, pr = 1.0;
@@ -255,30 +280,31 @@ __device__ inline void eval_reaction(const DevMech &m, int r, const PointState &
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const bool used = s < MAX_SIDE ? s < nre : (s - MAX_SIDE) < npr;
-        const int k = used ? ri.v[s] : 0;
+        const int kk = used ? ri.v[s] : 0;
         const int nu = used ? info_nu(info, s) : 0;
         const double sgn = s < MAX_SIDE ? -1.0 : 1.0;
-        const double c = used ? C[k] : 1.0;
+        const double c = used ? C[kk] : 1.0;
         Cs[s] = c;
         Ps[s] = ipow(c, nu);
         if (used) {
-            lnKc -= sgn * nu * gRT[k];
-            if (DERIV) dlnKc += sgn * nu * hRT[k];
+            if (invKc_in < 0.0) lnKc -= sgn * nu * gRT[kk];
+            if (DERIV) dlnKc += sgn * nu * hRT[kk];
         }
         if (s < MAX_SIDE) pf *= Ps[s]; else pr *= Ps[s];
     }
     // 1/K_c in FP64 in both modes: near equilibrium q = k_f (prod_f - prod_r / K_c) is
     // decided by this factor, so its relative error becomes the error of q
-    const double invKc = exp_fast(-lnKc);
-    const double kfd = (double)kf;
-    const double fac = kind == RXN_THREEBODY ? M : 1.0;
+    const double invKc = invKc_in >= 0.0 ? invKc_in : exp_fast(-lnKc);
+    o.invKc = invKc;
+    const double kfd = k.kf;
+    const double fac = kind == RXN_THREEBODY ? k.M : 1.0;
     const double krd = kfd * invKc;
     o.q = fac * (kfd * pf - krd * pr);
     if (DERIV) {
         dlnKc *= ps.invT;
         const double bracket = pf - invKc * pr;
-        o.t = fac * ((double)dkf_dT * bracket + krd * pr * dlnKc);
-        o.mfac = kind == RXN_THREEBODY ? kfd * bracket : kind == RXN_TROE ? (double)dkf_dM * bracket : 0.0;
+        o.t = fac * (k.dkfT * bracket + krd * pr * dlnKc);
+        o.mfac = kind == RXN_THREEBODY ? kfd * bracket : kind == RXN_TROE ? k.dkfM * bracket : 0.0;
         double sig = 0.0;
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
@@ -296,8 +322,18 @@ __device__ inline void eval_reaction(const DevMech &m, int r, const PointState &
             sig += d * Cs[s];
         }
         // efficiency part of sum_j C_j dq/dC_j: mfac * sum_j eps_j C_j = mfac * [M]
-        o.sigma = sig + o.mfac * M;
+        o.sigma = sig + o.mfac * k.M;
     }
+}
+
+// Rate of progress of reaction `r` (and, with DERIV, its derivatives).
+// MIXED: Arrhenius exponentials and Troe blending in FP32; everything else FP64.
+template <bool MIXED, bool DERIV>
+__device__ inline void eval_reaction(const DevMech &m, int r, const PointState &ps, const double *C,
+                                     const double *gRT, const double *hRT, int info, const RxnInts &ri,
+                                     double lnA, double bb, double th, int dnu_sum, RxnEval &o) {
+    const RateK k = rate_constant<MIXED, DERIV>(m, ps, C, info_kind(info), ri, lnA, bb, th);
+    reaction_rates<DERIV>(ps, C, gRT, hRT, info, ri, dnu_sum, k, -1.0, o);
 }
 
 // ------------------------------------------------------------------ thermo
@@ -341,13 +377,17 @@ __global__ __launch_bounds__(256) void k_thermo(DevMech m, int64_t n, const doub
 //   Q_T = (1/T) dT/dt + sum_k (Wbar/W_k) dY_k/dt - (dp0/dt)/p
 // with c_p = sum_k Y_k cp_k / W_k = (R/rho) sum_k C_k cp_k/R and
 // sum_k (Wbar/W_k) dY_k/dt = (Wbar/rho) sum_k w_k.
-template <bool MIXED, int PPW, bool SRC>
+// STORE: also writes every reaction's (k_f, 1/K_c, dk_f/dT, dk_f/d[M]) to
+// work[(i * nr + x) * 4 + 0..3] (x = the reaction's position in the processing order),
+// the transcendental part of the rates that the stored-intermediate VJP reuses.
+template <bool MIXED, int PPW, bool SRC, bool STORE>
 __global__ __launch_bounds__(256, 3) void k_wdot(DevMech m, int64_t n, const double *__restrict__ T,
                                               const double *__restrict__ p, int64_t ps,
                                               const double *__restrict__ Y, int64_t ld,
                                               double *__restrict__ wdot, double *__restrict__ hrr,
                                               double *__restrict__ rmass, double *__restrict__ dTdt,
-                                              double *__restrict__ QT, double dp0dt, int nsp) {
+                                              double *__restrict__ QT, double dp0dt, int nsp,
+                                              double *__restrict__ work) {
     constexpr int NA = SRC ? 5 : 4;
     extern __shared__ double lds[];
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
@@ -375,7 +415,18 @@ __global__ __launch_bounds__(256, 3) void k_wdot(DevMech m, int64_t n, const dou
             for (int q = 0; q < PPW; ++q) {
                 double *C = base + (NA * q + 0) * nsp, *G = C + nsp, *Wd = C + 3 * nsp;
                 RxnEval o;
-                eval_reaction<MIXED, false>(m, r, st[q], C, G, nullptr, info, ri, lnA, bb, th, dsum, o);
+                if constexpr (STORE) {
+                    const RateK k = rate_constant<MIXED, true>(m, st[q], C, info_kind(info), ri, lnA, bb, th);
+                    reaction_rates<false>(st[q], C, G, nullptr, info, ri, dsum, k, -1.0, o);
+                    const int64_t i = g * PPW + q;
+                    if (st[q].valid) {
+                        f64x2 *w = (f64x2 *)(work + ((size_t)i * m.nr + x) * 4);
+                        w[0] = f64x2{k.kf, o.invKc};
+                        w[1] = f64x2{k.dkfT, k.dkfM};
+                    }
+                } else {
+                    eval_reaction<MIXED, false>(m, r, st[q], C, G, nullptr, info, ri, lnA, bb, th, dsum, o);
+                }
 #pragma unroll
                 for (int s = 0; s < SLOTS; ++s) {
                     const bool used = s < MAX_SIDE ? s < nre : (s - MAX_SIDE) < npr;
@@ -425,12 +476,16 @@ __global__ __launch_bounds__(256, 3) void k_wdot(DevMech m, int64_t n, const dou
 
 // ------------------------------------------------------------------ VJP
 // LDS per wave: {C, g/RT, h/RT, cp/R, u, gC, w} x nsp doubles (one point at a time).
-template <bool MIXED>
+// STORED: the rate constants and their derivatives come from the forward pass's work
+// array (k_wdot with STORE) instead of being recomputed; the rest (concentration
+// products, equilibrium-constant derivative, chain rule) is formed here.
+template <bool MIXED, bool STORED>
 __global__ __launch_bounds__(256, 3) void k_vjp(DevMech m, int64_t n, const double *__restrict__ T,
                                              const double *__restrict__ p, int64_t ps,
                                              const double *__restrict__ Y, int64_t ld,
                                              const double *__restrict__ u, const double *__restrict__ uh,
-                                             double *__restrict__ gT, double *__restrict__ gY, int nsp) {
+                                             double *__restrict__ gT, double *__restrict__ gY, int nsp,
+                                             const double *__restrict__ work) {
     extern __shared__ double lds[];
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
     const int wpb = blockDim.x / WAVE;
@@ -453,8 +508,19 @@ __global__ __launch_bounds__(256, 3) void k_vjp(DevMech m, int64_t n, const doub
             const int info = m.info[r];
             const RxnInts ri = m.ri[r];
             RxnEval o;
-            eval_reaction<MIXED, true>(m, r, st, C, G, H, info, ri, m.lnA[r], m.b[r], m.theta[r],
-                                       m.dnu_sum[r], o);
+            if constexpr (STORED) {
+                const f64x2 *w = (const f64x2 *)(work + ((size_t)i * m.nr + x) * 4);
+                const f64x2 a = w[0], b = w[1];
+                RateK k;
+                k.M = info_kind(info) != RXN_ELEMENTARY ? third_body(m, ri, st.Ctot, C) : 0.0;
+                k.kf = a.x;
+                k.dkfT = b.x;
+                k.dkfM = b.y;
+                reaction_rates<true>(st, C, G, H, info, ri, m.dnu_sum[r], k, a.y, o);
+            } else {
+                eval_reaction<MIXED, true>(m, r, st, C, G, H, info, ri, m.lnA[r], m.b[r], m.theta[r],
+                                           m.dnu_sum[r], o);
+            }
             const int nre = info_nreac(info), npr = info_nprod(info);
             // ubar = sum_k dnu_k (u_k - u_hrr h_k)   (the hrr row is -sum_k h_k w_k)
             double ub = 0.0;
@@ -1423,14 +1489,14 @@ hipError_t launch_thermo(const DevMech &m, int64_t n, const double *T, const dou
     return hipGetLastError();
 }
 
-template <bool SRC>
+template <bool SRC, bool STORE>
 hipError_t launch_wdot_t(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
                          const double *Y, int64_t ld, double *wdot, double *hrr, double *rmass, double *dTdt,
-                         double *QT, double dp0dt, hipStream_t st) {
+                         double *QT, double dp0dt, double *work, hipStream_t st) {
     constexpr int PPW = 2;
     constexpr int NA = SRC ? 5 : 4;
     const int nsp = pad_odd(m.ns);
-    const void *fn = mixed ? (const void *)k_wdot<true, PPW, SRC> : (const void *)k_wdot<false, PPW, SRC>;
+    const void *fn = mixed ? (const void *)k_wdot<true, PPW, SRC, STORE> : (const void *)k_wdot<false, PPW, SRC, STORE>;
     int WPB = 4;
     size_t shm = 0;
     const hipError_t e = lds_waves(fn, (size_t)PPW * NA * nsp * sizeof(double), WPB, shm);
@@ -1438,39 +1504,52 @@ hipError_t launch_wdot_t(const DevMech &m, int mixed, int64_t n, const double *T
     const int64_t groups = (n + PPW - 1) / PPW;
     const dim3 grid(grid_for(groups, WPB, 16)), block(WPB * WAVE);
     if (mixed)
-        hipLaunchKernelGGL((k_wdot<true, PPW, SRC>), grid, block, shm, st, m, n, T, p, ps, Y, ld, wdot, hrr, rmass,
-                           dTdt, QT, dp0dt, nsp);
+        hipLaunchKernelGGL((k_wdot<true, PPW, SRC, STORE>), grid, block, shm, st, m, n, T, p, ps, Y, ld, wdot, hrr,
+                           rmass, dTdt, QT, dp0dt, nsp, work);
     else
-        hipLaunchKernelGGL((k_wdot<false, PPW, SRC>), grid, block, shm, st, m, n, T, p, ps, Y, ld, wdot, hrr, rmass,
-                           dTdt, QT, dp0dt, nsp);
+        hipLaunchKernelGGL((k_wdot<false, PPW, SRC, STORE>), grid, block, shm, st, m, n, T, p, ps, Y, ld, wdot, hrr,
+                           rmass, dTdt, QT, dp0dt, nsp, work);
     return hipGetLastError();
 }
 
 hipError_t launch_wdot(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
-                       const double *Y, int64_t ld, double *wdot, double *hrr, double *rmass, hipStream_t st) {
-    return launch_wdot_t<false>(m, mixed, n, T, p, ps, Y, ld, wdot, hrr, rmass, nullptr, nullptr, 0.0, st);
+                       const double *Y, int64_t ld, double *wdot, double *hrr, double *rmass, double *work,
+                       hipStream_t st) {
+    if (work)
+        return launch_wdot_t<false, true>(m, mixed, n, T, p, ps, Y, ld, wdot, hrr, rmass, nullptr, nullptr, 0.0,
+                                          work, st);
+    return launch_wdot_t<false, false>(m, mixed, n, T, p, ps, Y, ld, wdot, hrr, rmass, nullptr, nullptr, 0.0,
+                                       nullptr, st);
 }
 
 hipError_t launch_source(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
                          const double *Y, int64_t ld, double dp0dt, double *dYdt, double *dTdt, double *QT,
                          double *hrr, hipStream_t st) {
-    return launch_wdot_t<true>(m, mixed, n, T, p, ps, Y, ld, dYdt, hrr, nullptr, dTdt, QT, dp0dt, st);
+    return launch_wdot_t<true, false>(m, mixed, n, T, p, ps, Y, ld, dYdt, hrr, nullptr, dTdt, QT, dp0dt, nullptr,
+                                      st);
 }
 
 hipError_t launch_vjp(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
                       const double *Y, int64_t ld, const double *u, const double *uh, double *gT, double *gY,
-                      hipStream_t st) {
+                      const double *work, hipStream_t st) {
     const int nsp = pad_odd(m.ns);
-    const void *fn = mixed ? (const void *)k_vjp<true> : (const void *)k_vjp<false>;
+    // the stored values already carry the forward pass's precision: one stored instance
+    const void *fn = work ? (const void *)k_vjp<false, true>
+                          : (mixed ? (const void *)k_vjp<true, false> : (const void *)k_vjp<false, false>);
     int WPB = 4;
     size_t shm = 0;
     const hipError_t e = lds_waves(fn, (size_t)7 * nsp * sizeof(double), WPB, shm);
     if (e != hipSuccess) return e;
     const dim3 grid(grid_for(n, WPB, 16)), block(WPB * WAVE);
-    if (mixed)
-        hipLaunchKernelGGL((k_vjp<true>), grid, block, shm, st, m, n, T, p, ps, Y, ld, u, uh, gT, gY, nsp);
+    if (work)
+        hipLaunchKernelGGL((k_vjp<false, true>), grid, block, shm, st, m, n, T, p, ps, Y, ld, u, uh, gT, gY, nsp,
+                           work);
+    else if (mixed)
+        hipLaunchKernelGGL((k_vjp<true, false>), grid, block, shm, st, m, n, T, p, ps, Y, ld, u, uh, gT, gY, nsp,
+                           work);
     else
-        hipLaunchKernelGGL((k_vjp<false>), grid, block, shm, st, m, n, T, p, ps, Y, ld, u, uh, gT, gY, nsp);
+        hipLaunchKernelGGL((k_vjp<false, false>), grid, block, shm, st, m, n, T, p, ps, Y, ld, u, uh, gT, gY, nsp,
+                           work);
     return hipGetLastError();
 }
 

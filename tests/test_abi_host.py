@@ -137,6 +137,28 @@ def test_compute_calls_validate_before_launch(L, c0_path):
                         null) == 1
     assert b"finite" in L.crf_last_error()
     assert L.crf_source(h, 0, 10, fake, fake, 1, fake, 10, ctypes.c_double(0.0), fake, null, null, null, null) == 5
+    # workspace: size query, then CRF_E_WORKSPACE for a missing, short or misaligned buffer
+    nr = L.crf_n_reactions(h)
+    assert L.crf_workspace_bytes(h, 0, 1, 10) == 10 * nr * 32
+    assert L.crf_workspace_bytes(h, 1, 1, 0) == 0
+    assert L.crf_workspace_bytes(h, 0, 2, 10) == 0 and b"unknown operation" in L.crf_last_error()
+    assert L.crf_workspace_bytes(h, 5, 1, 10) == 0 and b"precision" in L.crf_last_error()
+    big = ctypes.c_size_t(10 * nr * 32)
+    assert L.crf_wdot_fwd(h, 0, 10, fake, fake, 1, fake, 10, fake, null, null, null, big, null) == 7
+    assert L.crf_wdot_fwd(h, 0, 10, fake, fake, 1, fake, 10, fake, null, null, fake, ctypes.c_size_t(10 * nr * 32 - 1),
+                          null) == 7
+    assert b"needed" in L.crf_last_error()
+    assert L.crf_wdot_fwd(h, 0, 10, fake, fake, 1, fake, 10, fake, null, null, ctypes.c_void_p(0x1008), big,
+                          null) == 7
+    assert b"aligned" in L.crf_last_error()
+    assert L.crf_wdot_fwd(h, 0, 10, fake, fake, 1, fake, 10, fake, null, null, fake, big, null) == 5
+    assert L.crf_wdot_vjp(h, 0, 10, fake, fake, 1, fake, 10, fake, null, fake, fake, ctypes.c_void_p(0x1004), big,
+                          null) == 7
+    assert L.crf_wdot_vjp(h, 0, 10, fake, fake, 1, fake, 10, fake, null, fake, fake, fake, ctypes.c_size_t(5),
+                          null) == 7
+    assert L.crf_wdot_vjp(h, 0, 10, fake, fake, 1, fake, 10, fake, null, fake, fake, null, ctypes.c_size_t(0),
+                          null) == 5          # no workspace: the recompute path
+    assert L.crf_status_str(7) == b"CRF_E_WORKSPACE"
     # bad precision is checked after the state
     assert L.crf_wdot_jvp(None, 0, 10, fake, fake, 1, fake, 10, null, fake, null, fake, null, null) == 1
     s2, h2 = _load(L, c0_path)
