@@ -22,11 +22,12 @@ from .kinetics import rates_of_progress, production_rates
 from .transport import transport_properties
 from .jacobian import jacobian, vjp, jvp, complex_step_jacobian, complex_step_jvp, central_fd_jacobian
 from .source import chemistry_source
+from .reactor import rhs, source_jacobian, ros2_step
 from .equil import equilibrate
 
 __all__ = [
     "OracleMech", "read_mechanism", "mixture_state", "nasa7", "thermo_properties",
     "rates_of_progress", "production_rates", "transport_properties", "jacobian", "vjp", "jvp",
     "complex_step_jacobian", "complex_step_jvp", "central_fd_jacobian", "equilibrate",
-    "chemistry_source",
+    "chemistry_source", "rhs", "source_jacobian", "ros2_step",
 ]
