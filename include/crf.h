@@ -66,7 +66,7 @@ typedef enum {
 } crf_status;
 
 /* Operations that take a caller-allocated workspace (crf_workspace_bytes). */
-typedef enum { CRF_OP_VJP = 1 } crf_op;
+typedef enum { CRF_OP_VJP = 1, CRF_OP_REACTOR = 2 } crf_op;
 
 typedef enum { CRF_FP64 = 0, CRF_MIXED = 1 } crf_precision;
 
@@ -139,7 +139,9 @@ crf_status crf_transport(const crf_mech *m, crf_precision prec, int64_t n, const
 /* Bytes of workspace that operation `op` needs for n points (0 and CRF_E_ARG in
  * crf_last_error for invalid arguments).  CRF_OP_VJP: the rate intermediates that
  * crf_wdot_fwd stores and crf_wdot_vjp reuses, 32 bytes per reaction and point (k_f,
- * 1/K_c, dk_f/dT, dk_f/d[M], FP64 in both modes).  Whether to store them or to let the
+ * 1/K_c, dk_f/dT, dk_f/d[M], FP64 in both modes).  CRF_OP_REACTOR: the matrices and
+ * stage vectors of crf_reactor_step (about 8 (Ns+1)^2 + 36 (Ns+1) bytes per point, plus
+ * 4 (Ns+1)^2 with CRF_MIXED).  Whether to store them or to let the
  * VJP recompute them is the caller's choice against its memory budget; the Python
  * binding stores them while they fit in CRF_HBM_BUDGET bytes (unset: recompute). */
 size_t crf_workspace_bytes(const crf_mech *m, crf_precision prec, int op, int64_t n);
@@ -208,6 +210,27 @@ crf_status crf_source(const crf_mech *m, crf_precision prec, int64_t n, const do
 crf_status crf_wdot_jac(const crf_mech *m, crf_precision prec, int64_t n, const double *T,
                         const double *p, int64_t p_stride, const double *Y, int64_t ld,
                         void *J, double *wdot, crf_stream stream);
+
+/* ---------------------------------------------------------------- reactor step */
+
+/* Advances every point, an adiabatic homogeneous mixture at constant pressure (the
+ * thermochemistry subsystem of Section 2, Eq. (1a)-(1b), without transport terms; the
+ * homogeneous autoignition of Section 3.1), by dt seconds: nsub substeps of the
+ * two-stage L-stable Rosenbrock method ROS2 (Verwer, Spee, Blom and Hundsdorfer, 1999),
+ *   (I - g h A) k1 = f(x),  (I - g h A) k2 = f(x + h k1) - 2 k1,  x <- x + 3/2 h k1 + 1/2 h k2,
+ * with h = dt/nsub, g = 1 + 1/sqrt(2), x = (T, Y), f the source terms of crf_source
+ * (dp0/dt = 0) and A = df/dx from the dense Jacobian of crf_wdot_jac (evaluated once per
+ * substep), each point's linear systems solved by LU with partial pivoting.
+ * T[n] and Y[k*ld + i] are read and overwritten in place; p is held fixed.
+ * CRF_MIXED evaluates the rates and the Jacobian in the mixed mode (FP32 Jacobian
+ * entries); the matrices, factorisation and updates are FP64 in both modes.
+ * work: caller workspace of at least crf_workspace_bytes(m, prec, CRF_OP_REACTOR, n)
+ * bytes, 256-byte aligned (else CRF_E_WORKSPACE); its contents on return are undefined.
+ * dt > 0 finite and 1 <= nsub <= 1000000, else CRF_E_ARG.  No step-size control: a
+ * singular Newton matrix or a step beyond the method's accuracy propagates IEEE values. */
+crf_status crf_reactor_step(const crf_mech *m, crf_precision prec, int64_t n, double *T, const double *p,
+                            int64_t p_stride, double *Y, int64_t ld, double dt, int nsub, void *work,
+                            size_t work_bytes, crf_stream stream);
 
 #ifdef __cplusplus
 }

@@ -8,11 +8,12 @@ EXPORTED = (
     "crf_load_mech", "crf_free_mech", "crf_n_species", "crf_n_reactions", "crf_device", "crf_jac_plan",
     "crf_last_error", "crf_status_str", "crf_thermo", "crf_wdot", "crf_transport",
     "crf_wdot_vjp", "crf_wdot_jac", "crf_wdot_jvp", "crf_source", "crf_workspace_bytes", "crf_wdot_fwd",
+    "crf_reactor_step",
 )
 
 CRF_OK, CRF_E_ARG, CRF_E_PARSE, CRF_E_MECH, CRF_E_NOMEM, CRF_E_DEVICE, CRF_E_UNSUPPORTED, CRF_E_WORKSPACE = range(8)
 CRF_FP64, CRF_MIXED = 0, 1
-CRF_OP_VJP = 1
+CRF_OP_VJP, CRF_OP_REACTOR = 1, 2
 
 _lib = None
 
@@ -71,6 +72,8 @@ def lib():
     L.crf_workspace_bytes.restype = SZ
     L.crf_wdot_fwd.argtypes = [P, I, I64, D, D, I64, D, I64, D, D, D, D, SZ, P]
     L.crf_wdot_fwd.restype = I
+    L.crf_reactor_step.argtypes = [P, I, I64, D, D, I64, D, I64, ctypes.c_double, I, D, SZ, P]
+    L.crf_reactor_step.restype = I
     _lib = L
     return L
 

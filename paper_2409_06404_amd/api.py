@@ -15,7 +15,7 @@ import os
 import torch
 
 from . import _lib
-from ._lib import CRF_FP64, CRF_MIXED, CRF_OP_VJP, CrfError, check
+from ._lib import CRF_FP64, CRF_MIXED, CRF_OP_REACTOR, CRF_OP_VJP, CrfError, check
 
 _PREC = {"fp64": CRF_FP64, "mixed": CRF_MIXED}
 
@@ -260,6 +260,25 @@ def wdot_jac(m, T, p, Y, precision="fp64", with_wdot=True, out=None):
     return out, w
 
 
+def reactor_workspace(m, n, precision="fp64"):
+    """A device buffer of the size crf_reactor_step needs for n points."""
+    b = _lib.lib().crf_workspace_bytes(m.handle, _prec(precision), CRF_OP_REACTOR, int(n))
+    return torch.empty(max(b, 1), dtype=torch.uint8, device=torch.device("cuda", m.device))
+
+
+def reactor_step(m, T, p, Y, dt, nsub=1, precision="fp64", work=None):
+    """Advance (T [n], Y [n, Ns] species-major) in place by dt seconds of an adiabatic
+    constant-pressure reactor: nsub ROS2 substeps.  Returns (T, Y)."""
+    n, p, ps, ld, dev = _state(m, T, p, Y)
+    if work is None:
+        work = reactor_workspace(m, n, precision)
+    if work.dtype != torch.uint8 or work.device != dev or not work.is_contiguous():
+        raise ValueError("work must be a contiguous uint8 tensor on the mechanism's device")
+    check(_lib.lib().crf_reactor_step(m.handle, _prec(precision), n, _ptr(T), _ptr(p), ps, _ptr(Y), ld,
+                                      float(dt), int(nsub), _ptr(work), work.numel(), _stream(dev)))
+    return T, Y
+
+
 class WdotFn(torch.autograd.Function):
     """(wdot, hrr) = WdotFn.apply(T, Y, p, mech, precision); backward = crf_wdot_vjp.
 
@@ -297,4 +316,5 @@ class WdotFn(torch.autograd.Function):
 
 
 __all__ = ["Mechanism", "species_major", "thermo", "wdot", "transport", "wdot_vjp", "wdot_jvp", "wdot_jac",
-           "wdot_fwd", "workspace_bytes", "new_workspace", "hbm_budget", "source", "WdotFn", "CrfError"]
+           "wdot_fwd", "workspace_bytes", "new_workspace", "hbm_budget", "source", "reactor_step", "reactor_workspace",
+           "WdotFn", "CrfError"]

@@ -162,8 +162,10 @@ size_t crf_workspace_bytes(const crf_mech *m, crf_precision prec, int op, int64_
     if (!m) { fail(CRF_E_ARG, "crf_workspace_bytes: mechanism is NULL"); return 0; }
     if (check_prec(prec, "crf_workspace_bytes") != CRF_OK) return 0;
     if (n < 0 || n > ((int64_t)1 << 40)) { fail(CRF_E_ARG, "crf_workspace_bytes: n out of range"); return 0; }
-    if (op != CRF_OP_VJP) { fail(CRF_E_ARG, "crf_workspace_bytes: unknown operation"); return 0; }
-    return (size_t)n * (size_t)m->host.nr() * VJP_WORK_PER_RXN;
+    if (op == CRF_OP_VJP) return (size_t)n * (size_t)m->host.nr() * VJP_WORK_PER_RXN;
+    if (op == CRF_OP_REACTOR) return reactor_work_bytes(m->host.ns(), prec == CRF_MIXED, n);
+    fail(CRF_E_ARG, "crf_workspace_bytes: unknown operation");
+    return 0;
 }
 
 namespace {
@@ -239,6 +241,29 @@ crf_status crf_source(const crf_mech *m, crf_precision prec, int64_t n, const do
     return on_device(m, "crf_source", [&] {
         return launch_source(m->dev, prec == CRF_MIXED, n, T, p, ps, Y, ld, dp0dt, dYdt, dTdt, QT, hrr,
                              (hipStream_t)stream);
+    });
+}
+
+crf_status crf_reactor_step(const crf_mech *m, crf_precision prec, int64_t n, double *T, const double *p,
+                            int64_t ps, double *Y, int64_t ld, double dt, int nsub, void *work, size_t work_bytes,
+                            crf_stream stream) {
+    crf_status s = check_state(m, n, T, p, ps, Y, ld, "crf_reactor_step");
+    if (s == CRF_OK) s = check_prec(prec, "crf_reactor_step");
+    if (s != CRF_OK) return s;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CRF_E_ARG, "crf_reactor_step: dt must be positive and finite");
+    if (nsub < 1 || nsub > 1000000) return fail(CRF_E_ARG, "crf_reactor_step: nsub must be in [1, 1000000]");
+    if (n > 0) {
+        const size_t need = reactor_work_bytes(m->host.ns(), prec == CRF_MIXED, n);
+        if (!work) return fail(CRF_E_WORKSPACE, "crf_reactor_step: work is NULL");
+        if (((uintptr_t)work & 255) != 0) return fail(CRF_E_WORKSPACE, "crf_reactor_step: work must be 256-byte aligned");
+        if (work_bytes < need)
+            return fail(CRF_E_WORKSPACE, "crf_reactor_step: work_bytes " + std::to_string(work_bytes) + " < " +
+                                             std::to_string(need) + " needed");
+    }
+    if (check_device(m, "crf_reactor_step") != CRF_OK) return CRF_E_DEVICE;
+    if (n == 0) return CRF_OK;
+    return on_device(m, "crf_reactor_step", [&] {
+        return launch_reactor(m->dev, prec == CRF_MIXED, n, T, p, ps, Y, ld, dt, nsub, work, (hipStream_t)stream);
     });
 }
 

@@ -183,6 +183,9 @@ hipError_t launch_jvp(const DevMech &m, int mixed, int64_t n, const double *T, c
 hipError_t launch_source(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
                          int64_t ps, const double *Y, int64_t ld, double dp0dt, double *dYdt,
                          double *dTdt, double *QT, double *hrr, hipStream_t st);
+size_t reactor_work_bytes(int ns, int mixed, int64_t n);
+hipError_t launch_reactor(const DevMech &m, int mixed, int64_t n, double *T, const double *p, int64_t ps,
+                          double *Y, int64_t ld, double dt, int nsub, void *work, hipStream_t st);
 hipError_t launch_jac(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
                       int64_t ps, const double *Y, int64_t ld, void *J, double *wdot, hipStream_t st);
 

@@ -1445,6 +1445,215 @@ __global__ __launch_bounds__(256) void k_transport(DevMech m, int64_t n, const d
     }
 }
 
+// ------------------------------------------------------------------ reactor step (ROS2)
+// Constant-pressure adiabatic reactor, x = (T, Y), dx/dt = f(x) = (hrr/(rho c_p), W_k w_k/rho),
+// one two-stage Rosenbrock (ROS2) substep of size h:
+//   (I - gamma h A) k1 = f(x),  (I - gamma h A) k2 = f(x + h k1) - 2 k1,
+//   x <- x + 3/2 h k1 + 1/2 h k2,  gamma = 1 + 1/sqrt(2),
+// with A = df/dx formed from the Jacobian J of (hrr, w) by the chain rule through
+// rho(T, Y) and c_p(T, Y).  k_ros_lu: one workgroup per point forms M = I - gamma h A, factors
+// it (LU with partial pivoting, the row of largest magnitude, lowest index on ties),
+// solves for k1 and writes the stage state x + h k1; k_ros_finish solves for k2 with the
+// stored factors and updates x in place.  The matrix lives in LDS when it fits (a copy
+// of the factors goes to the workspace for k_ros_finish), else in the workspace itself.
+constexpr int ROS_THREADS = 256;
+constexpr double ROS_GAMMA = 1.7071067811865475244;
+
+// Sum over the workgroup (ROS_THREADS threads); `red` holds ROS_THREADS / WAVE doubles.
+__device__ inline double block_sum(double v, double *red) {
+    v = wave_sum(v);
+    const int wave = threadIdx.x / WAVE;
+    __syncthreads();
+    if ((threadIdx.x & (WAVE - 1)) == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < ROS_THREADS / WAVE; ++w) s += red[w];
+    return s;
+}
+
+// LU factorisation with partial pivoting of the N x N row-major matrix A (lda = N), in
+// place; piv[k] = the row swapped with row k at step k.  All ROS_THREADS threads take part.
+__device__ inline void lu_factor(double *A, int N, int *piv) {
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1);
+    for (int k = 0; k < N; ++k) {
+        if (tid < WAVE) {   // pivot search on wavefront 0: largest |A[r][k]|, lowest r on ties
+            double best = -1.0;
+            int br = k;
+            for (int r = k + lane; r < N; r += WAVE) {
+                const double a = fabs(A[(size_t)r * N + k]);
+                if (a > best) { best = a; br = r; }
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double ob = __shfl_xor(best, off);
+                const int orr = __shfl_xor(br, off);
+                if (ob > best || (ob == best && orr < br)) { best = ob; br = orr; }
+            }
+            if (lane == 0) piv[k] = br;
+        }
+        __syncthreads();
+        const int pr = piv[k];
+        if (pr != k)
+            for (int c = tid; c < N; c += ROS_THREADS) {
+                const double a = A[(size_t)k * N + c];
+                A[(size_t)k * N + c] = A[(size_t)pr * N + c];
+                A[(size_t)pr * N + c] = a;
+            }
+        __syncthreads();
+        const double inv = 1.0 / A[(size_t)k * N + k];
+        for (int r = k + 1 + tid; r < N; r += ROS_THREADS) A[(size_t)r * N + k] *= inv;
+        __syncthreads();
+        const int m = N - k - 1;
+        for (int e = tid; e < m * m; e += ROS_THREADS) {
+            const int r = k + 1 + e / m, c = k + 1 + e % m;
+            A[(size_t)r * N + c] = fma(-A[(size_t)r * N + k], A[(size_t)k * N + c], A[(size_t)r * N + c]);
+        }
+        __syncthreads();
+    }
+}
+
+// Solves (LU) x = P b in place in b (LDS, N values) with the factors of lu_factor.
+__device__ inline void lu_solve(const double *A, int N, const int *piv, double *b) {
+    const int tid = threadIdx.x;
+    if (tid == 0)
+        for (int k = 0; k < N; ++k) {
+            const int pr = piv[k];
+            if (pr != k) { const double t = b[k]; b[k] = b[pr]; b[pr] = t; }
+        }
+    __syncthreads();
+    for (int k = 0; k < N; ++k) {          // forward: unit lower triangle
+        const double bk = b[k];
+        for (int r = k + 1 + tid; r < N; r += ROS_THREADS) b[r] = fma(-A[(size_t)r * N + k], bk, b[r]);
+        __syncthreads();
+    }
+    for (int k = N - 1; k >= 0; --k) {     // backward: upper triangle
+        if (tid == 0) b[k] = b[k] / A[(size_t)k * N + k];
+        __syncthreads();
+        const double bk = b[k];
+        for (int r = tid; r < k; r += ROS_THREADS) b[r] = fma(-A[(size_t)r * N + k], bk, b[r]);
+        __syncthreads();
+    }
+}
+
+// LDS of k_ros_lu: per-point vectors {f, drho/rho, dcp/cp, row scale, w} x N1, N1 pivots,
+// ROS_THREADS/WAVE reduction slots, then the N1 x N1 matrix when it fits.
+template <bool JF32>
+__global__ __launch_bounds__(ROS_THREADS) void k_ros_lu(DevMech m, int64_t n, const double *__restrict__ T,
+                                                        const double *__restrict__ p, int64_t ps,
+                                                        const double *__restrict__ Y, int64_t ld,
+                                                        const void *__restrict__ Jv, const double *__restrict__ wd,
+                                                        double h, double *__restrict__ Mbuf, int *__restrict__ pivg,
+                                                        double *__restrict__ k1g, double *__restrict__ Ts,
+                                                        double *__restrict__ Ys, int mat_in_lds) {
+    extern __shared__ double lds[];
+    const int tid = threadIdx.x;
+    const int ns = m.ns, N = ns + 1;
+    double *F = lds, *DR = F + N, *DC = DR + N, *RS = DC + N, *WV = RS + N;
+    double *red = WV + N;
+    int *piv = (int *)(red + ROS_THREADS / WAVE);
+    double *AL = (double *)(piv + ((N + 1) & ~1));
+    using Jt = typename std::conditional<JF32, float, double>::type;
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const double t = T[i], pp = p[i * ps], invT = 1.0 / t;
+        // mixture: Wbar, rho, c_p, dc_p/dT, hrr = -R T sum_k (h_k/RT) w_k
+        double syw = 0.0, scp = 0.0, sdcp = 0.0, shw = 0.0;
+        for (int k = tid; k < ns; k += ROS_THREADS) {
+            const double *c16 = m.nasa + 16 * k;
+            const double *a = (t <= c16[0]) ? c16 + 1 : c16 + 8;
+            const double cpR = a[0] + t * (a[1] + t * (a[2] + t * (a[3] + t * a[4])));
+            const double dcpR = a[1] + t * (2.0 * a[2] + t * (3.0 * a[3] + t * 4.0 * a[4]));
+            const double hRT = a[0] + t * (a[1] * 0.5 + t * (a[2] * (1.0 / 3.0) + t * (a[3] * 0.25 + t * (a[4] * 0.2)))) +
+                               a[5] * invT;
+            const double yw = Y[(int64_t)k * ld + i] * m.invW[k];
+            const double w = wd[(int64_t)k * n + i];
+            syw += yw;
+            scp += yw * cpR;
+            sdcp += yw * dcpR;
+            shw += hRT * w;
+            WV[1 + k] = w;
+            DC[1 + k] = cpR * m.invW[k];                     // d c_p/dY_k / R
+        }
+        syw = block_sum(syw, red);
+        scp = block_sum(scp, red);
+        sdcp = block_sum(sdcp, red);
+        shw = block_sum(shw, red);
+        const double wbar = 1.0 / syw, rho = pp * wbar / (m.R * t);
+        const double cp = m.R * scp, hrr = -m.R * t * shw;
+        const double fT = hrr / (rho * cp);
+        for (int c = tid; c < N; c += ROS_THREADS) {
+            if (c == 0) {
+                F[0] = fT;
+                DR[0] = -invT;                               // (d rho/dT)/rho
+                DC[0] = sdcp / scp;                          // (d c_p/dT)/c_p
+                RS[0] = 1.0 / (rho * cp);
+                WV[0] = 0.0;
+            } else {
+                F[c] = m.W[c - 1] * WV[c] / rho;
+                DR[c] = -wbar * m.invW[c - 1];               // (d rho/dY_j)/rho
+                DC[c] = DC[c] / scp;                         // (d c_p/dY_j)/c_p
+                RS[c] = m.W[c - 1] / rho;
+            }
+        }
+        __syncthreads();
+        // M = I - gamma h A
+        double *A = mat_in_lds ? AL : Mbuf + (size_t)i * N * N;
+        const Jt *Jp = (const Jt *)Jv + (size_t)i * N * N;
+        const double gh = ROS_GAMMA * h;
+        for (int e = tid; e < N * N; e += ROS_THREADS) {
+            const int r = e / N, c = e - r * N;
+            const double j = (double)Jp[e];
+            const double a = r == 0 ? RS[0] * j - fT * (DR[c] + DC[c]) : RS[r] * (j - WV[r] * DR[c]);
+            A[e] = (r == c ? 1.0 : 0.0) - gh * a;
+        }
+        __syncthreads();
+        lu_factor(A, N, piv);
+        double *b = RS;                                      // reuse: right-hand side f
+        for (int c = tid; c < N; c += ROS_THREADS) b[c] = F[c];
+        __syncthreads();
+        lu_solve(A, N, piv, b);
+        for (int c = tid; c < N; c += ROS_THREADS) {
+            k1g[(size_t)i * N + c] = b[c];
+            pivg[(size_t)i * N + c] = piv[c];
+            if (c == 0) Ts[i] = t + h * b[0];
+            else Ys[(int64_t)(c - 1) * n + i] = Y[(int64_t)(c - 1) * ld + i] + h * b[c];
+        }
+        if (mat_in_lds)
+            for (int e = tid; e < N * N; e += ROS_THREADS) Mbuf[(size_t)i * N * N + e] = A[e];
+        __syncthreads();
+    }
+}
+
+// Second stage: k2 = (LU)^-1 (f(x_s) - 2 k1), x <- x + 3/2 h k1 + 1/2 h k2 (T, Y in place).
+__global__ __launch_bounds__(ROS_THREADS) void k_ros_finish(DevMech m, int64_t n, double *__restrict__ T,
+                                                            double *__restrict__ Y, int64_t ld,
+                                                            const double *__restrict__ Mbuf,
+                                                            const int *__restrict__ pivg,
+                                                            const double *__restrict__ k1g,
+                                                            const double *__restrict__ fTs,
+                                                            const double *__restrict__ fYs, double h) {
+    extern __shared__ double lds[];
+    const int tid = threadIdx.x;
+    const int ns = m.ns, N = ns + 1;
+    double *b = lds;
+    int *piv = (int *)(b + N);
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        for (int c = tid; c < N; c += ROS_THREADS) {
+            const double f = c == 0 ? fTs[i] : fYs[(int64_t)(c - 1) * n + i];
+            b[c] = f - 2.0 * k1g[(size_t)i * N + c];
+            piv[c] = pivg[(size_t)i * N + c];
+        }
+        __syncthreads();
+        lu_solve(Mbuf + (size_t)i * N * N, N, piv, b);
+        for (int c = tid; c < N; c += ROS_THREADS) {
+            const double dx = 1.5 * h * k1g[(size_t)i * N + c] + 0.5 * h * b[c];
+            if (c == 0) T[i] += dx;
+            else Y[(int64_t)(c - 1) * ld + i] += dx;
+        }
+        __syncthreads();
+    }
+}
+
 int device_cu_count() {
     static int cached[64] = {0};
     int dev = 0;
@@ -1637,6 +1846,96 @@ hipError_t launch_jac(const DevMech &m, int mixed, int64_t n, const double *T, c
         hipLaunchKernelGGL((k_jac<true>), grid, block, shm, st, m, n, T, p, ps, Y, ld, J, wdot, nsp, sr, rb);
     else
         hipLaunchKernelGGL((k_jac<false>), grid, block, shm, st, m, n, T, p, ps, Y, ld, J, wdot, nsp, sr, rb);
+    return hipGetLastError();
+}
+
+// Copies the state (T, Y with leading dimension lds) to (T, Y with leading dimension ldd).
+__global__ __launch_bounds__(256) void k_state_copy(int64_t n, int ns, const double *__restrict__ Ts,
+                                                    const double *__restrict__ Ysrc, int64_t lds_,
+                                                    double *__restrict__ Td, double *__restrict__ Yd, int64_t ldd) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * (ns + 1);
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / n, i = e - c * n;
+        if (c == 0) Td[i] = Ts[i];
+        else Yd[(c - 1) * ldd + i] = Ysrc[(c - 1) * lds_ + i];
+    }
+}
+
+namespace {
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+}  // namespace
+
+// Byte layout of the reactor workspace for n points (offsets of its regions; all
+// regions 256-byte aligned).  FP64: the Newton matrix overwrites the Jacobian in place.
+struct RosLayout {
+    size_t J, M, wd, piv, k1, Tw, Yw, Ts, Ys, fT, fY, total;
+};
+RosLayout ros_layout(int ns, int mixed, int64_t n) {
+    const size_t N = (size_t)ns + 1, nn = (size_t)n;
+    RosLayout L{};
+    size_t o = 0;
+    L.J = o; o = align256(o + nn * N * N * (mixed ? sizeof(float) : sizeof(double)));
+    if (mixed) { L.M = o; o = align256(o + nn * N * N * sizeof(double)); } else { L.M = L.J; }
+    L.wd = o; o = align256(o + nn * ns * sizeof(double));
+    L.piv = o; o = align256(o + nn * N * sizeof(int));
+    L.k1 = o; o = align256(o + nn * N * sizeof(double));
+    L.Tw = o; o = align256(o + nn * sizeof(double));
+    L.Yw = o; o = align256(o + nn * ns * sizeof(double));
+    L.Ts = o; o = align256(o + nn * sizeof(double));
+    L.Ys = o; o = align256(o + nn * ns * sizeof(double));
+    L.fT = o; o = align256(o + nn * sizeof(double));
+    L.fY = o; o = align256(o + nn * ns * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+size_t reactor_work_bytes(int ns, int mixed, int64_t n) { return n > 0 ? ros_layout(ns, mixed, n).total : 0; }
+
+hipError_t launch_reactor(const DevMech &m, int mixed, int64_t n, double *T, const double *p, int64_t ps, double *Y,
+                          int64_t ld, double dt, int nsub, void *work, hipStream_t st) {
+    const int ns = m.ns, N = ns + 1;
+    const RosLayout L = ros_layout(ns, mixed, n);
+    char *w = (char *)work;
+    void *Jb = w + L.J;
+    double *Mb = (double *)(w + L.M), *wd = (double *)(w + L.wd), *k1 = (double *)(w + L.k1);
+    int *piv = (int *)(w + L.piv);
+    double *Tw = (double *)(w + L.Tw), *Yw = (double *)(w + L.Yw), *Ts = (double *)(w + L.Ts);
+    double *Ys = (double *)(w + L.Ys), *fT = (double *)(w + L.fT), *fY = (double *)(w + L.fY);
+    const dim3 cgrid(grid_for(n * N, 256, 8)), cblock(256);
+    hipLaunchKernelGGL(k_state_copy, cgrid, cblock, 0, st, n, ns, T, Y, ld, Tw, Yw, (int64_t)n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t vec_lds = (size_t)(5 * N + ROS_THREADS / WAVE) * sizeof(double) + (size_t)((N + 1) & ~1) * sizeof(int);
+    const size_t mat_lds = (size_t)N * N * sizeof(double);
+    const int in_lds = vec_lds + mat_lds <= (size_t)64 * 1024;
+    const size_t shm = vec_lds + (in_lds ? mat_lds : 0);
+    const void *fn = mixed ? (const void *)k_ros_lu<true> : (const void *)k_ros_lu<false>;
+    if (shm > (size_t)CU_LDS_BYTES) return hipErrorInvalidValue;
+    if (shm > 64 * 1024) {
+        e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+    }
+    const dim3 grid(grid_for(n, 1, 8)), block(ROS_THREADS);
+    const size_t fshm = (size_t)N * sizeof(double) + (size_t)N * sizeof(int);
+    const double h = dt / nsub;
+    for (int s = 0; s < nsub; ++s) {
+        e = launch_jac(m, mixed, n, Tw, p, ps, Yw, n, Jb, wd, st);
+        if (e != hipSuccess) return e;
+        if (mixed)
+            hipLaunchKernelGGL((k_ros_lu<true>), grid, block, shm, st, m, n, Tw, p, ps, Yw, (int64_t)n, Jb, wd, h, Mb,
+                               piv, k1, Ts, Ys, in_lds);
+        else
+            hipLaunchKernelGGL((k_ros_lu<false>), grid, block, shm, st, m, n, Tw, p, ps, Yw, (int64_t)n, Jb, wd, h, Mb,
+                               piv, k1, Ts, Ys, in_lds);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = launch_source(m, mixed, n, Ts, p, ps, Ys, n, 0.0, fY, fT, nullptr, nullptr, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_ros_finish, grid, block, fshm, st, m, n, Tw, Yw, (int64_t)n, Mb, piv, k1, fT, fY, h);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_state_copy, cgrid, cblock, 0, st, n, ns, Tw, Yw, (int64_t)n, T, Y, ld);
     return hipGetLastError();
 }
 

@@ -416,6 +416,19 @@ def mechanism_text(m: Mechanism) -> str:
     return "\n".join(lines) + "\n"
 
 
+def with_rate_shift(m: Mechanism, dlnA: float) -> Mechanism:
+    """A copy of m with every pre-exponential factor (and every falloff k0's) multiplied by
+    e^dlnA: the same chemistry on a slower clock, for integrator tests at a moderate
+    stiffness."""
+    import copy
+    out = copy.deepcopy(m)
+    for r in out.reactions:
+        r.lnA = r.lnA + dlnA
+        if r.kind == "troe":
+            r.troe = (r.troe[0] + dlnA,) + tuple(r.troe[1:])
+    return out
+
+
 def write_mechanism(spec_or_mech, path) -> str:
     m = generate_mechanism(spec_or_mech) if isinstance(spec_or_mech, MechSpec) else spec_or_mech
     text = mechanism_text(m)

@@ -141,7 +141,20 @@ def test_compute_calls_validate_before_launch(L, c0_path):
     nr = L.crf_n_reactions(h)
     assert L.crf_workspace_bytes(h, 0, 1, 10) == 10 * nr * 32
     assert L.crf_workspace_bytes(h, 1, 1, 0) == 0
-    assert L.crf_workspace_bytes(h, 0, 2, 10) == 0 and b"unknown operation" in L.crf_last_error()
+    assert L.crf_workspace_bytes(h, 0, 3, 10) == 0 and b"unknown operation" in L.crf_last_error()
+    r64, r32 = L.crf_workspace_bytes(h, 0, 2, 10), L.crf_workspace_bytes(h, 1, 2, 10)
+    assert 10 * 8 * 10 * 10 < r64 < r32          # the mixed mode adds an FP64 copy of the matrices
+    assert L.crf_workspace_bytes(h, 0, 2, 0) == 0
+    # reactor step: dt and nsub validated, then the workspace, then the device
+    step = lambda dt, nsub, work, nb: L.crf_reactor_step(h, 0, 10, fake, fake, 1, fake, 10, ctypes.c_double(dt),
+                                                         nsub, work, ctypes.c_size_t(nb), null)
+    assert step(0.0, 1, fake, r64) == 1 and b"dt" in L.crf_last_error()
+    assert step(float("nan"), 1, fake, r64) == 1
+    assert step(1e-3, 0, fake, r64) == 1 and b"nsub" in L.crf_last_error()
+    assert step(1e-3, 1, null, r64) == 7
+    assert step(1e-3, 1, ctypes.c_void_p(0x1180), r64) == 7 and b"aligned" in L.crf_last_error()
+    assert step(1e-3, 1, fake, r64 - 1) == 7
+    assert step(1e-3, 1, fake, r64) == 5
     assert L.crf_workspace_bytes(h, 5, 1, 10) == 0 and b"precision" in L.crf_last_error()
     big = ctypes.c_size_t(10 * nr * 32)
     assert L.crf_wdot_fwd(h, 0, 10, fake, fake, 1, fake, 10, fake, null, null, null, big, null) == 7
