@@ -232,6 +232,20 @@ crf_status crf_reactor_step(const crf_mech *m, crf_precision prec, int64_t n, do
                             int64_t p_stride, double *Y, int64_t ld, double dt, int nsub, void *work,
                             size_t work_bytes, crf_stream stream);
 
+/* crf_reactor_step for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same computation,
+ * with the workspace taken from a static scratch array of 128 MiB that the library holds
+ * on each device it runs on until the process ends.  Allocates nothing (no hipMalloc or
+ * hipFree, no allocating library call).  n is limited to what fits the 128 MiB
+ * (crf_workspace_bytes(m, prec, CRF_OP_REACTOR, n) <= 134217728: about 5 000 points at 53
+ * species in FP64); larger n returns CRF_E_WORKSPACE.  Every call on a device shares that
+ * device's scratch (no part of it needs to start at zero; its last contents stay): calls
+ * that overlap in time on one device, on different streams or threads, race and give
+ * undefined results; serialise them. */
+crf_status crf_reactor_step_static(const crf_mech *m, crf_precision prec, int64_t n, double *T, const double *p,
+                                   int64_t p_stride, double *Y, int64_t ld, double dt, int nsub,
+                                   crf_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -267,6 +267,26 @@ crf_status crf_reactor_step(const crf_mech *m, crf_precision prec, int64_t n, do
     });
 }
 
+crf_status crf_reactor_step_static(const crf_mech *m, crf_precision prec, int64_t n, double *T, const double *p,
+                                   int64_t ps, double *Y, int64_t ld, double dt, int nsub, crf_stream stream) {
+    crf_status s = check_state(m, n, T, p, ps, Y, ld, "crf_reactor_step_static");
+    if (s == CRF_OK) s = check_prec(prec, "crf_reactor_step_static");
+    if (s != CRF_OK) return s;
+    if (!(dt > 0.0) || !std::isfinite(dt))
+        return fail(CRF_E_ARG, "crf_reactor_step_static: dt must be positive and finite");
+    if (nsub < 1 || nsub > 1000000) return fail(CRF_E_ARG, "crf_reactor_step_static: nsub must be in [1, 1000000]");
+    const size_t need = reactor_work_bytes(m->host.ns(), prec == CRF_MIXED, n);
+    if (need > STATIC_SCRATCH_BYTES)
+        return fail(CRF_E_WORKSPACE, "crf_reactor_step_static: " + std::to_string(n) + " points need " +
+                                         std::to_string(need) + " bytes of scratch, more than the static " +
+                                         std::to_string(STATIC_SCRATCH_BYTES) + "; use crf_reactor_step");
+    if (check_device(m, "crf_reactor_step_static") != CRF_OK) return CRF_E_DEVICE;
+    if (n == 0) return CRF_OK;
+    return on_device(m, "crf_reactor_step_static", [&] {
+        return launch_reactor_static(m->dev, prec == CRF_MIXED, n, T, p, ps, Y, ld, dt, nsub, (hipStream_t)stream);
+    });
+}
+
 crf_status crf_wdot_jac(const crf_mech *m, crf_precision prec, int64_t n, const double *T,
                         const double *p, int64_t ps, const double *Y, int64_t ld, void *J, double *wdot,
                         crf_stream stream) {

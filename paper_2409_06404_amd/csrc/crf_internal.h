@@ -30,6 +30,9 @@ constexpr int SLOTS = 6;
 constexpr int MAX_SPECIES = 2048;
 // Workspace of the stored-intermediate VJP: k_f, 1/K_c, dk_f/dT, dk_f/d[M] per reaction and point.
 constexpr size_t VJP_WORK_PER_RXN = 4 * sizeof(double);
+// Static device scratch of crf_reactor_step_static (per device, for the life of the process).
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)128 << 20;
+constexpr int MAX_DEVICES = 64;
 // LDS of one compute unit (gfx950), the most one workgroup may request.
 constexpr int CU_LDS_BYTES = 160 * 1024;
 
@@ -186,6 +189,8 @@ hipError_t launch_source(const DevMech &m, int mixed, int64_t n, const double *T
 size_t reactor_work_bytes(int ns, int mixed, int64_t n);
 hipError_t launch_reactor(const DevMech &m, int mixed, int64_t n, double *T, const double *p, int64_t ps,
                           double *Y, int64_t ld, double dt, int nsub, void *work, hipStream_t st);
+hipError_t launch_reactor_static(const DevMech &m, int mixed, int64_t n, double *T, const double *p, int64_t ps,
+                                 double *Y, int64_t ld, double dt, int nsub, hipStream_t st);
 hipError_t launch_jac(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
                       int64_t ps, const double *Y, int64_t ld, void *J, double *wdot, hipStream_t st);
 

@@ -24,6 +24,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <type_traits>
 
 #include "crf_internal.h"
@@ -1937,6 +1938,40 @@ hipError_t launch_reactor(const DevMech &m, int mixed, int64_t n, double *T, con
     }
     hipLaunchKernelGGL(k_state_copy, cgrid, cblock, 0, st, n, ns, Tw, Yw, (int64_t)n, T, Y, ld);
     return hipGetLastError();
+}
+
+// Scratch of the allocation-free reactor entry point (crf_reactor_step_static): one copy per
+// device, held for the life of the process.  Host code never uses the array's name as an
+// address (on the host it is a stand-in symbol): each device's address comes from
+// hipGetSymbolAddress, taken once per device with that device current, and is passed to
+// the kernels like a caller's workspace.
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+hipError_t static_scratch(void **out) {
+    static std::mutex mu;
+    static void *addr[MAX_DEVICES] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = ptr;
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_reactor_static(const DevMech &m, int mixed, int64_t n, double *T, const double *p, int64_t ps,
+                                 double *Y, int64_t ld, double dt, int nsub, hipStream_t st) {
+    if (reactor_work_bytes(m.ns, mixed, n) > STATIC_SCRATCH_BYTES) return hipErrorInvalidValue;
+    void *work = nullptr;
+    const hipError_t e = static_scratch(&work);
+    if (e != hipSuccess) return e;
+    return launch_reactor(m, mixed, n, T, p, ps, Y, ld, dt, nsub, work, st);
 }
 
 hipError_t launch_transport(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
