@@ -20,52 +20,9 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import rates
 from .kinetics import production_rates
 from .thermo import mixture_state, nasa7
-
-LN10 = np.log(10.0)
-
-
-def _dlnk_dT(b, theta, T):
-    return (b + theta / T) / T
-
-
-def _troe_parts(T, M, lnA, b, theta, troe):
-    """Returns (kf, dkf/dT at fixed M, dkf/dM at fixed T) for one falloff reaction."""
-    lnA0, b0, th0, alpha, T3, T1, T2 = troe
-    kinf = np.exp(lnA) * T ** b * np.exp(-theta / T)
-    k0 = np.exp(lnA0) * T ** b0 * np.exp(-th0 / T)
-    Pr = k0 * M / kinf
-    Fcent = (1.0 - alpha) * np.exp(-T / T3) + alpha * np.exp(-T / T1) + np.exp(-T2 / T)
-    dFcent = -(1.0 - alpha) / T3 * np.exp(-T / T3) - alpha / T1 * np.exp(-T / T1) \
-        + T2 / T ** 2 * np.exp(-T2 / T)
-    lFc = np.log10(Fcent)
-    c = -0.4 - 0.67 * lFc
-    n = 0.75 - 1.27 * lFc
-    d = 0.14
-    ell = np.log10(Pr)
-    u = ell + c
-    den = n - d * u
-    f1 = u / den
-    logF = lFc / (1.0 + f1 ** 2)
-    F = 10.0 ** logF
-    kf = kinf * Pr / (1.0 + Pr) * F
-    # partial derivatives of log10 F
-    df1_dell = n / den ** 2
-    df1_dlFc = (-0.67 * den - u * (-1.27 + 0.67 * d)) / den ** 2
-    dlogF_dell = -lFc * 2.0 * f1 * df1_dell / (1.0 + f1 ** 2) ** 2
-    dlogF_dlFc = 1.0 / (1.0 + f1 ** 2) - lFc * 2.0 * f1 * df1_dlFc / (1.0 + f1 ** 2) ** 2
-    # temperature at fixed [M]
-    dlnkinf = _dlnk_dT(b, theta, T)
-    dlnk0 = _dlnk_dT(b0, th0, T)
-    dlnPr = dlnk0 - dlnkinf
-    dlFc_dT = dFcent / (Fcent * LN10)
-    dlnF_dT = LN10 * (dlogF_dell * dlnPr / LN10 + dlogF_dlFc * dlFc_dT)
-    dkf_dT = kf * (dlnkinf + dlnPr / (1.0 + Pr) + dlnF_dT)
-    # [M] at fixed T:  d ln kf / d ln Pr = 1/(1+Pr) + dlog10F/dell ;  kf/M = k0 F / (1+Pr)
-    dkf_dM = k0 * F / (1.0 + Pr) * (1.0 / (1.0 + Pr) + dlogF_dell)
-    return kf, dkf_dT, dkf_dM
-
 
 def jacobian(m, T, p, Y, return_gross=False):
     """J [n, Ns+1, Ns+1]: rows (hrr, w_1..Ns), columns (T, Y_1..Ns).
@@ -92,49 +49,46 @@ def jacobian(m, T, p, Y, return_gross=False):
         GT = np.zeros((n, ns))
     for i in range(m.n_reactions):
         M = C @ m.eff[i]
-        if m.kind[i] == "troe":
-            kf, dkf_dT, dkf_dM = _troe_parts(T, M, m.lnA[i], m.b[i], m.theta[i], m.troe[i])
-        else:
-            kf = np.exp(m.lnA[i]) * T ** m.b[i] * np.exp(-m.theta[i] / T)
-            dkf_dT = kf * _dlnk_dT(m.b[i], m.theta[i], T)
-            dkf_dM = np.zeros_like(kf)
+        kf, dkf_dT, dkf_dM = rates.forward(m, i, T, p, M)
         lnKc = -(gRT * dnu[i][None, :]).sum(axis=1) + dnu[i].sum() * lnp0RT
         dlnKc_dT = ((hRT * dnu[i][None, :]).sum(axis=1) - dnu[i].sum()) / T
-        invKc = np.exp(-lnKc)
-        reac = np.nonzero(m.nu_f[i])[0]
+        kr, dkr_terms, dkr_dM = rates.reverse(m, i, T, kf, dkf_dT, dkf_dM, lnKc, dlnKc_dT)
+        dkr_dT = sum(dkr_terms) if dkr_terms else 0.0 * kf
+        orders = rates.forward_orders(m, i)
         prod = np.nonzero(m.nu_r[i])[0]
         pf = np.ones(n, dtype=dtype)
         pr = np.ones(n, dtype=dtype)
-        for k in reac:
-            pf = pf * C[:, k] ** int(m.nu_f[i, k])
+        for k, o in orders.items():
+            pf = pf * rates.power(C[:, k], o)
         for k in prod:
             pr = pr * C[:, k] ** int(m.nu_r[i, k])
-
-        def dprod(species, nu):
-            """d(prod_k C_k^nu_k)/dC_j for each j in `species` (no division by C)."""
-            out = {}
-            for j in species:
-                v = nu[j] * C[:, j] ** int(nu[j] - 1)
-                for k in species:
-                    if k != j:
-                        v = v * C[:, k] ** int(nu[k])
-                out[j] = v
-            return out
-
-        dpf = dprod(reac, m.nu_f[i])
-        dpr = dprod(prod, m.nu_r[i])
-        bracket = pf - invKc * pr                # q = fac * kf * bracket
+        # d(prod_k C_k^o_k)/dC_j for each j of the product (no division by C)
+        dpf = {}
+        for j, oj in orders.items():
+            v = rates.dpower(C[:, j], oj)
+            for k, o in orders.items():
+                if k != j:
+                    v = v * rates.power(C[:, k], o)
+            dpf[j] = v
+        dpr = {}
+        for j in prod:
+            v = m.nu_r[i, j] * C[:, j] ** int(m.nu_r[i, j] - 1)
+            for k in prod:
+                if k != j:
+                    v = v * C[:, k] ** int(m.nu_r[i, k])
+            dpr[j] = v
+        falloff = m.kind[i] in rates.FALLOFF
         fac = M if m.kind[i] == "threebody" else np.ones_like(M)
         dq_dC = np.zeros((n, ns), dtype=dtype)
         for j, v in dpf.items():
             dq_dC[:, j] += fac * kf * v
         for j, v in dpr.items():
-            dq_dC[:, j] -= fac * kf * invKc * v
-        if m.kind[i] == "threebody":
-            dq_dC += (kf * bracket)[:, None] * m.eff[i][None, :]
-        elif m.kind[i] == "troe":
-            dq_dC += (dkf_dM * bracket)[:, None] * m.eff[i][None, :]
-        dq_dT = fac * (dkf_dT * bracket + kf * invKc * pr * dlnKc_dT)
+            dq_dC[:, j] -= fac * kr * v
+        # [M] = sum_k eps_k C_k: the whole rate for three-body reactions, k_f (and k_r) for falloff
+        dq_dM = (kf * pf - kr * pr) if m.kind[i] == "threebody" else \
+            (dkf_dM * pf - dkr_dM * pr) if falloff else np.zeros_like(kf)
+        dq_dC += dq_dM[:, None] * m.eff[i][None, :]
+        dq_dT = fac * (dkf_dT * pf - dkr_dT * pr)
         JC += dnu[i][None, :, None] * dq_dC[:, None, :]
         JTC += dnu[i][None, :] * dq_dT[:, None]
         if return_gross:
@@ -142,14 +96,13 @@ def jacobian(m, T, p, Y, return_gross=False):
             for j, v in dpf.items():
                 a[:, j] += np.abs(fac * kf * v)
             for j, v in dpr.items():
-                a[:, j] += np.abs(fac * kf * invKc * v)
+                a[:, j] += np.abs(fac * kr * v)
             if m.kind[i] == "threebody":
-                a += np.abs(kf * bracket)[:, None] * m.eff[i][None, :]
-            elif m.kind[i] == "troe":
-                a += np.abs(dkf_dM * bracket)[:, None] * m.eff[i][None, :]
+                a += (np.abs(kf * pf) + np.abs(kr * pr))[:, None] * m.eff[i][None, :]
+            elif falloff:
+                a += (np.abs(dkf_dM * pf) + np.abs(dkr_dM * pr))[:, None] * m.eff[i][None, :]
             sig = (a * C).sum(axis=1)
-            tabs = np.abs(fac) * (np.abs(dkf_dT * pf) + np.abs(dkf_dT * invKc * pr)
-                                  + np.abs(kf * invKc * pr * dlnKc_dT))
+            tabs = np.abs(fac) * (np.abs(dkf_dT * pf) + sum(np.abs(t * pr) for t in dkr_terms))
             gy = rho[:, None] * a / m.W[None, :] + (Wbar[:, None] / m.W[None, :]) * sig[:, None]
             GY += np.abs(dnu[i])[None, :, None] * gy[:, None, :]
             GT += np.abs(dnu[i])[None, :] * (tabs + sig / T)[:, None]

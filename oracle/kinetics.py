@@ -29,43 +29,25 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import rates
 from .thermo import mixture_state, nasa7
-
-
-def _rlog10_guard(x):
-    """log10 with the argument floored at 1e-300 (real-part comparison)."""
-    return np.log10(np.where(x.real < 1e-300, 1e-300, x))
-
-
-def _arrhenius(lnA, b, theta, T):
-    return np.exp(lnA) * T ** b * np.exp(-theta / T)
-
-
-def troe_factor(T, Pr, alpha, T3, T1, T2):
-    """Troe broadening factor F (Gilbert-Luther-Troe 4-parameter form)."""
-    Fcent = (1.0 - alpha) * np.exp(-T / T3) + alpha * np.exp(-T / T1) + np.exp(-T2 / T)
-    lFc = _rlog10_guard(Fcent)
-    c = -0.4 - 0.67 * lFc
-    n = 0.75 - 1.27 * lFc
-    d = 0.14
-    u = _rlog10_guard(Pr) + c
-    f1 = u / (n - d * u)
-    return 10.0 ** (lFc / (1.0 + f1 ** 2))
 
 
 def rates_of_progress(m, T, p, Y):
     """Per-reaction quantities, each [n, Nr]:
 
-    kf  forward rate constant (falloff-blended for Troe reactions)
-    kr  reverse rate constant kf / Kc
+    kf  forward rate constant (falloff-blended, PLOG- or Chebyshev-evaluated)
+    kr  reverse rate constant: kf / Kc, the explicit reverse expression, or 0
     lnKc
-    M   third-body concentration sum_k eps_ik C_k (all reactions; used by threebody/troe)
-    qf, qr   forward / reverse rates including the [M] factor of three-body reactions
+    M   third-body concentration sum_k eps_ik C_k (all reactions; used by three-body/falloff)
+    qf, qr   forward / reverse rates including the [M] factor of three-body reactions,
+             with the forward orders of rates.forward_orders
     q   net rate qf - qr
     """
     T = np.asarray(T)
     Y = np.asarray(Y)
     n = T.shape[0]
+    p = np.broadcast_to(np.asarray(p), T.shape)
     Wbar, rho, X, C = mixture_state(m, T, p, Y)
     _, _, _, gRT = nasa7(m, T)
     nr = m.n_reactions
@@ -75,21 +57,14 @@ def rates_of_progress(m, T, p, Y):
     lnp0RT = np.log(m.p0 / (m.R * T))
     M_all = C @ m.eff.T                                      # [n, Nr]
     for i in range(nr):
-        kinf = _arrhenius(m.lnA[i], m.b[i], m.theta[i], T)
         M = M_all[:, i]
-        if m.kind[i] == "troe":
-            lnA0, b0, th0, alpha, T3, T1, T2 = m.troe[i]
-            k0 = _arrhenius(lnA0, b0, th0, T)
-            Pr = k0 * M / kinf
-            kf = kinf * (Pr / (1.0 + Pr)) * troe_factor(T, Pr, alpha, T3, T1, T2)
-        else:
-            kf = kinf
+        kf, dkf, dkM = rates.forward(m, i, T, p, M)
         lnKc = -(gRT * dnu[i][None, :]).sum(axis=1) + dnu[i].sum() * lnp0RT
-        kr = kf / np.exp(lnKc)
+        kr, _, _ = rates.reverse(m, i, T, kf, dkf, dkM, lnKc, 0.0 * T)
         pf = np.ones(n, dtype=dtype)
         pr = np.ones(n, dtype=dtype)
-        for k in np.nonzero(m.nu_f[i])[0]:
-            pf = pf * C[:, k] ** int(m.nu_f[i, k])
+        for k, o in rates.forward_orders(m, i).items():
+            pf = pf * rates.power(C[:, k], o)
         for k in np.nonzero(m.nu_r[i])[0]:
             pr = pr * C[:, k] ** int(m.nu_r[i, k])
         fac = M if m.kind[i] == "threebody" else 1.0

@@ -36,6 +36,15 @@ class OracleMech:
     mu_fit: np.ndarray       # [Ns, 4]
     lam_fit: np.ndarray      # [Ns, 4]
     dif_fit: np.ndarray      # [Ns, Ns, 4] symmetric, diagonal unused
+    # per reaction, the optional rate forms and modifiers (empty dict for a plain reaction):
+    #   "k0": (lnA0, b0, theta0)           low-pressure limit of a lindemann / sri falloff
+    #   "sri": (a, b, c, d, e)
+    #   "plog": [(p, lnA, b, theta), ...]  ascending p (Pa)
+    #   "cheb": (Tmin, Tmax, Pmin, Pmax, alpha [nT, nP])
+    #   "reverse": (lnA, b, theta)         explicit reverse Arrhenius
+    #   "irreversible": True
+    #   "orders": {species: order}         forward reaction orders (reactants)
+    extra: list = None
 
     @property
     def n_species(self):
@@ -96,6 +105,7 @@ def read_mechanism(path) -> OracleMech:
     nu_f = np.zeros((nr, ns)); nu_r = np.zeros((nr, ns))
     lnA = np.zeros(nr); b = np.zeros(nr); theta = np.zeros(nr)
     eff = np.ones((nr, ns)); troe = np.zeros((nr, 7))
+    extra = []
     for i in range(nr):
         t = next(it).split()
         assert t[0] == "reaction"
@@ -116,9 +126,47 @@ def read_mechanism(path) -> OracleMech:
         for k, v in _pairs(t[p + 2:], n, float).items():
             eff[i, k] = v
         p += 2 + n
+        ex = {}
         if t[1] == "troe":
             assert t[p] == "troe"
             troe[i] = [float(x) for x in t[p + 1:p + 8]]
+            p += 8
+        elif t[1] == "lindemann":
+            assert t[p] == "falloff"
+            ex["k0"] = tuple(float(x) for x in t[p + 1:p + 4])
+            p += 4
+        elif t[1] == "sri":
+            assert t[p] == "sri"
+            f = [float(x) for x in t[p + 1:p + 9]]
+            ex["k0"], ex["sri"] = tuple(f[:3]), tuple(f[3:])
+            p += 9
+        elif t[1] == "plog":
+            assert t[p] == "plog"
+            n = int(t[p + 1])
+            f = [float(x) for x in t[p + 2:p + 2 + 4 * n]]
+            ex["plog"] = [tuple(f[4 * j:4 * j + 4]) for j in range(n)]
+            p += 2 + 4 * n
+        elif t[1] == "chebyshev":
+            assert t[p] == "chebyshev"
+            Tmin, Tmax, Pmin, Pmax = (float(x) for x in t[p + 1:p + 5])
+            nT, nP = int(t[p + 5]), int(t[p + 6])
+            a = np.array([float(x) for x in t[p + 7:p + 7 + nT * nP]]).reshape(nT, nP)
+            ex["cheb"] = (Tmin, Tmax, Pmin, Pmax, a)
+            p += 7 + nT * nP
+        while p < len(t):
+            if t[p] == "reverse":
+                ex["reverse"] = tuple(float(x) for x in t[p + 1:p + 4])
+                p += 4
+            elif t[p] == "irreversible":
+                ex["irreversible"] = True
+                p += 1
+            elif t[p] == "orders":
+                n = int(t[p + 1])
+                ex["orders"] = _pairs(t[p + 2:], n, float)
+                p += 2 + n
+            else:
+                raise ValueError(f"reaction {i}: unknown token {t[p]}")
+        extra.append(ex)
     assert next(it) == "transport"
     mu = np.zeros((ns, 4)); lam = np.zeros((ns, 4)); dif = np.zeros((ns, ns, 4))
     for line in it:
@@ -135,4 +183,4 @@ def read_mechanism(path) -> OracleMech:
     W = comp @ aw
     return OracleMech(R, p0, elements, aw, names, comp, W, np.array(tl), np.array(tm), np.array(th),
                       np.array(alo), np.array(ahi), kind, nu_f, nu_r, lnA, b, theta, eff, troe,
-                      mu, lam, dif)
+                      mu, lam, dif, extra)

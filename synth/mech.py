@@ -77,6 +77,10 @@ class Reaction:
     theta: float
     efficiencies: dict = field(default_factory=dict)
     troe: tuple = ()               # (lnA0, b0, theta0, alpha, T3, T1, T2)
+    # optional rate forms and modifiers: "k0" (lindemann/sri low-pressure Arrhenius),
+    # "sri" (a, b, c, d, e), "plog" [(p, lnA, b, theta)], "cheb" (Tmin, Tmax, Pmin, Pmax,
+    # alpha [nT, nP]), "reverse" (lnA, b, theta), "irreversible" True, "orders" {k: o}
+    extra: dict = field(default_factory=dict)
 
 
 @dataclass
@@ -404,6 +408,24 @@ def mechanism_text(m: Mechanism) -> str:
         toks += [f"{k}:{f(e)}" for k, e in sorted(r.efficiencies.items())]
         if r.kind == "troe":
             toks += ["troe"] + [f(float(x)) for x in r.troe]
+        ex = r.extra
+        if r.kind == "lindemann":
+            toks += ["falloff"] + [f(float(x)) for x in ex["k0"]]
+        elif r.kind == "sri":
+            toks += ["sri"] + [f(float(x)) for x in tuple(ex["k0"]) + tuple(ex["sri"])]
+        elif r.kind == "plog":
+            toks += ["plog", str(len(ex["plog"]))] + [f(float(x)) for e in ex["plog"] for x in e]
+        elif r.kind == "chebyshev":
+            Tmin, Tmax, Pmin, Pmax, a = ex["cheb"]
+            a = np.asarray(a, dtype=float)
+            toks += ["chebyshev"] + [f(float(x)) for x in (Tmin, Tmax, Pmin, Pmax)]
+            toks += [str(a.shape[0]), str(a.shape[1])] + [f(float(x)) for x in a.ravel()]
+        if "reverse" in ex:
+            toks += ["reverse"] + [f(float(x)) for x in ex["reverse"]]
+        if ex.get("irreversible"):
+            toks += ["irreversible"]
+        if ex.get("orders"):
+            toks += ["orders", str(len(ex["orders"]))] + [f"{k}:{f(float(o))}" for k, o in sorted(ex["orders"].items())]
         lines.append(" ".join(toks))
     lines.append("transport")
     for k in range(len(m.names)):
@@ -414,6 +436,70 @@ def mechanism_text(m: Mechanism) -> str:
         lines.append(" ".join(["diffusion", str(j), str(k)] + [f(float(x)) for x in c]))
     lines.append("end")
     return "\n".join(lines) + "\n"
+
+
+# A mechanism that uses every optional rate form: the 53-species reaction set of MECH_C1's
+# generator at a smaller size, with reactions converted by their own seeded draws.
+MECH_V = MechSpec("v", ("C", "H", "O", "N"), 32, 6, 50, 6, 12, 11)
+
+
+def generate_variant_mechanism(spec: MechSpec = MECH_V) -> Mechanism:
+    """generate_mechanism(spec) with reactions converted to the optional forms:
+    of the 12 falloff reactions, 4 Lindemann and 5 SRI (the rest Troe); of the elementary
+    ones, 6 PLOG (3-4 pressures, 1e4-1e7 Pa, each Arrhenius perturbed from the reaction's),
+    5 Chebyshev (4 x 3 coefficients around the reaction's Arrhenius at 1 atm), 6 with an
+    explicit reverse expression, 6 irreversible of which 4 have non-integer orders."""
+    m = generate_mechanism(spec)
+    rng = np.random.default_rng(spec.seed + 1000)
+    fall = [i for i, r in enumerate(m.reactions) if r.kind == "troe"]
+    elem = [i for i, r in enumerate(m.reactions) if r.kind == "elementary"]
+    rng.shuffle(fall)
+    rng.shuffle(elem)
+    for i in fall[:4]:
+        r = m.reactions[i]
+        r.kind, r.extra = "lindemann", {"k0": tuple(r.troe[:3])}
+        r.troe = ()
+    for i in fall[4:9]:
+        r = m.reactions[i]
+        sri = (rng.uniform(0.5, 2.0), rng.uniform(0.0, 1500.0), rng.uniform(300.0, 3000.0),
+               rng.uniform(0.6, 1.4), rng.uniform(-0.3, 0.3))
+        r.kind, r.extra = "sri", {"k0": tuple(r.troe[:3]), "sri": sri}
+        r.troe = ()
+    k = 0
+    for i in elem[k:k + 6]:
+        r = m.reactions[i]
+        npres = int(rng.integers(3, 5))
+        ps = np.sort(np.exp(rng.uniform(np.log(1e4), np.log(1e7), npres)))
+        r.kind = "plog"
+        r.extra = {"plog": [(float(pp), r.lnA + rng.uniform(-1.5, 1.5), r.b + rng.uniform(-0.3, 0.3),
+                             max(0.0, r.theta + rng.uniform(-2000.0, 2000.0))) for pp in ps]}
+    k += 6
+    for i in elem[k:k + 5]:
+        r = m.reactions[i]
+        Tmin, Tmax, Pmin, Pmax = 290.0, 3000.0, 1e3, 1e8
+        # log10 k of the reaction's Arrhenius at four temperatures, as a cubic in Tr, plus
+        # pressure terms
+        Tr = np.cos(np.pi * (np.arange(4) + 0.5) / 4)
+        Ts = 2.0 / (Tr * (1.0 / Tmax - 1.0 / Tmin) + 1.0 / Tmin + 1.0 / Tmax)
+        lg = (r.lnA + r.b * np.log(Ts) - r.theta / Ts) / np.log(10.0)
+        a = np.zeros((4, 3))
+        a[:, 0] = np.polynomial.chebyshev.chebfit(Tr, lg, 3)
+        a[:, 1] = rng.uniform(-0.3, 0.3, 4) * np.array([1.0, 0.5, 0.2, 0.1])
+        a[:, 2] = rng.uniform(-0.1, 0.1, 4) * np.array([1.0, 0.5, 0.2, 0.1])
+        r.kind = "chebyshev"
+        r.extra = {"cheb": (Tmin, Tmax, Pmin, Pmax, a)}
+    k += 5
+    for i in elem[k:k + 6]:
+        r = m.reactions[i]
+        r.extra = {"reverse": (r.lnA - rng.uniform(0.0, 4.0), r.b + rng.uniform(-0.5, 0.5),
+                               r.theta + rng.uniform(5000.0, 20000.0))}
+    k += 6
+    for j, i in enumerate(elem[k:k + 6]):
+        r = m.reactions[i]
+        r.extra = {"irreversible": True}
+        if j < 4:
+            r.extra["orders"] = {s_: round(float(n_) * rng.uniform(0.5, 1.5), 2) for s_, n_ in r.reactants.items()}
+    return m
 
 
 def with_rate_shift(m: Mechanism, dlnA: float) -> Mechanism:
