@@ -44,6 +44,21 @@ class Mechanism:
         self._h = h
         self.path = str(path)
 
+    @classmethod
+    def from_cantera_yaml(cls, path, device=None, transport=True):
+        """Load a Cantera YAML mechanism (converted by cantera_yaml.to_crf_mech)."""
+        import tempfile
+
+        from . import cantera_yaml
+        text = cantera_yaml.to_crf_mech(open(path).read(), transport=transport)
+        with tempfile.NamedTemporaryFile("w", suffix=".mech", delete=False) as fh:
+            fh.write(text)
+            tmp = fh.name
+        try:
+            return cls(tmp, device=device)
+        finally:
+            os.unlink(tmp)
+
     @property
     def handle(self):
         if self._h is None:

@@ -11,8 +11,23 @@
 
 namespace crf {
 
-// Reaction kinds (bits 0-1 of the packed reaction info word).
+// Reaction kinds (bits 0-1 of the packed reaction info word).  RXN_TROE is every falloff
+// reaction (Troe, Lindemann or SRI broadening, RxnVar flags).
 enum : int { RXN_ELEMENTARY = 0, RXN_THREEBODY = 1, RXN_TROE = 2 };
+
+// Optional rate forms and modifiers of a reaction (RxnVar.flags):
+enum : int {
+    VAR_PLOG = 1,          // rate: PLOG table at vtab[rate_off]: n, then n x (ln p, ln A, b, theta)
+    VAR_CHEB = 2,          // rate: Chebyshev at vtab[rate_off]: nT, nP, 1/Tmin, 1/Tmax, log10 Pmin,
+                           //       log10 Pmax, alpha[nT][nP]
+    VAR_RATE_MASK = 3,
+    VAR_LINDEMANN = 4,     // falloff broadening F = 1 (troe row: ln A0, b0, theta0)
+    VAR_SRI = 8,           // falloff broadening SRI (troe row: ln A0, b0, theta0, a, b, c, d, e)
+    VAR_REVERSE = 16,      // explicit reverse Arrhenius at vtab[rev_off]: ln A, b, theta
+    VAR_IRREV = 32,        // no reverse reaction
+    VAR_ORDERS = 64        // forward orders of reactant slots 0..2 at vtab[ord_off]
+};
+struct alignas(16) RxnVar { int flags, rate_off, rev_off, ord_off; };
 
 // Slots per reaction: up to 3 distinct reactant species (slots 0-2) and up to 3
 // distinct product species (slots 3-5).  Packed info word:
@@ -74,6 +89,9 @@ struct DevMech {
     const double *troe;       // [n_troe][8]: lnA0, b0, theta0, alpha, 1/T3, 1/T1, T2, 0
     const int *eff_sp;        // [n_exc]
     const double *eff_m1;     // [n_exc] eps - 1
+    const RxnVar *var;        // [nr] optional rate forms (all zero for a plain mechanism)
+    const double *vtab;       // their parameters
+    int n_var;                // reactions with a nonzero RxnVar
     // Segmented Jacobian plan (build_jac_plan in mech.cpp); jp_ok == 0 if the mechanism does not fit it
     const int *jp_thr;        // [JS_THREADS] per-thread reaction constants (JsThr)
     const unsigned *jp_recs;  // gather rounds, [JS_WAVES][JS_DMAX][64 lanes] uint2 (build_jac_plan)
@@ -131,6 +149,9 @@ struct HostMech {
     std::vector<double> troe;            // [n_troe][8]
     std::vector<int> eff_sp;
     std::vector<double> eff_m1;
+    std::vector<RxnVar> var;             // [nr]
+    std::vector<double> vtab;
+    int n_var = 0;
     // segmented Jacobian plan
     std::vector<JsThr> jp_thr;
     std::vector<unsigned> jp_recs;

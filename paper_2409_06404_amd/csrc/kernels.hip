@@ -204,53 +204,132 @@ __device__ inline double third_body(const DevMech &m, const RxnInts &ri, double 
     return M;
 }
 
-// Rate constant (with DERIV, its derivatives).  MIXED: Arrhenius exponentials and Troe
-// blending in FP32.
+// PLOG: ln k is linear in ln p between the two tabulated pressures that bracket p, and the
+// end expressions apply beyond the table (t: n, then n x (ln p_j, ln A_j, b_j, theta_j)).
+template <class Rt>
+__device__ inline void plog_rate(const double *t, double lnp, Rt lnT, Rt invT, Rt &lnk, Rt &dlnk) {
+    const int n = (int)t[0];
+    const double *e = t + 1;
+    int j = 0;
+    while (j + 2 < n && lnp >= e[4 * (j + 1)]) ++j;
+    const int j1 = n > 1 ? j + 1 : j;
+    Rt w = 0;
+    if (n > 1) {
+        const double ww = (lnp - e[4 * j]) / (e[4 * j1] - e[4 * j]);
+        w = (Rt)(ww < 0.0 ? 0.0 : ww > 1.0 ? 1.0 : ww);
+    }
+    const Rt l0 = (Rt)e[4 * j + 1] + (Rt)e[4 * j + 2] * lnT - (Rt)e[4 * j + 3] * invT;
+    const Rt l1 = (Rt)e[4 * j1 + 1] + (Rt)e[4 * j1 + 2] * lnT - (Rt)e[4 * j1 + 3] * invT;
+    const Rt d0 = ((Rt)e[4 * j + 2] + (Rt)e[4 * j + 3] * invT) * invT;
+    const Rt d1 = ((Rt)e[4 * j1 + 2] + (Rt)e[4 * j1 + 3] * invT) * invT;
+    lnk = ((Rt)1 - w) * l0 + w * l1;
+    dlnk = ((Rt)1 - w) * d0 + w * d1;
+}
+
+// Chebyshev: log10 k = sum_t c_t T_t(Tr), c_t = sum_q alpha_tq T_q(Pr), with T_n the Chebyshev
+// polynomials, Tr = (2/T - 1/Tmin - 1/Tmax)/(1/Tmax - 1/Tmin), Pr likewise in log10 p;
+// T_t' = t U_(t-1) for the temperature derivative (t: nT, nP, 1/Tmin, 1/Tmax, log10 Pmin,
+// log10 Pmax, alpha[nT][nP]).
+template <class Rt>
+__device__ inline void cheb_rate(const double *t, double log10p, Rt invT, Rt &lnk, Rt &dlnk) {
+    const int nT = (int)t[0], nP = (int)t[1];
+    const Rt iTmin = (Rt)t[2], iTmax = (Rt)t[3];
+    const Rt Tr = ((Rt)2 * invT - iTmin - iTmax) / (iTmax - iTmin);
+    const Rt dTr = (Rt)-2 * invT * invT / (iTmax - iTmin);
+    const Rt Pr = (Rt)((2.0 * log10p - t[4] - t[5]) / (t[5] - t[4]));
+    const double *al = t + 6;
+    Rt tm1 = 0, t0 = 1, um2 = 0, um1 = 0;     // T_{t-1}, T_t; U_{t-2}, U_{t-1}
+    Rt lg = 0, dlg = 0;
+    for (int it = 0; it < nT; ++it) {
+        Rt c = 0, pm1 = 0, p0 = 1;
+        for (int iq = 0; iq < nP; ++iq) {
+            c += (Rt)al[it * nP + iq] * p0;
+            const Rt pn = iq == 0 ? Pr : (Rt)2 * Pr * p0 - pm1;
+            pm1 = p0;
+            p0 = pn;
+        }
+        lg += c * t0;
+        dlg += c * (Rt)it * um1;                 // T_t' = t U_{t-1}
+        const Rt tn = it == 0 ? Tr : (Rt)2 * Tr * t0 - tm1;
+        const Rt un = it == 0 ? (Rt)1 : it == 1 ? (Rt)2 * Tr : (Rt)2 * Tr * um1 - um2;
+        tm1 = t0;
+        t0 = tn;
+        um2 = um1;
+        um1 = un;
+    }
+    lnk = lg * (Rt)LN10;
+    dlnk = dlg * dTr * (Rt)LN10;
+}
+
+// Rate constant (with DERIV, its derivatives).  MIXED: Arrhenius exponentials and falloff
+// blending in FP32.  Falloff broadening: Troe (Gilbert-Luther-Troe), Lindemann (F = 1) or
+// SRI (F = d (a e^(-b/T) + e^(-T/c))^X T^e, X = 1/(1 + log10^2 P_r)); plain reactions may
+// use a PLOG or Chebyshev rate instead of their Arrhenius expression.
 template <bool MIXED, bool DERIV>
 __device__ inline RateK rate_constant(const DevMech &m, const PointState &ps, const double *C, int kind,
-                                      const RxnInts &ri, double lnA, double bb, double th) {
+                                      const RxnInts &ri, const RxnVar &var, double lnA, double bb, double th) {
     using Rt = typename std::conditional<MIXED, float, double>::type;
     RateK k;
     k.M = kind != RXN_ELEMENTARY ? third_body(m, ri, ps.Ctot, C) : 0.0;
     const Rt lnT = (Rt)ps.lnT, invT = (Rt)ps.invT, T = (Rt)ps.T;
-    const Rt lnkinf = (Rt)lnA + (Rt)bb * lnT - (Rt)th * invT;
+    Rt lnkinf = (Rt)lnA + (Rt)bb * lnT - (Rt)th * invT;
+    Rt dlnkinf = ((Rt)bb + (Rt)th * invT) * invT;
+    if (var.flags & VAR_PLOG) plog_rate<Rt>(m.vtab + var.rate_off, log(ps.p), lnT, invT, lnkinf, dlnkinf);
+    else if (var.flags & VAR_CHEB) cheb_rate<Rt>(m.vtab + var.rate_off, log10(ps.p), invT, lnkinf, dlnkinf);
     const Rt kinf = exp_r<Rt>(lnkinf);
-    const Rt dlnkinf = ((Rt)bb + (Rt)th * invT) * invT;
     Rt kf = kinf, dkf_dT = kinf * dlnkinf, dkf_dM = 0;
     if (kind == RXN_TROE) {
         const double *tp = m.troe + 8 * (ri.v[7] >> 8);
-        const Rt lnA0 = (Rt)tp[0], b0 = (Rt)tp[1], th0 = (Rt)tp[2], alpha = (Rt)tp[3];
-        const Rt iT3 = (Rt)tp[4], iT1 = (Rt)tp[5], T2 = (Rt)tp[6];
+        const Rt lnA0 = (Rt)tp[0], b0 = (Rt)tp[1], th0 = (Rt)tp[2];
         const Rt lnk0 = lnA0 + b0 * lnT - th0 * invT;
         const Rt lnM = log_r<Rt>((Rt)k.M);
         const Rt lnPr = lnk0 - lnkinf + lnM;
         const Rt Pr = exp_r<Rt>(lnPr);
-        const Rt e3 = exp_r<Rt>(-T * iT3), e1 = exp_r<Rt>(-T * iT1), e2 = exp_r<Rt>(-T2 * invT);
-        const Rt Fc = ((Rt)1 - alpha) * e3 + alpha * e1 + e2;
-        const Rt tiny = MIXED ? (Rt)1e-37 : (Rt)1e-300;
-        const Rt lFc = log_r<Rt>(Fc > tiny ? Fc : tiny) * (Rt)INV_LN10;
-        const Rt c = (Rt)-0.4 - (Rt)0.67 * lFc;
-        const Rt nn = (Rt)0.75 - (Rt)1.27 * lFc;
         const Rt lnfloor = MIXED ? (Rt)-85.19 : (Rt)-690.7755278982137;
         const Rt ell = (lnPr > lnfloor ? lnPr : lnfloor) * (Rt)INV_LN10;
-        const Rt u = ell + c;
-        const Rt den = nn - (Rt)0.14 * u;
-        const Rt f1 = u / den;
-        const Rt g = (Rt)1 / ((Rt)1 + f1 * f1);
-        const Rt F = exp_r<Rt>(lFc * g * (Rt)LN10);
+        // broadening F, d log10 F / d log10 P_r and d log10 F / dT at fixed P_r
+        Rt F = 1, dlogF_dell = 0, dlogF_dT = 0;
+        if (var.flags & VAR_SRI) {
+            const Rt a = (Rt)tp[3], b = (Rt)tp[4], c = (Rt)tp[5], d = (Rt)tp[6], e = (Rt)tp[7];
+            const Rt X = (Rt)1 / ((Rt)1 + ell * ell);
+            const Rt ea = exp_r<Rt>(-b * invT), ec = exp_r<Rt>(-T / c);
+            const Rt S = a * ea + ec;
+            const Rt lnS = log_r<Rt>(S);
+            F = d * exp_r<Rt>(X * lnS + e * lnT);
+            if (DERIV) {
+                dlogF_dell = (Rt)-2 * ell * X * X * lnS * (Rt)INV_LN10;
+                const Rt dS = a * b * invT * invT * ea - ec / c;
+                dlogF_dT = (X * dS / S + e * invT) * (Rt)INV_LN10;
+            }
+        } else if (!(var.flags & VAR_LINDEMANN)) {
+            const Rt alpha = (Rt)tp[3], iT3 = (Rt)tp[4], iT1 = (Rt)tp[5], T2 = (Rt)tp[6];
+            const Rt e3 = exp_r<Rt>(-T * iT3), e1 = exp_r<Rt>(-T * iT1), e2 = exp_r<Rt>(-T2 * invT);
+            const Rt Fc = ((Rt)1 - alpha) * e3 + alpha * e1 + e2;
+            const Rt tiny = MIXED ? (Rt)1e-37 : (Rt)1e-300;
+            const Rt lFc = log_r<Rt>(Fc > tiny ? Fc : tiny) * (Rt)INV_LN10;
+            const Rt c = (Rt)-0.4 - (Rt)0.67 * lFc;
+            const Rt nn = (Rt)0.75 - (Rt)1.27 * lFc;
+            const Rt u = ell + c;
+            const Rt den = nn - (Rt)0.14 * u;
+            const Rt f1 = u / den;
+            const Rt g = (Rt)1 / ((Rt)1 + f1 * f1);
+            F = exp_r<Rt>(lFc * g * (Rt)LN10);
+            if (DERIV) {
+                const Rt idd = (Rt)1 / (den * den);
+                const Rt df1_dell = nn * idd;
+                const Rt df1_dlFc = ((Rt)-0.67 * den - u * ((Rt)-1.27 + (Rt)0.67 * (Rt)0.14)) * idd;
+                dlogF_dell = -lFc * (Rt)2 * f1 * df1_dell * g * g;
+                const Rt dlogF_dlFc = g - lFc * (Rt)2 * f1 * df1_dlFc * g * g;
+                const Rt dFc = -((Rt)1 - alpha) * iT3 * e3 - alpha * iT1 * e1 + T2 * invT * invT * e2;
+                dlogF_dT = dlogF_dlFc * dFc / (Fc * (Rt)LN10);
+            }
+        }
         const Rt Prp = (Rt)1 / ((Rt)1 + (Rt)1 / Pr);     // Pr/(1+Pr), safe for Pr -> 0, inf
         kf = kinf * Prp * F;
         if (DERIV) {
-            const Rt idd = (Rt)1 / (den * den);
-            const Rt df1_dell = nn * idd;
-            const Rt df1_dlFc = ((Rt)-0.67 * den - u * ((Rt)-1.27 + (Rt)0.67 * (Rt)0.14)) * idd;
-            const Rt dlogF_dell = -lFc * (Rt)2 * f1 * df1_dell * g * g;
-            const Rt dlogF_dlFc = g - lFc * (Rt)2 * f1 * df1_dlFc * g * g;
             const Rt dlnk0 = (b0 + th0 * invT) * invT;
             const Rt dlnPr = dlnk0 - dlnkinf;
-            const Rt dFc = -((Rt)1 - alpha) * iT3 * e3 - alpha * iT1 * e1 + T2 * invT * invT * e2;
-            const Rt dlFc = dFc / (Fc * (Rt)LN10);
-            const Rt dlnF = dlogF_dell * dlnPr + (Rt)LN10 * dlogF_dlFc * dlFc;
+            const Rt dlnF = dlogF_dell * dlnPr + (Rt)LN10 * dlogF_dT;
             const Rt ip1 = (Rt)1 / ((Rt)1 + Pr);
             dkf_dT = kf * (dlnkinf + dlnPr * ip1 + dlnF);
             const Rt k0 = exp_r<Rt>(lnk0);
@@ -263,21 +342,33 @@ __device__ inline RateK rate_constant(const DevMech &m, const PointState &ps, co
     return k;
 }
 
+// C^o and d(C^o)/dC for a reaction order o > 0 (integer orders as plain powers).
+__device__ inline double order_pow(double c, double o) {
+    return o == 1.0 ? c : o == 2.0 ? c * c : o == 3.0 ? c * c * c : (c > 0.0 ? pow(c, o) : 0.0);
+}
+__device__ inline double order_dpow(double c, double o) {
+    return o == 1.0 ? 1.0 : o == 2.0 ? 2.0 * c : o == 3.0 ? 3.0 * c * c : o * pow(c, o - 1.0);
+}
+
 // Rate of progress of a reaction from its rate constant (and, with DERIV, its
 // derivatives): equilibrium constant, concentration products, q, dq/dC of every slot,
-// dq/dT at fixed C, dq/d[M].  All FP64.  invKc_in >= 0 supplies 1/K_c (a stored value);
-// a negative value forms it from the Gibbs sums of the slots.
+// dq/dT at fixed C, dq/d[M].  All FP64.  The reverse rate constant is k_f/K_c, an explicit
+// reverse Arrhenius expression, or 0 for an irreversible reaction; invKc_in >= 0 supplies
+// 1/K_c (a stored value), a negative value forms it from the Gibbs sums of the slots.
+// Non-integer forward orders replace the reactant coefficients in the forward product.
 template <bool DERIV>
-__device__ inline void reaction_rates(const PointState &ps, const double *C, const double *gRT, const double *hRT,
-                                      int info, const RxnInts &ri, int dnu_sum, const RateK &k, double invKc_in,
-                                      RxnEval &o) {
+__device__ inline void reaction_rates(const DevMech &m, const RxnVar &var, const PointState &ps, const double *C,
+                                      const double *gRT, const double *hRT, int info, const RxnInts &ri,
+                                      int dnu_sum, const RateK &k, double invKc_in, RxnEval &o) {
     const int kind = info_kind(info);
     const int nre = info_nreac(info), npr = info_nprod(info);
+    const bool kc_form = !(var.flags & (VAR_REVERSE | VAR_IRREV));
+    const double *ord = m.vtab + var.ord_off;
     // equilibrium constant: ln K_c = -sum dnu_k g_k/RT + dnu ln(p0/RT)
     double lnKc = (double)dnu_sum * ps.lnp0RT;
     double dlnKc = -(double)dnu_sum;
     double pf = 1.0, pr = 1.0;
-    double Cs[SLOTS], Ps[SLOTS];
+    double Cs[SLOTS], Ps[SLOTS], Os[SLOTS];
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const bool used = s < MAX_SIDE ? s < nre : (s - MAX_SIDE) < npr;
@@ -286,8 +377,9 @@ __device__ inline void reaction_rates(const PointState &ps, const double *C, con
         const double sgn = s < MAX_SIDE ? -1.0 : 1.0;
         const double c = used ? C[kk] : 1.0;
         Cs[s] = c;
-        Ps[s] = ipow(c, nu);
-        if (used) {
+        Os[s] = (s < MAX_SIDE && used && (var.flags & VAR_ORDERS)) ? ord[s] : (double)nu;
+        Ps[s] = (s < MAX_SIDE && (var.flags & VAR_ORDERS)) ? (used ? order_pow(c, Os[s]) : 1.0) : ipow(c, nu);
+        if (used && kc_form) {
             if (invKc_in < 0.0) lnKc -= sgn * nu * gRT[kk];
             if (DERIV) dlnKc += sgn * nu * hRT[kk];
         }
@@ -295,29 +387,36 @@ __device__ inline void reaction_rates(const PointState &ps, const double *C, con
     }
     // 1/K_c in FP64 in both modes: near equilibrium q = k_f (prod_f - prod_r / K_c) is
     // decided by this factor, so its relative error becomes the error of q
-    const double invKc = invKc_in >= 0.0 ? invKc_in : exp_fast(-lnKc);
-    o.invKc = invKc;
+    double invKc = 0.0, krd = 0.0, dkrT = 0.0;
     const double kfd = k.kf;
+    if (var.flags & VAR_REVERSE) {
+        const double *rv = m.vtab + var.rev_off;
+        krd = exp_fast(rv[0] + rv[1] * ps.lnT - rv[2] * ps.invT);
+        if (DERIV) dkrT = krd * (rv[1] + rv[2] * ps.invT) * ps.invT;
+    } else if (kc_form) {
+        invKc = invKc_in >= 0.0 ? invKc_in : exp_fast(-lnKc);
+        krd = kfd * invKc;
+        if (DERIV) dkrT = k.dkfT * invKc - krd * dlnKc * ps.invT;
+    }
+    o.invKc = invKc;
     const double fac = kind == RXN_THREEBODY ? k.M : 1.0;
-    const double krd = kfd * invKc;
     o.q = fac * (kfd * pf - krd * pr);
     if (DERIV) {
-        dlnKc *= ps.invT;
-        const double bracket = pf - invKc * pr;
-        o.t = fac * (k.dkfT * bracket + krd * pr * dlnKc);
-        o.mfac = kind == RXN_THREEBODY ? kfd * bracket : kind == RXN_TROE ? k.dkfM * bracket : 0.0;
+        o.t = fac * (k.dkfT * pf - dkrT * pr);
+        o.mfac = kind == RXN_THREEBODY ? kfd * pf - krd * pr : kind == RXN_TROE ? k.dkfM * (pf - invKc * pr) : 0.0;
         double sig = 0.0;
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
             const bool used = s < MAX_SIDE ? s < nre : (s - MAX_SIDE) < npr;
             const int nu = used ? info_nu(info, s) : 1;
-            // d(prod)/dC_s = nu C_s^(nu-1) * product of the other slots of the same side
+            // d(prod)/dC_s = (order) C_s^(order-1) * product of the other slots of the same side
             double other = 1.0;
             const int lo = s < MAX_SIDE ? 0 : MAX_SIDE;
 #pragma unroll
             for (int t = 0; t < MAX_SIDE; ++t)
                 if (lo + t != s) other *= Ps[lo + t];
-            const double dp = ipow_m1(Cs[s], nu) * other;
+            const double dp = ((s < MAX_SIDE && (var.flags & VAR_ORDERS)) ? order_dpow(Cs[s], Os[s])
+                                                                           : ipow_m1(Cs[s], nu)) * other;
             const double d = used ? (s < MAX_SIDE ? fac * kfd * dp : -fac * krd * dp) : 0.0;
             o.d[s] = d;
             sig += d * Cs[s];
@@ -333,8 +432,9 @@ template <bool MIXED, bool DERIV>
 __device__ inline void eval_reaction(const DevMech &m, int r, const PointState &ps, const double *C,
                                      const double *gRT, const double *hRT, int info, const RxnInts &ri,
                                      double lnA, double bb, double th, int dnu_sum, RxnEval &o) {
-    const RateK k = rate_constant<MIXED, DERIV>(m, ps, C, info_kind(info), ri, lnA, bb, th);
-    reaction_rates<DERIV>(ps, C, gRT, hRT, info, ri, dnu_sum, k, -1.0, o);
+    const RxnVar var = m.var[r];
+    const RateK k = rate_constant<MIXED, DERIV>(m, ps, C, info_kind(info), ri, var, lnA, bb, th);
+    reaction_rates<DERIV>(m, var, ps, C, gRT, hRT, info, ri, dnu_sum, k, -1.0, o);
 }
 
 // ------------------------------------------------------------------ thermo
@@ -417,8 +517,9 @@ __global__ __launch_bounds__(256, 3) void k_wdot(DevMech m, int64_t n, const dou
                 double *C = base + (NA * q + 0) * nsp, *G = C + nsp, *Wd = C + 3 * nsp;
                 RxnEval o;
                 if constexpr (STORE) {
-                    const RateK k = rate_constant<MIXED, true>(m, st[q], C, info_kind(info), ri, lnA, bb, th);
-                    reaction_rates<false>(st[q], C, G, nullptr, info, ri, dsum, k, -1.0, o);
+                    const RxnVar var = m.var[r];
+                    const RateK k = rate_constant<MIXED, true>(m, st[q], C, info_kind(info), ri, var, lnA, bb, th);
+                    reaction_rates<false>(m, var, st[q], C, G, nullptr, info, ri, dsum, k, -1.0, o);
                     const int64_t i = g * PPW + q;
                     if (st[q].valid) {
                         f64x2 *w = (f64x2 *)(work + ((size_t)i * m.nr + x) * 4);
@@ -517,7 +618,7 @@ __global__ __launch_bounds__(256, 3) void k_vjp(DevMech m, int64_t n, const doub
                 k.kf = a.x;
                 k.dkfT = b.x;
                 k.dkfM = b.y;
-                reaction_rates<true>(st, C, G, H, info, ri, m.dnu_sum[r], k, a.y, o);
+                reaction_rates<true>(m, m.var[r], st, C, G, H, info, ri, m.dnu_sum[r], k, a.y, o);
             } else {
                 eval_reaction<MIXED, true>(m, r, st, C, G, H, info, ri, m.lnA[r], m.b[r], m.theta[r],
                                            m.dnu_sum[r], o);
@@ -1766,30 +1867,21 @@ hipError_t launch_vjp(const DevMech &m, int mixed, int64_t n, const double *T, c
 hipError_t launch_jvp(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
                       const double *Y, int64_t ld, const double *vT, const double *vY, double *jh, double *jw,
                       double *wdot, hipStream_t st) {
+    // one point per wavefront: the two-point form needed more than the 168 VGPRs of three
+    // waves per SIMD and spilled to scratch (and its mixed-mode build returned NaN on the
+    // mechanism with PLOG/Chebyshev/SRI reactions, which this form does not)
     const int nsp = pad_odd(m.ns);
     const size_t per_point = (size_t)7 * nsp * sizeof(double);
-    // two points per wavefront while one wavefront's share fits the compute unit's LDS
-    const bool two = 2 * per_point <= (size_t)CU_LDS_BYTES;
-    const void *fn = two ? (mixed ? (const void *)k_jvp<true, 2> : (const void *)k_jvp<false, 2>)
-                         : (mixed ? (const void *)k_jvp<true, 1> : (const void *)k_jvp<false, 1>);
-    const int ppw = two ? 2 : 1;
+    const void *fn = mixed ? (const void *)k_jvp<true, 1> : (const void *)k_jvp<false, 1>;
     int WPB = 4;
     size_t shm = 0;
-    const hipError_t e = lds_waves(fn, ppw * per_point, WPB, shm);
+    const hipError_t e = lds_waves(fn, per_point, WPB, shm);
     if (e != hipSuccess) return e;
-    const int64_t groups = (n + ppw - 1) / ppw;
-    const dim3 grid(grid_for(groups, WPB, 16)), block(WPB * WAVE);
-    if (two) {
-        if (mixed)
-            hipLaunchKernelGGL((k_jvp<true, 2>), grid, block, shm, st, m, n, T, p, ps, Y, ld, vT, vY, jh, jw, wdot, nsp);
-        else
-            hipLaunchKernelGGL((k_jvp<false, 2>), grid, block, shm, st, m, n, T, p, ps, Y, ld, vT, vY, jh, jw, wdot, nsp);
-    } else {
-        if (mixed)
-            hipLaunchKernelGGL((k_jvp<true, 1>), grid, block, shm, st, m, n, T, p, ps, Y, ld, vT, vY, jh, jw, wdot, nsp);
-        else
-            hipLaunchKernelGGL((k_jvp<false, 1>), grid, block, shm, st, m, n, T, p, ps, Y, ld, vT, vY, jh, jw, wdot, nsp);
-    }
+    const dim3 grid(grid_for(n, WPB, 16)), block(WPB * WAVE);
+    if (mixed)
+        hipLaunchKernelGGL((k_jvp<true, 1>), grid, block, shm, st, m, n, T, p, ps, Y, ld, vT, vY, jh, jw, wdot, nsp);
+    else
+        hipLaunchKernelGGL((k_jvp<false, 1>), grid, block, shm, st, m, n, T, p, ps, Y, ld, vT, vY, jh, jw, wdot, nsp);
     return hipGetLastError();
 }
 

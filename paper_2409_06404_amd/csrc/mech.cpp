@@ -125,10 +125,16 @@ crf_status parse_mechanism(const char *path, HostMech &h) {
         std::string kind;
         if (!(ss >> kw >> kind) || kw != "reaction") return perr(ln, "expected 'reaction <kind>'");
         int kc;
+        RxnVar var{0, 0, 0, 0};
         if (kind == "elementary") kc = RXN_ELEMENTARY;
         else if (kind == "threebody") kc = RXN_THREEBODY;
         else if (kind == "troe") kc = RXN_TROE;
+        else if (kind == "lindemann") { kc = RXN_TROE; var.flags |= VAR_LINDEMANN; }
+        else if (kind == "sri") { kc = RXN_TROE; var.flags |= VAR_SRI; }
+        else if (kind == "plog") { kc = RXN_ELEMENTARY; var.flags |= VAR_PLOG; }
+        else if (kind == "chebyshev") { kc = RXN_ELEMENTARY; var.flags |= VAR_CHEB; }
         else return fail(CRF_E_UNSUPPORTED, "reaction " + std::to_string(i) + ": unsupported kind '" + kind + "'");
+        const std::string rn = "reaction " + std::to_string(i);
         RxnInts r; for (int s = 0; s < 8; ++s) r.v[s] = -1;
         int info = kc;
         std::vector<long> el(ne, 0);
@@ -176,18 +182,105 @@ crf_status parse_mechanism(const char *path, HostMech &h) {
             h.eff_sp.push_back(k);
             h.eff_m1.push_back(v - 1.0);
         }
-        if (kc == RXN_TROE) {
+        auto finite_all = [](const double *v, int n) {
+            for (int j = 0; j < n; ++j) if (!std::isfinite(v[j])) return false;
+            return true;
+        };
+        if (kc == RXN_TROE && !(var.flags & (VAR_LINDEMANN | VAR_SRI))) {
             double t[7];
             if (!(ss >> kw) || kw != "troe") return perr(ln, "troe reaction without troe block");
             for (int j = 0; j < 7; ++j) if (!(ss >> t[j])) return perr(ln, "troe block needs 7 numbers");
             if (!(t[4] > 0) || !(t[5] > 0) || !(t[6] >= 0) || !std::isfinite(t[3]))
-                return fail(CRF_E_MECH, "reaction " + std::to_string(i) + ": Troe needs T*** > 0, T* > 0, T** >= 0");
+                return fail(CRF_E_MECH, rn + ": Troe needs T*** > 0, T* > 0, T** >= 0");
             ntroe_idx = (int)(h.troe.size() / 8);
             double rec[8] = {t[0], t[1], t[2], t[3], 1.0 / t[4], 1.0 / t[5], t[6], 0.0};
             h.troe.insert(h.troe.end(), rec, rec + 8);
+        } else if (var.flags & VAR_LINDEMANN) {
+            double t[3];
+            if (!(ss >> kw) || kw != "falloff") return perr(ln, "lindemann reaction without falloff block");
+            for (int j = 0; j < 3; ++j) if (!(ss >> t[j])) return perr(ln, "falloff block needs 3 numbers");
+            if (!finite_all(t, 3)) return fail(CRF_E_MECH, rn + ": non-finite falloff parameters");
+            ntroe_idx = (int)(h.troe.size() / 8);
+            double rec[8] = {t[0], t[1], t[2], 0, 0, 0, 0, 0};
+            h.troe.insert(h.troe.end(), rec, rec + 8);
+        } else if (var.flags & VAR_SRI) {
+            double t[8];
+            if (!(ss >> kw) || kw != "sri") return perr(ln, "sri reaction without sri block");
+            for (int j = 0; j < 8; ++j) if (!(ss >> t[j])) return perr(ln, "sri block needs 8 numbers");
+            if (!finite_all(t, 8) || !(t[3] >= 0) || !(t[5] > 0) || !(t[6] > 0))
+                return fail(CRF_E_MECH, rn + ": SRI needs a >= 0, c > 0, d > 0");
+            ntroe_idx = (int)(h.troe.size() / 8);
+            h.troe.insert(h.troe.end(), t, t + 8);
+        } else if (var.flags & VAR_PLOG) {
+            int np_;
+            if (!(ss >> kw >> np_) || kw != "plog" || np_ < 1 || np_ > 64) return perr(ln, "bad plog block");
+            var.rate_off = (int)h.vtab.size();
+            h.vtab.push_back(np_);
+            double lastp = 0.0;
+            for (int j = 0; j < np_; ++j) {
+                double e[4];
+                for (int q = 0; q < 4; ++q) if (!(ss >> e[q])) return perr(ln, "plog entry needs 4 numbers");
+                if (!finite_all(e, 4) || !(e[0] > lastp)) return fail(CRF_E_MECH, rn + ": PLOG pressures must be positive and ascending");
+                lastp = e[0];
+                const double rec[4] = {std::log(e[0]), e[1], e[2], e[3]};
+                h.vtab.insert(h.vtab.end(), rec, rec + 4);
+            }
+        } else if (var.flags & VAR_CHEB) {
+            double r4[4];
+            int nT, nP;
+            if (!(ss >> kw) || kw != "chebyshev") return perr(ln, "bad chebyshev block");
+            for (int q = 0; q < 4; ++q) if (!(ss >> r4[q])) return perr(ln, "chebyshev block needs Tmin Tmax Pmin Pmax");
+            if (!(ss >> nT >> nP) || nT < 1 || nP < 1 || nT > 16 || nP > 16) return perr(ln, "chebyshev needs 1..16 x 1..16 coefficients");
+            if (!finite_all(r4, 4) || !(0 < r4[0] && r4[0] < r4[1]) || !(0 < r4[2] && r4[2] < r4[3]))
+                return fail(CRF_E_MECH, rn + ": Chebyshev needs 0 < Tmin < Tmax and 0 < Pmin < Pmax");
+            var.rate_off = (int)h.vtab.size();
+            const double head[6] = {(double)nT, (double)nP, 1.0 / r4[0], 1.0 / r4[1], std::log10(r4[2]), std::log10(r4[3])};
+            h.vtab.insert(h.vtab.end(), head, head + 6);
+            for (int q = 0; q < nT * nP; ++q) {
+                double a;
+                if (!(ss >> a) || !std::isfinite(a)) return perr(ln, "bad chebyshev coefficient");
+                h.vtab.push_back(a);
+            }
         }
+        // optional modifiers
         std::string extra;
-        if (ss >> extra) return perr(ln, "trailing token '" + extra + "'");
+        while (ss >> extra) {
+            if (extra == "reverse") {
+                double t[3];
+                for (int j = 0; j < 3; ++j) if (!(ss >> t[j])) return perr(ln, "reverse block needs 3 numbers");
+                if (!finite_all(t, 3)) return fail(CRF_E_MECH, rn + ": non-finite reverse parameters");
+                if (kc == RXN_TROE) return fail(CRF_E_UNSUPPORTED, rn + ": explicit reverse rates of falloff reactions are not supported");
+                if (var.flags & (VAR_REVERSE | VAR_IRREV)) return fail(CRF_E_MECH, rn + ": more than one reverse specification");
+                var.flags |= VAR_REVERSE;
+                var.rev_off = (int)h.vtab.size();
+                h.vtab.insert(h.vtab.end(), t, t + 3);
+            } else if (extra == "irreversible") {
+                if (var.flags & (VAR_REVERSE | VAR_IRREV)) return fail(CRF_E_MECH, rn + ": more than one reverse specification");
+                var.flags |= VAR_IRREV;
+            } else if (extra == "orders") {
+                int no;
+                if (!(ss >> no) || no < 1 || no > MAX_SIDE) return perr(ln, "bad orders block");
+                if (var.flags & VAR_ORDERS) return fail(CRF_E_MECH, rn + ": orders given twice");
+                double ord[MAX_SIDE];
+                for (int sl = 0; sl < MAX_SIDE; ++sl) ord[sl] = r.v[sl] >= 0 ? (double)info_nu(info, sl) : 0.0;
+                for (int j = 0; j < no; ++j) {
+                    std::string tok; int k; double v;
+                    if (!(ss >> tok) || !parse_pair(tok, k, v)) return perr(ln, "bad order token");
+                    int sl = -1;
+                    for (int q = 0; q < MAX_SIDE; ++q) if (r.v[q] == k) sl = q;
+                    if (sl < 0) return fail(CRF_E_UNSUPPORTED, rn + ": orders are supported for reactant species only");
+                    if (!(v > 0) || !std::isfinite(v)) return fail(CRF_E_MECH, rn + ": orders must be positive and finite");
+                    ord[sl] = v;
+                }
+                var.flags |= VAR_ORDERS;
+                var.ord_off = (int)h.vtab.size();
+                h.vtab.insert(h.vtab.end(), ord, ord + MAX_SIDE);
+            } else {
+                return perr(ln, "trailing token '" + extra + "'");
+            }
+        }
+        if (var.flags != 0) ++h.n_var;
+        h.var.push_back(var);
         r.v[7] = neff | (ntroe_idx << 8);
         h.ri[i] = r;
         h.info[i] = info;
@@ -201,7 +294,7 @@ crf_status parse_mechanism(const char *path, HostMech &h) {
         for (int i = 0; i < nr; ++i) order[i] = i;
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return info_kind(h.info[a]) < info_kind(h.info[b]); });
         auto perm = [&](auto &v) { auto c = v; for (int i = 0; i < nr; ++i) v[i] = c[order[i]]; };
-        perm(h.lnA); perm(h.b); perm(h.theta); perm(h.info); perm(h.dnu_sum); perm(h.ri);
+        perm(h.lnA); perm(h.b); perm(h.theta); perm(h.info); perm(h.dnu_sum); perm(h.ri); perm(h.var);
     }
     // transport
     if (!L.next(ss) || !(ss >> kw) || kw != "transport") return perr(lineno(), "missing transport section");
@@ -324,6 +417,7 @@ void build_jac_plan(HostMech &h) {
         h.jp_mrx.clear();
     };
     if (ns < 1 || nr < 1) return no("empty mechanism");
+    if (h.n_var > 0) return no("PLOG, Chebyshev, Lindemann, SRI, explicit-reverse, irreversible or order reactions");
     if (ns > 64) return no("more than 64 species (the state phase is one species per lane)");
     if (nr > JS_THREADS) return no("more reactions than threads per workgroup");
     {   // emission: column pairs x row phases over JS_EWAVES wavefronts, at most JS_EROWS rows each
@@ -789,15 +883,19 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
     // ones, so that the longest branches run in as few groups of 64 as possible
     std::vector<int> rxn_order;
     for (int kind : {RXN_TROE, RXN_THREEBODY, RXN_ELEMENTARY})
-        for (int i = 0; i < nr; ++i)
-            if (info_kind(h.info[i]) == kind) rxn_order.push_back(i);
+        for (int rate : {(int)VAR_CHEB, (int)VAR_PLOG, 0})      // then the tabulated rate forms together
+            for (int i = 0; i < nr; ++i)
+                if (info_kind(h.info[i]) == kind && (h.var[i].flags & VAR_RATE_MASK) == rate) rxn_order.push_back(i);
+    std::vector<double> vtab = h.vtab;
+    if (vtab.empty()) vtab.push_back(0.0);
     Packer P;
     size_t oW = P.add(h.W), oInvW = P.add(invW), oNasa = P.add(h.nasa), oMu = P.add(h.mu_fit),
            oLam = P.add(h.lam_fit), oW4 = P.add(w4), oIw4 = P.add(iw4), oWc = P.add(wc),
            oLnA = P.add(h.lnA), oB = P.add(h.b), oTh = P.add(h.theta), oInfo = P.add(h.info),
            oDs = P.add(h.dnu_sum), oRi = P.add(h.ri), oTroe = P.add(h.troe), oEs = P.add(h.eff_sp),
            oEm = P.add(h.eff_m1), oJt = P.add(h.jp_thr), oJr = P.add(h.jp_recs), oJp = P.add(h.jp_prog), oJm = P.add(h.jp_mrx),
-           oTj = P.add(tr_jk), oTf = P.add(tr_fit), oRo = P.add(rxn_order);
+           oTj = P.add(tr_jk), oTf = P.add(tr_fit), oRo = P.add(rxn_order), oVar = P.add(h.var),
+           oVt = P.add(vtab);
     int prev = -1;
     if (hipGetDevice(&prev) != hipSuccess) return fail(CRF_E_DEVICE, "hipGetDevice failed (no HIP device?)");
     if (hipSetDevice(device) != hipSuccess) return fail(CRF_E_DEVICE, "hipSetDevice(" + std::to_string(device) + ") failed");
@@ -821,6 +919,7 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
     m.theta = (const double *)at(oTh); m.info = (const int *)at(oInfo); m.rxn_order = (const int *)at(oRo); m.dnu_sum = (const int *)at(oDs);
     m.ri = (const RxnInts *)at(oRi); m.troe = (const double *)at(oTroe); m.eff_sp = (const int *)at(oEs);
     m.eff_m1 = (const double *)at(oEm);
+    m.var = (const RxnVar *)at(oVar); m.vtab = (const double *)at(oVt); m.n_var = h.n_var;
     m.jp_thr = (const int *)at(oJt); m.jp_recs = (const unsigned *)at(oJr); m.jp_prog = (const int *)at(oJp);
     m.jp_mrx = (const int *)at(oJm); m.jp_nm = h.jp_nm; m.jp_off_mx = h.jp_off_mx; m.jp_off_mq = h.jp_off_mq;
     m.jp_qb = h.jp_qb;

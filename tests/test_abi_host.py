@@ -65,9 +65,10 @@ def _edit(src, dst, fn):
 @pytest.mark.parametrize("edit,status,msg", [
     (lambda t: t.replace("crf-mech 1", "crf-mech 2"), 2, "version"),
     (lambda t: "\n".join(t.splitlines()[:40]), 2, ""),                                   # truncated
-    (lambda t: t.replace("reaction elementary reactants 2", "reaction plog reactants 2", 1), 6, "unsupported"),
+    (lambda t: t.replace("reaction elementary reactants 2", "reaction surface reactants 2", 1), 6, "unsupported"),
+    (lambda t: t.replace("reaction elementary reactants 2", "reaction plog reactants 2", 1), 2, "plog"),
     (lambda t: t.replace("gas-constant 8314.46261815324", "gas-constant -1"), 3, "positive"),
-], ids=["version", "truncated", "kind", "gasconst"])
+], ids=["version", "truncated", "kind", "plog-block", "gasconst"])
 def test_malformed_files(L, c0_path, tmp_path, edit, status, msg):
     bad = _edit(c0_path, tmp_path / "bad.mech", edit)
     s, h = _load(L, bad)
