@@ -41,7 +41,8 @@ def kernel_source_hash():
 
 def jac_kernel_name(plan, prec):
     """Name (as rocprofv3 shows it, shortened) of the kernel crf_wdot_jac launches."""
-    base = "k_jac_seg" if plan.startswith("segmented") else "k_jac"
+    base = ("k_jac_seg" if plan.startswith("segmented") else
+            "k_jac_rt" if plan.startswith("reaction-table") else "k_jac")
     return "%s<%s>" % (base, "false" if prec == "fp64" else "true")
 
 

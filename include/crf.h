@@ -93,9 +93,13 @@ int crf_device(const crf_mech *m);        /* device the tables live on, -1 for h
 
 /* Which kernel crf_wdot_jac runs for this mechanism: "segmented" (one workgroup per
  * point, one reaction per thread, lockstep gather of the derivative sums; needs at
- * most 384 reactions, 64 species, 3 molecules per side and 80 KB of LDS) or
- * "row-block (<reason>)" for the general kernel.  Informational; the string is owned
- * by the mechanism and valid until the next call on it or crf_free_mech. "" for NULL. */
+ * most 384 reactions, 64 species, 3 molecules per side, no optional rate forms and
+ * 80 KB of LDS), "reaction-table (<reason>)" (each reaction evaluated once per point
+ * into an LDS table, rows assembled from it in blocks; needs the table and 16 rows of
+ * accumulators in 160 KB of LDS, FP32 table entries in the mixed mode) or
+ * "row-block (<reason>)" (reactions re-evaluated per block of rows; any size).
+ * Informational; the string is owned by the mechanism and valid until crf_free_mech.
+ * "" for NULL. */
 const char *crf_jac_plan(const crf_mech *m);
 
 /* Message describing the last non-OK status returned on this thread ("" if none). */
@@ -205,8 +209,9 @@ crf_status crf_source(const crf_mech *m, crf_precision prec, int64_t n, const do
  * column 1 + j = Y_j.  J holds doubles for CRF_FP64 and floats for CRF_MIXED.
  * wdot (nullable) receives the production rates of the same evaluation, [k*ld + i]
  * (with CRF_MIXED and the segmented kernel, summed in FP32).  Results are bitwise
- * reproducible run to run with the segmented kernel; the row-block kernel sums a
- * point's rows over several wavefronts with LDS atomics, reproducible to rounding. */
+ * reproducible run to run with the segmented kernel; the reaction-table and row-block
+ * kernels sum a point's rows over several wavefronts with LDS atomics, reproducible to
+ * rounding. */
 crf_status crf_wdot_jac(const crf_mech *m, crf_precision prec, int64_t n, const double *T,
                         const double *p, int64_t p_stride, const double *Y, int64_t ld,
                         void *J, double *wdot, crf_stream stream);

@@ -74,7 +74,12 @@ crf_status crf_load_mech(const char *path, int device, crf_mech **out) {
     crf_status s = parse_mechanism(path, m->host);
     if (s == CRF_OK) {
         build_jac_plan(m->host);
-        m->plan_text = m->host.jp_ok ? std::string("segmented") : "row-block (" + m->host.jp_why + ")";
+        const HostMech &h = m->host;
+        if (h.jp_ok) m->plan_text = "segmented";
+        else if (jac_rt_fits(h.ns(), h.nr(), false)) m->plan_text = "reaction-table (" + h.jp_why + ")";
+        else if (jac_rt_fits(h.ns(), h.nr(), true))
+            m->plan_text = "reaction-table in the mixed mode, row-block in FP64 (" + h.jp_why + ")";
+        else m->plan_text = "row-block (" + h.jp_why + ")";
     }
     if (s == CRF_OK && device >= 0) s = upload_mechanism(m, device);
     if (s != CRF_OK) { delete m; return s; }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -187,7 +188,31 @@ crf_status parse_mechanism(const char *path, HostMech &out);
 void build_jac_plan(HostMech &h);
 crf_status upload_mechanism(crf_mech *m, int device);
 
-// Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.
+// LDS of the reaction-table Jacobian kernel (k_jac_rt): the species state {C, g/RT, h/RT,
+// cp/R} (nsp each), the row scalars {tau, jtc, R, w} (nsp + 1 each), every reaction's
+// enthalpy (nrp doubles) and 7 table values (d of six slots and d/d[M]; FP64, or FP32 in
+// the mixed mode), then rb Jacobian rows of FP64 accumulators with two per-row scalars
+// each.  The kernel takes the mechanism when 16 rows fit 160 KB and there are at most
+// 511 species (one emitting thread per column).
+struct JacRtLayout { size_t total; int rows; };
+inline bool jac_rt_fits(int ns, int nr, bool mixed, JacRtLayout *out = nullptr) {
+    const int nsp = ns | 1, n1 = ns + 1, sr = n1 | 1, nrp = (nr + 1) & ~1;
+    const size_t fixed = (size_t)(4 * nsp + 4 * (nsp + 1) + nrp) * sizeof(double) +
+                         (size_t)7 * nrp * (mixed ? sizeof(float) : sizeof(double)) + 16;
+    const size_t budget = CU_LDS_BYTES - 256, row_bytes = (size_t)(sr + 2) * sizeof(double);
+    if (n1 > 512 || fixed + (size_t)16 * row_bytes > budget) return false;
+    if (out) {
+        int rb = (int)((budget - fixed) / row_bytes);
+        if (rb >= n1) rb = n1;
+        const int nblk = (n1 + rb - 1) / rb;
+        rb = (n1 + nblk - 1) / nblk;
+        out->rows = rb;
+        out->total = fixed + (size_t)rb * row_bytes;
+    }
+    return true;
+}
+
+// Kernel launchers (kernels.hip).// Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_thermo(const DevMech &m, int64_t n, const double *T, const double *p, int64_t ps,
                          const double *Y, int64_t ld, double *cp_k, double *h_k, double *s_k,
                          double *g_k, double *cp_mass, double *h_mass, double *rho, double *Wbar,

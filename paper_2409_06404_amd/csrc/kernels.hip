@@ -265,17 +265,18 @@ __device__ inline void cheb_rate(const double *t, double log10p, Rt invT, Rt &ln
 // blending in FP32.  Falloff broadening: Troe (Gilbert-Luther-Troe), Lindemann (F = 1) or
 // SRI (F = d (a e^(-b/T) + e^(-T/c))^X T^e, X = 1/(1 + log10^2 P_r)); plain reactions may
 // use a PLOG or Chebyshev rate instead of their Arrhenius expression.
-template <bool MIXED, bool DERIV>
+template <bool MIXED, bool DERIV, bool VAR>
 __device__ inline RateK rate_constant(const DevMech &m, const PointState &ps, const double *C, int kind,
                                       const RxnInts &ri, const RxnVar &var, double lnA, double bb, double th) {
     using Rt = typename std::conditional<MIXED, float, double>::type;
+    const int vf = VAR ? var.flags : 0;      // optional rate forms compiled in only with VAR
     RateK k;
     k.M = kind != RXN_ELEMENTARY ? third_body(m, ri, ps.Ctot, C) : 0.0;
     const Rt lnT = (Rt)ps.lnT, invT = (Rt)ps.invT, T = (Rt)ps.T;
     Rt lnkinf = (Rt)lnA + (Rt)bb * lnT - (Rt)th * invT;
     Rt dlnkinf = ((Rt)bb + (Rt)th * invT) * invT;
-    if (var.flags & VAR_PLOG) plog_rate<Rt>(m.vtab + var.rate_off, log(ps.p), lnT, invT, lnkinf, dlnkinf);
-    else if (var.flags & VAR_CHEB) cheb_rate<Rt>(m.vtab + var.rate_off, log10(ps.p), invT, lnkinf, dlnkinf);
+    if (vf & VAR_PLOG) plog_rate<Rt>(m.vtab + var.rate_off, log(ps.p), lnT, invT, lnkinf, dlnkinf);
+    else if (vf & VAR_CHEB) cheb_rate<Rt>(m.vtab + var.rate_off, log10(ps.p), invT, lnkinf, dlnkinf);
     const Rt kinf = exp_r<Rt>(lnkinf);
     Rt kf = kinf, dkf_dT = kinf * dlnkinf, dkf_dM = 0;
     if (kind == RXN_TROE) {
@@ -289,7 +290,7 @@ __device__ inline RateK rate_constant(const DevMech &m, const PointState &ps, co
         const Rt ell = (lnPr > lnfloor ? lnPr : lnfloor) * (Rt)INV_LN10;
         // broadening F, d log10 F / d log10 P_r and d log10 F / dT at fixed P_r
         Rt F = 1, dlogF_dell = 0, dlogF_dT = 0;
-        if (var.flags & VAR_SRI) {
+        if (vf & VAR_SRI) {
             const Rt a = (Rt)tp[3], b = (Rt)tp[4], c = (Rt)tp[5], d = (Rt)tp[6], e = (Rt)tp[7];
             const Rt X = (Rt)1 / ((Rt)1 + ell * ell);
             const Rt ea = exp_r<Rt>(-b * invT), ec = exp_r<Rt>(-T / c);
@@ -301,7 +302,7 @@ __device__ inline RateK rate_constant(const DevMech &m, const PointState &ps, co
                 const Rt dS = a * b * invT * invT * ea - ec / c;
                 dlogF_dT = (X * dS / S + e * invT) * (Rt)INV_LN10;
             }
-        } else if (!(var.flags & VAR_LINDEMANN)) {
+        } else if (!(vf & VAR_LINDEMANN)) {
             const Rt alpha = (Rt)tp[3], iT3 = (Rt)tp[4], iT1 = (Rt)tp[5], T2 = (Rt)tp[6];
             const Rt e3 = exp_r<Rt>(-T * iT3), e1 = exp_r<Rt>(-T * iT1), e2 = exp_r<Rt>(-T2 * invT);
             const Rt Fc = ((Rt)1 - alpha) * e3 + alpha * e1 + e2;
@@ -356,13 +357,14 @@ __device__ inline double order_dpow(double c, double o) {
 // reverse Arrhenius expression, or 0 for an irreversible reaction; invKc_in >= 0 supplies
 // 1/K_c (a stored value), a negative value forms it from the Gibbs sums of the slots.
 // Non-integer forward orders replace the reactant coefficients in the forward product.
-template <bool DERIV>
+template <bool DERIV, bool VAR>
 __device__ inline void reaction_rates(const DevMech &m, const RxnVar &var, const PointState &ps, const double *C,
                                       const double *gRT, const double *hRT, int info, const RxnInts &ri,
                                       int dnu_sum, const RateK &k, double invKc_in, RxnEval &o) {
+    const int vf = VAR ? var.flags : 0;      // optional forms compiled in only with VAR
     const int kind = info_kind(info);
     const int nre = info_nreac(info), npr = info_nprod(info);
-    const bool kc_form = !(var.flags & (VAR_REVERSE | VAR_IRREV));
+    const bool kc_form = !(vf & (VAR_REVERSE | VAR_IRREV));
     const double *ord = m.vtab + var.ord_off;
     // equilibrium constant: ln K_c = -sum dnu_k g_k/RT + dnu ln(p0/RT)
     double lnKc = (double)dnu_sum * ps.lnp0RT;
@@ -377,8 +379,8 @@ __device__ inline void reaction_rates(const DevMech &m, const RxnVar &var, const
         const double sgn = s < MAX_SIDE ? -1.0 : 1.0;
         const double c = used ? C[kk] : 1.0;
         Cs[s] = c;
-        Os[s] = (s < MAX_SIDE && used && (var.flags & VAR_ORDERS)) ? ord[s] : (double)nu;
-        Ps[s] = (s < MAX_SIDE && (var.flags & VAR_ORDERS)) ? (used ? order_pow(c, Os[s]) : 1.0) : ipow(c, nu);
+        Os[s] = (s < MAX_SIDE && used && (vf & VAR_ORDERS)) ? ord[s] : (double)nu;
+        Ps[s] = (s < MAX_SIDE && (vf & VAR_ORDERS)) ? (used ? order_pow(c, Os[s]) : 1.0) : ipow(c, nu);
         if (used && kc_form) {
             if (invKc_in < 0.0) lnKc -= sgn * nu * gRT[kk];
             if (DERIV) dlnKc += sgn * nu * hRT[kk];
@@ -389,7 +391,7 @@ __device__ inline void reaction_rates(const DevMech &m, const RxnVar &var, const
     // decided by this factor, so its relative error becomes the error of q
     double invKc = 0.0, krd = 0.0, dkrT = 0.0;
     const double kfd = k.kf;
-    if (var.flags & VAR_REVERSE) {
+    if (vf & VAR_REVERSE) {
         const double *rv = m.vtab + var.rev_off;
         krd = exp_fast(rv[0] + rv[1] * ps.lnT - rv[2] * ps.invT);
         if (DERIV) dkrT = krd * (rv[1] + rv[2] * ps.invT) * ps.invT;
@@ -415,7 +417,7 @@ __device__ inline void reaction_rates(const DevMech &m, const RxnVar &var, const
 #pragma unroll
             for (int t = 0; t < MAX_SIDE; ++t)
                 if (lo + t != s) other *= Ps[lo + t];
-            const double dp = ((s < MAX_SIDE && (var.flags & VAR_ORDERS)) ? order_dpow(Cs[s], Os[s])
+            const double dp = ((s < MAX_SIDE && (vf & VAR_ORDERS)) ? order_dpow(Cs[s], Os[s])
                                                                            : ipow_m1(Cs[s], nu)) * other;
             const double d = used ? (s < MAX_SIDE ? fac * kfd * dp : -fac * krd * dp) : 0.0;
             o.d[s] = d;
@@ -428,13 +430,13 @@ __device__ inline void reaction_rates(const DevMech &m, const RxnVar &var, const
 
 // Rate of progress of reaction `r` (and, with DERIV, its derivatives).
 // MIXED: Arrhenius exponentials and Troe blending in FP32; everything else FP64.
-template <bool MIXED, bool DERIV>
+template <bool MIXED, bool DERIV, bool VAR>
 __device__ inline void eval_reaction(const DevMech &m, int r, const PointState &ps, const double *C,
                                      const double *gRT, const double *hRT, int info, const RxnInts &ri,
                                      double lnA, double bb, double th, int dnu_sum, RxnEval &o) {
-    const RxnVar var = m.var[r];
-    const RateK k = rate_constant<MIXED, DERIV>(m, ps, C, info_kind(info), ri, var, lnA, bb, th);
-    reaction_rates<DERIV>(m, var, ps, C, gRT, hRT, info, ri, dnu_sum, k, -1.0, o);
+    const RxnVar var = VAR ? m.var[r] : RxnVar{0, 0, 0, 0};
+    const RateK k = rate_constant<MIXED, DERIV, VAR>(m, ps, C, info_kind(info), ri, var, lnA, bb, th);
+    reaction_rates<DERIV, VAR>(m, var, ps, C, gRT, hRT, info, ri, dnu_sum, k, -1.0, o);
 }
 
 // ------------------------------------------------------------------ thermo
@@ -481,7 +483,7 @@ __global__ __launch_bounds__(256) void k_thermo(DevMech m, int64_t n, const doub
 // STORE: also writes every reaction's (k_f, 1/K_c, dk_f/dT, dk_f/d[M]) to
 // work[(i * nr + x) * 4 + 0..3] (x = the reaction's position in the processing order),
 // the transcendental part of the rates that the stored-intermediate VJP reuses.
-template <bool MIXED, int PPW, bool SRC, bool STORE>
+template <bool MIXED, int PPW, bool SRC, bool STORE, bool VAR>
 __global__ __launch_bounds__(256, 3) void k_wdot(DevMech m, int64_t n, const double *__restrict__ T,
                                               const double *__restrict__ p, int64_t ps,
                                               const double *__restrict__ Y, int64_t ld,
@@ -517,9 +519,9 @@ __global__ __launch_bounds__(256, 3) void k_wdot(DevMech m, int64_t n, const dou
                 double *C = base + (NA * q + 0) * nsp, *G = C + nsp, *Wd = C + 3 * nsp;
                 RxnEval o;
                 if constexpr (STORE) {
-                    const RxnVar var = m.var[r];
-                    const RateK k = rate_constant<MIXED, true>(m, st[q], C, info_kind(info), ri, var, lnA, bb, th);
-                    reaction_rates<false>(m, var, st[q], C, G, nullptr, info, ri, dsum, k, -1.0, o);
+                    const RxnVar var = VAR ? m.var[r] : RxnVar{0, 0, 0, 0};
+                    const RateK k = rate_constant<MIXED, true, VAR>(m, st[q], C, info_kind(info), ri, var, lnA, bb, th);
+                    reaction_rates<false, VAR>(m, var, st[q], C, G, nullptr, info, ri, dsum, k, -1.0, o);
                     const int64_t i = g * PPW + q;
                     if (st[q].valid) {
                         f64x2 *w = (f64x2 *)(work + ((size_t)i * m.nr + x) * 4);
@@ -527,7 +529,7 @@ __global__ __launch_bounds__(256, 3) void k_wdot(DevMech m, int64_t n, const dou
                         w[1] = f64x2{k.dkfT, k.dkfM};
                     }
                 } else {
-                    eval_reaction<MIXED, false>(m, r, st[q], C, G, nullptr, info, ri, lnA, bb, th, dsum, o);
+                    eval_reaction<MIXED, false, VAR>(m, r, st[q], C, G, nullptr, info, ri, lnA, bb, th, dsum, o);
                 }
 #pragma unroll
                 for (int s = 0; s < SLOTS; ++s) {
@@ -581,7 +583,7 @@ __global__ __launch_bounds__(256, 3) void k_wdot(DevMech m, int64_t n, const dou
 // STORED: the rate constants and their derivatives come from the forward pass's work
 // array (k_wdot with STORE) instead of being recomputed; the rest (concentration
 // products, equilibrium-constant derivative, chain rule) is formed here.
-template <bool MIXED, bool STORED>
+template <bool MIXED, bool STORED, bool VAR>
 __global__ __launch_bounds__(256, 3) void k_vjp(DevMech m, int64_t n, const double *__restrict__ T,
                                              const double *__restrict__ p, int64_t ps,
                                              const double *__restrict__ Y, int64_t ld,
@@ -618,10 +620,10 @@ __global__ __launch_bounds__(256, 3) void k_vjp(DevMech m, int64_t n, const doub
                 k.kf = a.x;
                 k.dkfT = b.x;
                 k.dkfM = b.y;
-                reaction_rates<true>(m, m.var[r], st, C, G, H, info, ri, m.dnu_sum[r], k, a.y, o);
+                reaction_rates<true, VAR>(m, VAR ? m.var[r] : RxnVar{0, 0, 0, 0}, st, C, G, H, info, ri, m.dnu_sum[r], k, a.y, o);
             } else {
-                eval_reaction<MIXED, true>(m, r, st, C, G, H, info, ri, m.lnA[r], m.b[r], m.theta[r],
-                                           m.dnu_sum[r], o);
+                eval_reaction<MIXED, true, VAR>(m, r, st, C, G, H, info, ri, m.lnA[r], m.b[r], m.theta[r],
+                                                m.dnu_sum[r], o);
             }
             const int nre = info_nreac(info), npr = info_nprod(info);
             // ubar = sum_k dnu_k (u_k - u_hrr h_k)   (the hrr row is -sum_k h_k w_k)
@@ -672,7 +674,7 @@ __global__ __launch_bounds__(256, 3) void k_vjp(DevMech m, int64_t n, const doub
 //   dq = (dq/dT)_C vT + sum_slots (dq/dC_s) dC_s + (dq/d[M]) d[M]
 // to dw_k = sum_i dnu_ki dq_i, and d hrr = -sum_k h_k dw_k - vT sum_k cp_k w_k.
 // LDS per wave: PPW points x {C, g/RT, h/RT, cp/R, dC, dw, w} x nsp doubles.
-template <bool MIXED, int PPW>
+template <bool MIXED, int PPW, bool VAR>
 __global__ __launch_bounds__(256, 3) void k_jvp(DevMech m, int64_t n, const double *__restrict__ T,
                                              const double *__restrict__ p, int64_t ps,
                                              const double *__restrict__ Y, int64_t ld,
@@ -726,7 +728,7 @@ __global__ __launch_bounds__(256, 3) void k_jvp(DevMech m, int64_t n, const doub
                 double *C = base + (NA * q + 0) * nsp, *G = C + nsp, *H = G + nsp, *DC = H + 2 * nsp,
                        *DW = DC + nsp, *Wd = DW + nsp;
                 RxnEval o;
-                eval_reaction<MIXED, true>(m, r, st[q], C, G, H, info, ri, lnA, bb, th, dsum, o);
+                eval_reaction<MIXED, true, VAR>(m, r, st[q], C, G, H, info, ri, lnA, bb, th, dsum, o);
                 double dq = o.t * vt[q];
                 if (o.mfac != 0.0) {
                     double dM = dct[q];
@@ -786,7 +788,7 @@ __global__ __launch_bounds__(256, 3) void k_jvp(DevMech m, int64_t n, const doub
 // stores J in FP32).  The wavefronts split the reactions of every pass; the rows of a
 // block accumulate through LDS atomics.
 constexpr int KJ_WAVES = 4;
-template <bool MIXED>
+template <bool MIXED, bool VAR>
 __global__ __launch_bounds__(KJ_WAVES * 64) void k_jac(DevMech m, int64_t n, const double *__restrict__ T,
                                                        const double *__restrict__ p, int64_t ps,
                                                        const double *__restrict__ Y, int64_t ld,
@@ -821,8 +823,8 @@ __global__ __launch_bounds__(KJ_WAVES * 64) void k_jac(DevMech m, int64_t n, con
                 const int info = m.info[r];
                 const RxnInts ri = m.ri[r];
                 RxnEval o;
-                eval_reaction<MIXED, true>(m, r, st, C, G, H, info, ri, m.lnA[r], m.b[r], m.theta[r],
-                                           m.dnu_sum[r], o);
+                eval_reaction<MIXED, true, VAR>(m, r, st, C, G, H, info, ri, m.lnA[r], m.b[r], m.theta[r],
+                                                m.dnu_sum[r], o);
                 const int nre = info_nreac(info), npr = info_nprod(info);
                 double dh = 0.0;   // reaction enthalpy sum_k dnu_k h_k
 #pragma unroll
@@ -919,6 +921,173 @@ __global__ __launch_bounds__(KJ_WAVES * 64) void k_jac(DevMech m, int64_t n, con
                 } else {
                     Jp[e0] = v[0];
                     if (e0 + 1 < e_hi) Jp[e0 + 1] = v[1];
+                }
+            }
+            __syncthreads();
+        }
+        if (wdot)
+            for (int k = tid; k < ns; k += NT) wdot[(int64_t)k * ld + i] = Wd[1 + k];
+    }
+}
+
+// ------------------------------------------------------------------ Jacobian (reaction table)
+// For mechanisms the segmented kernel does not take (more than 64 species or 384
+// reactions, optional rate forms): one workgroup of KR_WAVES wavefronts per point.  Each
+// reaction is evaluated once per point; its derivative data (dq/dC of its slots and
+// dq/d[M], FP64, or FP32 in the mixed mode) go to a table in LDS, its reaction enthalpy
+// sum_k dnu_k h_k beside them, and the row scalars (tau, J_T at fixed C, R, w) are summed
+// at once.  The Jacobian rows are then assembled in blocks of `rb` rows from the table
+// (as in k_jac, without re-evaluating the reactions), and emitted.  The row accumulators
+// are FP64 LDS atomics, so results are reproducible to rounding (not bitwise).
+// LDS: {C, g/RT, h/RT, cp/R} x nsp and {tau, jtc, R, w} x (nsp+1) doubles, the enthalpy of
+// every reaction (nrp doubles), the table (7 x nrp values), rb x sr FP64 accumulators and
+// two per-row scalars of the block.
+constexpr int KR_WAVES = 8;
+template <bool MIXED, bool VAR>
+__global__ __launch_bounds__(KR_WAVES * 64) void k_jac_rt(DevMech m, int64_t n, const double *__restrict__ T,
+                                                          const double *__restrict__ p, int64_t ps,
+                                                          const double *__restrict__ Y, int64_t ld,
+                                                          void *__restrict__ Jv, double *__restrict__ wdot, int nsp,
+                                                          int sr, int rb, int nrp) {
+    using Out = typename std::conditional<MIXED, float, double>::type;
+    using Vt = typename std::conditional<MIXED, float, double>::type;
+    extern __shared__ double lds[];
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    constexpr int NT = KR_WAVES * WAVE;
+    const int ns = m.ns, n1 = ns + 1, nr = m.nr;
+    double *C = lds, *G = C + nsp, *H = G + nsp, *CP = H + nsp;
+    double *TAU = CP + nsp, *JTC = TAU + (nsp + 1), *RC = JTC + (nsp + 1), *Wd = RC + (nsp + 1);
+    double *DH = Wd + (nsp + 1);
+    Vt *TB = (Vt *)(DH + nrp);                      // [7][nrp]: d[0..5], mfac
+    double *S = (double *)(TB + 7 * (size_t)nrp + (MIXED ? (7 * nrp) & 1 : 0));
+    Out *J = (Out *)Jv;
+    double *AL = S + (size_t)rb * sr, *JT = AL + rb;    // per-row scalars of the current block
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        __syncthreads();
+        const PointState st = load_point<true, true>(m, i, n, T, p, ps, Y, ld, C, G, H, CP, wave == 0);
+        for (int k = tid; k <= ns; k += NT) { TAU[k] = 0.0; JTC[k] = 0.0; RC[k] = 0.0; Wd[k] = 0.0; }
+        const double RT = m.R * st.T;
+        __syncthreads();
+        // every reaction once: table entries and the row scalars
+        for (int x = tid; x < nr; x += NT) {
+            const int r = m.rxn_order[x];
+            const int info = m.info[r];
+            const RxnInts ri = m.ri[r];
+            RxnEval o;
+            eval_reaction<MIXED, true, VAR>(m, r, st, C, G, H, info, ri, m.lnA[r], m.b[r], m.theta[r], m.dnu_sum[r], o);
+            const int nre = info_nreac(info), npr = info_nprod(info);
+            double dh = 0.0;
+#pragma unroll
+            for (int a = 0; a < SLOTS; ++a) {
+                const bool used = a < MAX_SIDE ? a < nre : (a - MAX_SIDE) < npr;
+                TB[a * nrp + x] = (Vt)(used ? o.d[a] : 0.0);
+                if (!used) continue;
+                const int k = ri.v[a];
+                const double dn = (a < MAX_SIDE ? -1.0 : 1.0) * info_nu(info, a);
+                dh += dn * RT * H[k];
+                atomicAdd(&Wd[1 + k], dn * o.q);
+                atomicAdd(&JTC[1 + k], dn * o.t);
+                atomicAdd(&RC[1 + k], dn * o.sigma);
+                if (o.mfac != 0.0) atomicAdd(&TAU[1 + k], dn * o.mfac);
+            }
+            TB[6 * nrp + x] = (Vt)o.mfac;
+            DH[x] = dh;
+        }
+        __syncthreads();
+        if (wave == 0) {
+            // row 0 scalars: tau_0, jtc_0, R_0 = -sum_k h_k (...)_k; sum cp_k w_k (in Wd[0])
+            double t0 = 0.0, j0 = 0.0, q0 = 0.0, cw = 0.0;
+            for (int k = lane; k < ns; k += WAVE) {
+                const double hk = RT * H[k];
+                t0 -= hk * TAU[1 + k];
+                j0 -= hk * JTC[1 + k];
+                q0 -= hk * RC[1 + k];
+                cw += m.R * CP[k] * Wd[1 + k];
+            }
+            t0 = wave_sum(t0); j0 = wave_sum(j0); q0 = wave_sum(q0); cw = wave_sum(cw);
+            if (lane == 0) { TAU[0] = t0; JTC[0] = j0; RC[0] = q0; Wd[0] = cw; }
+        }
+        Out *Jp = J + (size_t)i * n1 * n1;
+        for (int r0 = 0; r0 < n1; r0 += rb) {
+            const int r1 = r0 + rb < n1 ? r0 + rb : n1;
+            const bool first = r0 == 0;
+            for (int e = tid; e < (r1 - r0) * sr; e += NT) S[e] = 0.0;
+            __syncthreads();
+            for (int x = tid; x < nr; x += NT) {
+                const int r = m.rxn_order[x];
+                const int info = m.info[r];
+                const RxnInts ri = m.ri[r];
+                const int nre = info_nreac(info), npr = info_nprod(info);
+                double d[SLOTS];
+#pragma unroll
+                for (int b = 0; b < SLOTS; ++b) d[b] = (double)TB[b * nrp + x];
+                const double mf = (double)TB[6 * nrp + x], dh = DH[x];
+                bool any = first;
+#pragma unroll
+                for (int a = 0; a < SLOTS; ++a) {
+                    const bool used = a < MAX_SIDE ? a < nre : (a - MAX_SIDE) < npr;
+                    const int row = used ? 1 + ri.v[a] : -1;
+                    any |= row >= r0 && row < r1;
+                }
+                if (!any) continue;
+#pragma unroll
+                for (int a = 0; a < SLOTS; ++a) {
+                    const bool used = a < MAX_SIDE ? a < nre : (a - MAX_SIDE) < npr;
+                    if (!used) continue;
+                    const int row = 1 + ri.v[a];
+                    if (row < r0 || row >= r1) continue;
+                    const double dn = (a < MAX_SIDE ? -1.0 : 1.0) * info_nu(info, a);
+                    double *Srow = S + (size_t)(row - r0) * sr;
+#pragma unroll
+                    for (int b = 0; b < SLOTS; ++b) {
+                        const bool ub = b < MAX_SIDE ? b < nre : (b - MAX_SIDE) < npr;
+                        if (ub) atomicAdd(&Srow[ri.v[b]], dn * d[b]);
+                    }
+                }
+                if (first) {   // hrr row: -dh times the reaction's derivatives
+#pragma unroll
+                    for (int b = 0; b < SLOTS; ++b) {
+                        const bool ub = b < MAX_SIDE ? b < nre : (b - MAX_SIDE) < npr;
+                        if (ub) atomicAdd(&S[ri.v[b]], -dh * d[b]);
+                    }
+                }
+                if (mf != 0.0) {
+                    const int n_exc = ri.v[7] & 255;
+                    for (int e = 0; e < n_exc; ++e) {
+                        const int ke = m.eff_sp[ri.v[6] + e];
+                        const double me = mf * m.eff_m1[ri.v[6] + e];
+                        if (first) atomicAdd(&S[ke], -dh * me);
+                        for (int a = 0; a < SLOTS; ++a) {
+                            const bool used = a < MAX_SIDE ? a < nre : (a - MAX_SIDE) < npr;
+                            const int row = used ? 1 + ri.v[a] : -1;
+                            if (row < r0 || row >= r1) continue;
+                            const double dn = (a < MAX_SIDE ? -1.0 : 1.0) * info_nu(info, a);
+                            atomicAdd(&S[(size_t)(row - r0) * sr + ke], dn * me);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            // emission of rows r0..r1-1: thread = (row phase, column), rows strided by the phase
+            // count; per-row scalars formed once: AL[row] = rho tau - Wbar R, JT[row] = J_T of the row
+            for (int row = r0 + tid; row < r1; row += NT) {
+                const double Rr = RC[row];
+                AL[row - r0] = st.rho * TAU[row] - st.Wbar * Rr;
+                JT[row - r0] = JTC[row] - Rr * st.invT - (row == 0 ? Wd[0] : 0.0);
+            }
+            __syncthreads();
+            {
+                const int nph = NT / n1;                 // row phases (n1 <= NT)
+                const int ph = tid / n1, c = tid - ph * n1;
+                if (ph < nph) {
+                    const double iw = c > 0 ? m.invW[c - 1] : 0.0;
+                    const double rho = st.rho;
+                    for (int row = r0 + ph; row < r1; row += nph) {
+                        const double v = c == 0 ? JT[row - r0]
+                                                : (rho * S[(size_t)(row - r0) * sr + c - 1] + AL[row - r0]) * iw;
+                        Jp[(size_t)row * n1 + c] = (Out)v;
+                    }
                 }
             }
             __syncthreads();
@@ -1800,14 +1969,14 @@ hipError_t launch_thermo(const DevMech &m, int64_t n, const double *T, const dou
     return hipGetLastError();
 }
 
-template <bool SRC, bool STORE>
-hipError_t launch_wdot_t(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
-                         const double *Y, int64_t ld, double *wdot, double *hrr, double *rmass, double *dTdt,
-                         double *QT, double dp0dt, double *work, hipStream_t st) {
+template <bool SRC, bool STORE, bool VAR>
+hipError_t launch_wdot_tv(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
+                          const double *Y, int64_t ld, double *wdot, double *hrr, double *rmass, double *dTdt,
+                          double *QT, double dp0dt, double *work, hipStream_t st) {
     constexpr int PPW = 2;
     constexpr int NA = SRC ? 5 : 4;
     const int nsp = pad_odd(m.ns);
-    const void *fn = mixed ? (const void *)k_wdot<true, PPW, SRC, STORE> : (const void *)k_wdot<false, PPW, SRC, STORE>;
+    const void *fn = mixed ? (const void *)k_wdot<true, PPW, SRC, STORE, VAR> : (const void *)k_wdot<false, PPW, SRC, STORE, VAR>;
     int WPB = 4;
     size_t shm = 0;
     const hipError_t e = lds_waves(fn, (size_t)PPW * NA * nsp * sizeof(double), WPB, shm);
@@ -1815,12 +1984,24 @@ hipError_t launch_wdot_t(const DevMech &m, int mixed, int64_t n, const double *T
     const int64_t groups = (n + PPW - 1) / PPW;
     const dim3 grid(grid_for(groups, WPB, 16)), block(WPB * WAVE);
     if (mixed)
-        hipLaunchKernelGGL((k_wdot<true, PPW, SRC, STORE>), grid, block, shm, st, m, n, T, p, ps, Y, ld, wdot, hrr,
+        hipLaunchKernelGGL((k_wdot<true, PPW, SRC, STORE, VAR>), grid, block, shm, st, m, n, T, p, ps, Y, ld, wdot, hrr,
                            rmass, dTdt, QT, dp0dt, nsp, work);
     else
-        hipLaunchKernelGGL((k_wdot<false, PPW, SRC, STORE>), grid, block, shm, st, m, n, T, p, ps, Y, ld, wdot, hrr,
+        hipLaunchKernelGGL((k_wdot<false, PPW, SRC, STORE, VAR>), grid, block, shm, st, m, n, T, p, ps, Y, ld, wdot, hrr,
                            rmass, dTdt, QT, dp0dt, nsp, work);
     return hipGetLastError();
+}
+
+// Mechanisms with optional rate forms run the instances that evaluate them (VAR); the
+// others run instances without that code (fewer registers, no per-reaction form record).
+template <bool SRC, bool STORE>
+hipError_t launch_wdot_t(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
+                         const double *Y, int64_t ld, double *wdot, double *hrr, double *rmass, double *dTdt,
+                         double *QT, double dp0dt, double *work, hipStream_t st) {
+    if (m.n_var)
+        return launch_wdot_tv<SRC, STORE, true>(m, mixed, n, T, p, ps, Y, ld, wdot, hrr, rmass, dTdt, QT, dp0dt, work,
+                                                st);
+    return launch_wdot_tv<SRC, STORE, false>(m, mixed, n, T, p, ps, Y, ld, wdot, hrr, rmass, dTdt, QT, dp0dt, work, st);
 }
 
 hipError_t launch_wdot(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
@@ -1840,49 +2021,65 @@ hipError_t launch_source(const DevMech &m, int mixed, int64_t n, const double *T
                                       st);
 }
 
-hipError_t launch_vjp(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
-                      const double *Y, int64_t ld, const double *u, const double *uh, double *gT, double *gY,
-                      const double *work, hipStream_t st) {
+template <bool VAR>
+hipError_t launch_vjp_v(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
+                        const double *Y, int64_t ld, const double *u, const double *uh, double *gT, double *gY,
+                        const double *work, hipStream_t st) {
     const int nsp = pad_odd(m.ns);
     // the stored values already carry the forward pass's precision: one stored instance
-    const void *fn = work ? (const void *)k_vjp<false, true>
-                          : (mixed ? (const void *)k_vjp<true, false> : (const void *)k_vjp<false, false>);
+    const void *fn = work ? (const void *)k_vjp<false, true, VAR>
+                          : (mixed ? (const void *)k_vjp<true, false, VAR> : (const void *)k_vjp<false, false, VAR>);
     int WPB = 4;
     size_t shm = 0;
     const hipError_t e = lds_waves(fn, (size_t)7 * nsp * sizeof(double), WPB, shm);
     if (e != hipSuccess) return e;
     const dim3 grid(grid_for(n, WPB, 16)), block(WPB * WAVE);
     if (work)
-        hipLaunchKernelGGL((k_vjp<false, true>), grid, block, shm, st, m, n, T, p, ps, Y, ld, u, uh, gT, gY, nsp,
+        hipLaunchKernelGGL((k_vjp<false, true, VAR>), grid, block, shm, st, m, n, T, p, ps, Y, ld, u, uh, gT, gY, nsp,
                            work);
     else if (mixed)
-        hipLaunchKernelGGL((k_vjp<true, false>), grid, block, shm, st, m, n, T, p, ps, Y, ld, u, uh, gT, gY, nsp,
+        hipLaunchKernelGGL((k_vjp<true, false, VAR>), grid, block, shm, st, m, n, T, p, ps, Y, ld, u, uh, gT, gY, nsp,
                            work);
     else
-        hipLaunchKernelGGL((k_vjp<false, false>), grid, block, shm, st, m, n, T, p, ps, Y, ld, u, uh, gT, gY, nsp,
+        hipLaunchKernelGGL((k_vjp<false, false, VAR>), grid, block, shm, st, m, n, T, p, ps, Y, ld, u, uh, gT, gY, nsp,
                            work);
     return hipGetLastError();
 }
 
-hipError_t launch_jvp(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
-                      const double *Y, int64_t ld, const double *vT, const double *vY, double *jh, double *jw,
-                      double *wdot, hipStream_t st) {
+hipError_t launch_vjp(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
+                      const double *Y, int64_t ld, const double *u, const double *uh, double *gT, double *gY,
+                      const double *work, hipStream_t st) {
+    return m.n_var ? launch_vjp_v<true>(m, mixed, n, T, p, ps, Y, ld, u, uh, gT, gY, work, st)
+                   : launch_vjp_v<false>(m, mixed, n, T, p, ps, Y, ld, u, uh, gT, gY, work, st);
+}
+
+template <bool VAR>
+hipError_t launch_jvp_v(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
+                        const double *Y, int64_t ld, const double *vT, const double *vY, double *jh, double *jw,
+                        double *wdot, hipStream_t st) {
     // one point per wavefront: the two-point form needed more than the 168 VGPRs of three
     // waves per SIMD and spilled to scratch (and its mixed-mode build returned NaN on the
     // mechanism with PLOG/Chebyshev/SRI reactions, which this form does not)
     const int nsp = pad_odd(m.ns);
     const size_t per_point = (size_t)7 * nsp * sizeof(double);
-    const void *fn = mixed ? (const void *)k_jvp<true, 1> : (const void *)k_jvp<false, 1>;
+    const void *fn = mixed ? (const void *)k_jvp<true, 1, VAR> : (const void *)k_jvp<false, 1, VAR>;
     int WPB = 4;
     size_t shm = 0;
     const hipError_t e = lds_waves(fn, per_point, WPB, shm);
     if (e != hipSuccess) return e;
     const dim3 grid(grid_for(n, WPB, 16)), block(WPB * WAVE);
     if (mixed)
-        hipLaunchKernelGGL((k_jvp<true, 1>), grid, block, shm, st, m, n, T, p, ps, Y, ld, vT, vY, jh, jw, wdot, nsp);
+        hipLaunchKernelGGL((k_jvp<true, 1, VAR>), grid, block, shm, st, m, n, T, p, ps, Y, ld, vT, vY, jh, jw, wdot, nsp);
     else
-        hipLaunchKernelGGL((k_jvp<false, 1>), grid, block, shm, st, m, n, T, p, ps, Y, ld, vT, vY, jh, jw, wdot, nsp);
+        hipLaunchKernelGGL((k_jvp<false, 1, VAR>), grid, block, shm, st, m, n, T, p, ps, Y, ld, vT, vY, jh, jw, wdot, nsp);
     return hipGetLastError();
+}
+
+hipError_t launch_jvp(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
+                      const double *Y, int64_t ld, const double *vT, const double *vY, double *jh, double *jw,
+                      double *wdot, hipStream_t st) {
+    return m.n_var ? launch_jvp_v<true>(m, mixed, n, T, p, ps, Y, ld, vT, vY, jh, jw, wdot, st)
+                   : launch_jvp_v<false>(m, mixed, n, T, p, ps, Y, ld, vT, vY, jh, jw, wdot, st);
 }
 
 template <int DMAX>
@@ -1897,6 +2094,49 @@ hipError_t launch_jac_seg(const DevMech &m, int mixed, int64_t n, const double *
         hipLaunchKernelGGL((k_jac_seg<true, DMAX>), grid, block, m.jp_lds, st, m, n, T, p, ps, Y, ld, J, wdot);
     else
         hipLaunchKernelGGL((k_jac_seg<false, DMAX>), grid, block, m.jp_lds, st, m, n, T, p, ps, Y, ld, J, wdot);
+    return hipGetLastError();
+}
+
+// The kernels for mechanisms the segmented plan does not take: the reaction table when it
+// fits the LDS, else the row blocks that re-evaluate the reactions per block.
+template <bool VAR>
+hipError_t launch_jac_general(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
+                              const double *Y, int64_t ld, void *J, double *wdot, hipStream_t st) {
+    const int nsp = pad_odd(m.ns);
+    const int n1 = m.ns + 1;
+    const int sr = pad_odd(n1);
+    const size_t acc = sizeof(double);
+    JacRtLayout lay;
+    if (jac_rt_fits(m.ns, m.nr, mixed != 0, &lay)) {
+        // reaction table in LDS: each reaction evaluated once per point
+        const int nrp = (m.nr + 1) & ~1;
+        const void *fn = mixed ? (const void *)k_jac_rt<true, VAR> : (const void *)k_jac_rt<false, VAR>;
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lay.total);
+        if (e != hipSuccess) return e;
+        const dim3 grid(grid_for(n, 1, 1)), block(KR_WAVES * WAVE);
+        if (mixed)
+            hipLaunchKernelGGL((k_jac_rt<true, VAR>), grid, block, lay.total, st, m, n, T, p, ps, Y, ld, J, wdot, nsp, sr,
+                               lay.rows, nrp);
+        else
+            hipLaunchKernelGGL((k_jac_rt<false, VAR>), grid, block, lay.total, st, m, n, T, p, ps, Y, ld, J, wdot, nsp, sr,
+                               lay.rows, nrp);
+        return hipGetLastError();
+    }
+    const size_t fixed = (size_t)(4 * nsp + 4 * (nsp + 1)) * sizeof(double);
+    // rows per block: as many as fit one compute unit's LDS (one workgroup per point)
+    const size_t budget = CU_LDS_BYTES - 256;
+    int rb = (int)((budget > fixed ? budget - fixed : 0) / ((size_t)sr * acc));
+    if (rb >= n1) rb = n1;
+    if (rb < 1) return hipErrorInvalidValue;
+    const size_t shm = fixed + (size_t)rb * sr * acc;
+    const void *fn = mixed ? (const void *)k_jac<true, VAR> : (const void *)k_jac<false, VAR>;
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    const dim3 grid(grid_for(n, 1, 1)), block(KJ_WAVES * WAVE);
+    if (mixed)
+        hipLaunchKernelGGL((k_jac<true, VAR>), grid, block, shm, st, m, n, T, p, ps, Y, ld, J, wdot, nsp, sr, rb);
+    else
+        hipLaunchKernelGGL((k_jac<false, VAR>), grid, block, shm, st, m, n, T, p, ps, Y, ld, J, wdot, nsp, sr, rb);
     return hipGetLastError();
 }
 
@@ -1920,26 +2160,8 @@ hipError_t launch_jac(const DevMech &m, int mixed, int64_t n, const double *T, c
         if (r <= 22) return launch_jac_seg<22>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
         return launch_jac_seg<JS_DMAX>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
     }
-    const int nsp = pad_odd(m.ns);
-    const int n1 = m.ns + 1;
-    const int sr = pad_odd(n1);
-    const size_t acc = sizeof(double);
-    const size_t fixed = (size_t)(4 * nsp + 4 * (nsp + 1)) * sizeof(double);
-    // rows per block: as many as fit one compute unit's LDS (one workgroup per point)
-    const size_t budget = CU_LDS_BYTES - 256;
-    int rb = (int)((budget > fixed ? budget - fixed : 0) / ((size_t)sr * acc));
-    if (rb >= n1) rb = n1;
-    if (rb < 1) return hipErrorInvalidValue;
-    const size_t shm = fixed + (size_t)rb * sr * acc;
-    const void *fn = mixed ? (const void *)k_jac<true> : (const void *)k_jac<false>;
-    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-    const dim3 grid(grid_for(n, 1, 1)), block(KJ_WAVES * WAVE);
-    if (mixed)
-        hipLaunchKernelGGL((k_jac<true>), grid, block, shm, st, m, n, T, p, ps, Y, ld, J, wdot, nsp, sr, rb);
-    else
-        hipLaunchKernelGGL((k_jac<false>), grid, block, shm, st, m, n, T, p, ps, Y, ld, J, wdot, nsp, sr, rb);
-    return hipGetLastError();
+    return m.n_var ? launch_jac_general<true>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st)
+                   : launch_jac_general<false>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
 }
 
 // Copies the state (T, Y with leading dimension lds) to (T, Y with leading dimension ldd).

@@ -41,7 +41,7 @@ def _dev(st):
 
 def test_variant_plan_is_row_block(var):
     crf, g, om = var
-    assert g.jac_plan.startswith("row-block") and "PLOG" in g.jac_plan
+    assert g.jac_plan.startswith("reaction-table") and "PLOG" in g.jac_plan
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
