@@ -5,10 +5,13 @@ Workload: the 53-species / 325-reaction mechanism (40 three-body, 25 Troe fallof
 10 % near-equilibrium points, p in {1, 10} atm, Y ~ Dirichlet(0.3)), synthetic.
 One step = one fused crf_wdot_jac call (state, thermo, rate constants, falloff,
 equilibrium constants, rates of progress, production rates and the dense Jacobian)
-over the whole batch.  The rest of the per-point path (thermo, transport, VJP) is
-timed in the same run and reported under "path_mpoints_per_s"; "supporting" holds the
-200-species figures (one launch of 1000 spectral elements of 8^3 points at 40 atm; the
-mixed Jacobian on a chunk of 2^15 points).
+over the whole batch.  The rest of the per-point path is timed in the same run on the
+2^20-point state ("path": production rates, transport, VJP, J v, source terms, the
+stored-intermediate VJP and thermo, each with its HBM fraction and its fraction of the
+bound set by its exponentials at the measured exponential rates in "peaks_measured"),
+"c0" is the 9-species mechanism in microseconds per call, and "c4" the 200-species
+figures aggregated over 8 launches of 1000-8000 spectral elements of 8^3 points at
+40 atm (the mixed Jacobian in chunks of whole elements under a 12 GB budget).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-path] [--no-c4]
 
@@ -78,64 +81,191 @@ def timed(fn, steps, warmup, stream):
     return start.elapsed_time(stop) / steps      # ms per call
 
 
-def supporting_c4(crf, steps):
-    """Supporting figures on the 200-species / 1500-reaction mechanism (300 third-body,
-    150 Troe) at 40 atm: one launch of 1000 spectral elements of 8^3 points with flame
-    fronts (512 000 points): production rates, transport and VJP in both modes, and the
-    mixed-mode Jacobian (FP32, 201 x 201 per point) on a chunk of 2^15 points."""
+def transcendentals(om, prec, kind):
+    """FP64 and FP32 exponentials/logarithms per point of one call on this mechanism (the
+    minimum the kernels evaluate): rate constants (one per reaction, FP32 in the mixed
+    mode), 1/K_c (one FP64 per reaction in both modes), Troe P_r, F_cent (3), log F_cent,
+    ln [M], F (6 per falloff reaction, plus k0 for derivatives); transport: mu_k, lambda_k
+    and the pair diffusivities (FP32 in the mixed mode)."""
+    nr = om.n_reactions
+    nt = sum(1 for k in om.kind if k == "troe")
+    ns = om.n_species
+    if kind == "transport":
+        n = 2 * ns + ns * (ns - 1) // 2
+        return (0, n) if prec == "mixed" else (n, 0)
+    deriv = kind in ("vjp", "jvp", "jac")
+    rate = nr + 6 * nt + (nt if deriv else 0)
+    return (nr, rate) if prec == "mixed" else (nr + rate, 0)
+
+
+def measure_peaks(crf, stream):
+    """Measured rates of the probe kinds (operations/s) and a plain HBM copy (GB/s)."""
+    import ctypes
+
+    import torch
+    from paper_2409_06404_amd import _lib
+    L = _lib.lib()
+    threads = 256 * 256 * 8
+    out = torch.empty(threads, dtype=torch.float64, device="cuda")
+    res = {}
+    for kind, name, iters in ((0, "exp_f64_library", 64), (1, "exp_f64_devicelib", 64), (2, "exp_f32_v_exp", 256),
+                              (3, "fma_f64", 1024), (4, "fma_f32", 1024)):
+        fn = lambda: _lib.check(L.crf_peak_rate(kind, threads, iters, ctypes.c_void_p(out.data_ptr()),
+                                                ctypes.c_void_p(stream.cuda_stream)))
+        ms = timed(fn, 3, 1, stream)
+        res[name] = threads * iters * 8 / (ms * 1e-3)
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+    b = torch.empty_like(a)
+    ms = timed(lambda: b.copy_(a), 5, 1, stream)
+    res["hbm_copy_GBps"] = 2 * a.numel() * 8 / (ms * 1e-3) / 1e9
+    del a, b, out
+    torch.cuda.empty_cache()
+    return res
+
+
+def roof(n, ms, bytes_per_point, t64, t32, peaks):
+    """Rate, HBM fraction and transcendental-bound fraction of one call."""
+    rate = n / (ms * 1e-3)
+    t_exp = t64 / peaks["exp_f64_library"] + t32 / peaks["exp_f32_v_exp"]      # s per point
+    return {"mpoints_per_s": rate / 1e6, "bytes_per_point": bytes_per_point,
+            "hbm_frac": rate * bytes_per_point / (HBM_PEAK_GBS * 1e9),
+            "exp_per_point": [t64, t32], "exp_bound_mpoints_per_s": 1.0 / t_exp / 1e6 if t_exp > 0 else None,
+            "exp_frac": rate * t_exp if t_exp > 0 else None}
+
+
+def path_figures(crf, m, om, T, p, Y, u, prec, steps, stream, peaks):
+    """Every per-point call on the 2^20-point state (C1: FP64; C2: mixed; C3: VJP)."""
+    import torch
+    n, ns = T.shape[0], om.n_species
+    dev = T.device
+    out = {}
+    io = 8 * (2 + ns)
+    calls = {
+        "wdot": (lambda: crf.wdot(m, T, p, Y, prec, hrr=True), io + 8 * ns + 8, "wdot"),
+        "transport": (lambda: crf.transport(m, T, p, Y, prec), io + 8 * ns + 16, "transport"),
+        "vjp": (lambda: crf.wdot_vjp(m, T, p, Y, u, None, prec), io + 8 * ns + 8 + 8 * ns, "vjp"),
+        "jvp": (lambda: crf.wdot_jvp(m, T, p, Y, u, T, prec), io + 8 * ns + 8 + 8 * ns + 8, "jvp"),
+        "source": (lambda: crf.source(m, T, p, Y, prec), io + 8 * ns + 24, "wdot"),
+    }
+    for name, (fn, bpp, kind) in calls.items():
+        ms = timed(fn, steps, 1, stream)
+        out[name] = roof(n, ms, bpp, *transcendentals(om, prec, kind), peaks)
+    work = crf.new_workspace(m, n, prec)
+    ms = timed(lambda: crf.wdot_fwd(m, T, p, Y, work, prec), steps, 1, stream)
+    out["wdot_fwd_store"] = roof(n, ms, io + 8 * ns + 8 + 32 * om.n_reactions, *transcendentals(om, prec, "jac"),
+                                 peaks)
+    ms = timed(lambda: crf.wdot_vjp(m, T, p, Y, u, None, prec, work=work), steps, 1, stream)
+    out["vjp_stored"] = roof(n, ms, io + 16 * ns + 8 + 32 * om.n_reactions, 0, 0, peaks)
+    del work
+    torch.cuda.empty_cache()
+    if prec == "fp64":
+        ms = timed(lambda: crf.thermo(m, T, p, Y), steps, 1, stream)
+        out["thermo"] = roof(n, ms, io + 4 * 8 * ns + 32, 0, 0, peaks)
+    return out
+
+
+def c0_latency(crf, steps, stream):
+    """The 9-species / 21-reaction mechanism on 4096 points: microseconds per crf_wdot call
+    (launch-bound by construction: fewer points than one wave per compute unit)."""
     import numpy as np
     import torch
 
     import synth
     dev = torch.device("cuda", 0)
-    stream = torch.cuda.current_stream(dev)
+    with tempfile.TemporaryDirectory() as d:
+        path = synth.write_mechanism(synth.MECH_C0, os.path.join(d, "c0.mech"))
+        m = crf.Mechanism(path, device=0)
+        st = synth.state_c0(m.n_species, n=4096, seed=0)
+        T = torch.from_numpy(st["T"]).to(dev)
+        p = torch.from_numpy(st["p"]).to(dev)
+        Y = torch.from_numpy(np.ascontiguousarray(st["Y"])).to(dev).t()
+        us = timed(lambda: crf.wdot(m, T, p, Y, "fp64", hrr=True), max(steps, 200), 10, stream) * 1e3
+        m.close()
+    return {"workload": "9 species / 21 reactions, 4096 points, 1 atm", "us_per_call": us, "calls": max(steps, 200)}
+
+
+def supporting_c4(crf, stream, budget_gb=12.0):
+    """The 200-species / 1500-reaction mechanism (300 third-body, 150 Troe) at 40 atm over
+    its 8 launches of U{1000..8000} spectral elements of 8^3 points (the same element-count
+    draw as the parity state): production rates and VJP over whole launches in both modes,
+    and the mixed-mode Jacobian (201 x 201 FP32 per point) in chunks of whole elements
+    that fit `budget_gb` GB, every chunk of every launch computed; aggregate rates."""
+    import numpy as np
+    import torch
+
+    import synth
+    dev = torch.device("cuda", 0)
+    counts = synth.c4_element_counts(seed=4)
     with tempfile.TemporaryDirectory() as d:
         path = synth.write_mechanism(synth.MECH_C4, os.path.join(d, "c4.mech"))
         m = crf.Mechanism(path, device=0)
         ns = m.n_species
-        st = synth.state_c4_launch(ns, 1000, seed=4, launch=0)
-        n = st["T"].shape[0]
-        T = torch.from_numpy(st["T"]).to(dev)
-        p = torch.from_numpy(st["p"]).to(dev)
-        Y = torch.from_numpy(np.ascontiguousarray(st["Y"])).to(dev).t()
-        u = torch.randn((ns, n), dtype=torch.float64, device=dev).t()
-        out = {"workload": "200 species / 1500 reactions (300 third-body, 150 Troe), 40 atm, "
-                           "1000 elements x 8^3 points", "n_points": n, "unit": "Mpoints/s"}
-        for prec in ("fp64", "mixed"):
-            out[prec] = {
-                "wdot": n / (timed(lambda: crf.wdot(m, T, p, Y, prec, hrr=True), steps, 1, stream) * 1e-3) / 1e6,
-                "transport": n / (timed(lambda: crf.transport(m, T, p, Y, prec), steps, 1, stream) * 1e-3) / 1e6,
-                "vjp": n / (timed(lambda: crf.wdot_vjp(m, T, p, Y, u, None, prec), steps, 1, stream) * 1e-3) / 1e6,
-            }
-        nj = 1 << 15
-        J = torch.empty((nj, ns + 1, ns + 1), dtype=torch.float32, device=dev)
-        Tj, pj, Yj = T[:nj], p[:nj], Y[:nj]
-        ms = timed(lambda: crf.wdot_jac(m, Tj, pj, Yj, "mixed", out=J), steps, 1, stream)
-        out["mixed"]["jac_chunk"] = nj / (ms * 1e-3) / 1e6
-        out["jac_chunk_points"] = nj
-        out["jac_plan"] = m.jac_plan
+        n1 = ns + 1
+        chunk = int(budget_gb * 1e9 / (n1 * n1 * 4)) // 512 * 512
+        J = torch.empty((chunk, n1, n1), dtype=torch.float32, device=dev)
+        tot = {"points": 0, "fp64": {"wdot": 0.0, "vjp": 0.0}, "mixed": {"wdot": 0.0, "vjp": 0.0, "jac": 0.0}}
+        per_launch = []
+        for li, E in enumerate(counts):
+            T, p, Ysm = synth.state_c4_launch_device(ns, E, seed=4, launch=li, device="cuda")
+            Y = Ysm.t()
+            n = T.shape[0]
+            u = torch.randn((ns, n), dtype=torch.float64, device=dev).t()
+            rec = {"elements": E, "points": n}
+            for prec in ("fp64", "mixed"):
+                for name, fn in (("wdot", lambda: crf.wdot(m, T, p, Y, prec, hrr=True)),
+                                 ("vjp", lambda: crf.wdot_vjp(m, T, p, Y, u, None, prec))):
+                    ms = timed(fn, 1, 1 if li == 0 else 0, stream)
+                    tot[prec][name] += ms
+                    rec[f"{prec}_{name}_ms"] = ms
+            def jac_all():
+                for c0 in range(0, n, chunk):
+                    c1 = min(n, c0 + chunk)
+                    crf.wdot_jac(m, T[c0:c1], p[c0:c1], Y[c0:c1], "mixed", out=J[:c1 - c0], with_wdot=False)
+            ms = timed(jac_all, 1, 1 if li == 0 else 0, stream)
+            tot["mixed"]["jac"] += ms
+            rec["mixed_jac_ms"] = ms
+            tot["points"] += n
+            per_launch.append(rec)
+            del T, p, Ysm, Y, u
+            torch.cuda.empty_cache()
         del J
+        plan = m.jac_plan
         m.close()
         torch.cuda.empty_cache()
-    return out
+    agg = {prec: {k: tot["points"] / (v * 1e-3) / 1e6 for k, v in tot[prec].items()} for prec in ("fp64", "mixed")}
+    jb = n1 * n1 * 4 + 8 * (2 + 2 * ns)
+    return {"workload": "200 species / 1500 reactions (300 third-body, 150 Troe), 40 atm, 8 launches of "
+                        f"{counts} elements x 8^3 points", "points": tot["points"], "unit": "Mpoints/s",
+            "aggregate": agg, "jac_chunk_points": chunk, "jac_plan": plan,
+            "jac_roofline": {"bound": "hbm", "bytes_per_point": jb,
+                             "frac": agg["mixed"]["jac"] * 1e6 * jb / (HBM_PEAK_GBS * 1e9)},
+            "per_launch": per_launch}
 
 
 def cpu_baseline(mech_path, st, n_sample):
-    """The FP64 numpy oracle (production rates + analytic Jacobian) on a bounded sample."""
+    """The FP64 numpy oracle (production rates + analytic Jacobian) on a bounded sample;
+    cores = the host threads it kept busy on average (process CPU time / wall time)."""
     import numpy as np
 
     import oracle
     om = oracle.read_mechanism(mech_path)
     T, p, Y = st["T"][:n_sample], st["p"][:n_sample], np.ascontiguousarray(st["Y"][:, :n_sample].T)
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+    except Exception:
+        blas = None
     c0, w0 = time.process_time(), time.perf_counter()
     oracle.production_rates(om, T, p, Y)
+    w1 = time.perf_counter()
     oracle.jacobian(om, T, p, Y)
     wall = time.perf_counter() - w0
     cpu = time.process_time() - c0
     return {"value": n_sample / wall / 1e6, "unit": "Mpoints/s", "cores": max(1, round(cpu / wall)),
             "kind": "oracle",
-            "sample": f"{n_sample} points of the same state (production rates + analytic Jacobian, FP64 numpy), "
-                      f"{wall:.1f} s wall on {os.cpu_count()} host CPUs"}
+            "sample": f"{n_sample} points of the same state: production rates ({w1 - w0:.1f} s) + analytic "
+                      f"Jacobian ({wall - (w1 - w0):.1f} s), FP64 numpy; {cpu / wall:.1f} threads busy on average "
+                      f"(BLAS pool {blas}, host CPUs {os.cpu_count()})"}
 
 
 def main():
@@ -144,6 +274,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--points", type=int, default=1 << 18)
+    ap.add_argument("--path-points", type=int, default=1 << 20,
+                    help="points of the supporting per-point calls (the 2^20-point state)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=10240,
                     help="points of the oracle CPU baseline (about 10-30 s of host time)")
@@ -152,6 +284,8 @@ def main():
                     help="also run a plain 1 GiB device copy (the reference for HBM byte counters)")
     ap.add_argument("--no-path", action="store_true", help="time the fused wdot+Jacobian call only")
     ap.add_argument("--no-c4", action="store_true", help="skip the 200-species supporting figures")
+    ap.add_argument("--no-jac", action="store_true",
+                    help="skip the headline Jacobian (profiling runs of the supporting calls)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -161,6 +295,7 @@ def main():
     import numpy as np
     import torch
 
+    import oracle
     import synth
     import paper_2409_06404_amd as crf
 
@@ -168,6 +303,7 @@ def main():
     n = args.points
     with tempfile.TemporaryDirectory() as d:
         mech_path = synth.write_mechanism(synth.MECH_C1, os.path.join(d, "c1.mech"))
+        om = oracle.read_mechanism(mech_path)
         m = crf.Mechanism(mech_path, device=0)
         ns = m.n_species
         full = synth.state_c1(ns, n=1 << 20, seed=1)
@@ -175,7 +311,6 @@ def main():
         T = torch.from_numpy(st["T"]).to(dev)
         p = torch.from_numpy(st["p"]).to(dev)
         Y = torch.from_numpy(st["Y"]).to(dev).t()
-        u = torch.randn((ns, n), dtype=torch.float64, device=dev).t()
         stream = torch.cuda.current_stream(dev)
         if args.calib_copy:
             a = torch.ones(1 << 27, dtype=torch.float64, device=dev)     # 1 GiB
@@ -186,7 +321,7 @@ def main():
             torch.cuda.empty_cache()
         res = {}
         precs = [args.only] if args.only else ["fp64", "mixed"]
-        for prec in precs:
+        for prec in ([] if args.no_jac else precs):
             J = torch.empty((n, ns + 1, ns + 1), dtype=torch.float64 if prec == "fp64" else torch.float32,
                             device=dev)
             ms = timed(lambda: crf.wdot_jac(m, T, p, Y, prec, out=J), args.steps, args.warmup, stream)
@@ -200,24 +335,24 @@ def main():
                                       "bytes_per_point": bpp, "kernel": kname}}
             del J
             torch.cuda.empty_cache()
-        path = {}
-        for prec in ([] if args.no_path else precs):
-            path[prec] = {
-                "wdot": n / (timed(lambda: crf.wdot(m, T, p, Y, prec, hrr=True), args.steps, 1, stream) * 1e-3) / 1e6,
-                "transport": n / (timed(lambda: crf.transport(m, T, p, Y, prec), max(2, args.steps // 4), 1, stream) * 1e-3) / 1e6,
-                "vjp": n / (timed(lambda: crf.wdot_vjp(m, T, p, Y, u, None, prec), args.steps, 1, stream) * 1e-3) / 1e6,
-                "jvp": n / (timed(lambda: crf.wdot_jvp(m, T, p, Y, u, T, prec), args.steps, 1, stream) * 1e-3) / 1e6,
-                "source": n / (timed(lambda: crf.source(m, T, p, Y, prec), args.steps, 1, stream) * 1e-3) / 1e6,
-            }
-            work = crf.new_workspace(m, n, prec)
-            path[prec]["wdot_fwd_store"] = n / (timed(lambda: crf.wdot_fwd(m, T, p, Y, work, prec), args.steps, 1,
-                                                      stream) * 1e-3) / 1e6
-            path[prec]["vjp_stored"] = n / (timed(lambda: crf.wdot_vjp(m, T, p, Y, u, None, prec, work=work),
-                                                  args.steps, 1, stream) * 1e-3) / 1e6
-            del work
-        if "fp64" in path:
-            path["fp64"]["thermo"] = n / (timed(lambda: crf.thermo(m, T, p, Y), args.steps, 1, stream) * 1e-3) / 1e6
+        path, peaks, c0 = {}, None, None
+        if not args.no_path:
+            peaks = measure_peaks(crf, stream)
+            npath = args.path_points
+            Tf = torch.from_numpy(full["T"][:npath]).to(dev)
+            pf = torch.from_numpy(full["p"][:npath]).to(dev)
+            Yf = torch.from_numpy(np.ascontiguousarray(full["Y"][:, :npath])).to(dev).t()
+            uf = torch.randn((ns, npath), dtype=torch.float64, device=dev).t()
+            for prec in precs:
+                path[prec] = path_figures(crf, m, om, Tf, pf, Yf, uf, prec, max(3, args.steps // 4), stream, peaks)
+            path["points"] = npath
+            del Tf, pf, Yf, uf
+            torch.cuda.empty_cache()
+            c0 = c0_latency(crf, args.steps, stream)
         m.close()
+        if args.no_jac:
+            print(json.dumps({"path": path, "peaks_measured": peaks, "c0": c0}), flush=True)
+            return
         head = "fp64" if "fp64" in res else precs[0]
         out = {
             "metric": "Mpoints/s wdot+Jacobian (53 sp), FP64 vs mixed precision, % of roofline",
@@ -232,9 +367,12 @@ def main():
         }
         if "mixed" in res and head != "mixed":
             out["mixed"] = dict(res["mixed"], dtype="f32+f64")
-        out["path_mpoints_per_s"] = path
+        if not args.no_path:
+            out["peaks_measured"] = peaks
+            out["path"] = path
+            out["c0"] = c0
         if not (args.no_path or args.no_c4):
-            out["supporting"] = {"c4_200sp": supporting_c4(crf, max(3, args.steps // 4))}
+            out["c4"] = supporting_c4(crf, stream)
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline(mech_path, st, args.cpu_sample)
     print(json.dumps(out), flush=True)

@@ -8,7 +8,7 @@ EXPORTED = (
     "crf_load_mech", "crf_free_mech", "crf_n_species", "crf_n_reactions", "crf_device", "crf_jac_plan",
     "crf_last_error", "crf_status_str", "crf_thermo", "crf_wdot", "crf_transport",
     "crf_wdot_vjp", "crf_wdot_jac", "crf_wdot_jvp", "crf_source", "crf_workspace_bytes", "crf_wdot_fwd",
-    "crf_reactor_step", "crf_reactor_step_static",
+    "crf_reactor_step", "crf_reactor_step_static", "crf_peak_rate",
 )
 
 CRF_OK, CRF_E_ARG, CRF_E_PARSE, CRF_E_MECH, CRF_E_NOMEM, CRF_E_DEVICE, CRF_E_UNSUPPORTED, CRF_E_WORKSPACE = range(8)
@@ -76,6 +76,8 @@ def lib():
     L.crf_reactor_step.restype = I
     L.crf_reactor_step_static.argtypes = [P, I, I64, D, D, I64, D, I64, ctypes.c_double, I, P]
     L.crf_reactor_step_static.restype = I
+    L.crf_peak_rate.argtypes = [I, I64, I, D, P]
+    L.crf_peak_rate.restype = I
     _lib = L
     return L
 

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <string>
 
+#include "crf_bench.h"
 #include "crf_internal.h"
 
 namespace crf {
@@ -304,6 +305,16 @@ crf_status crf_wdot_jac(const crf_mech *m, crf_precision prec, int64_t n, const 
     return on_device(m, "crf_wdot_jac", [&] {
         return launch_jac(m->dev, prec == CRF_MIXED, n, T, p, ps, Y, ld, J, wdot, (hipStream_t)stream);
     });
+}
+
+crf_status crf_peak_rate(int kind, int64_t threads, int iters, double *out, crf_stream stream) {
+    if (kind < 0 || kind > 4) return fail(CRF_E_ARG, "crf_peak_rate: kind must be 0..4");
+    if (threads < 256 || threads % 256 != 0 || threads > ((int64_t)1 << 26))
+        return fail(CRF_E_ARG, "crf_peak_rate: threads must be a multiple of 256 in [256, 2^26]");
+    if (iters < 1 || !out) return fail(CRF_E_ARG, "crf_peak_rate: iters >= 1 and out required");
+    const hipError_t e = launch_peak(kind, threads, iters, out, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(CRF_E_DEVICE, std::string("crf_peak_rate: launch failed: ") + hipGetErrorString(e));
+    return CRF_OK;
 }
 
 }  // extern "C"

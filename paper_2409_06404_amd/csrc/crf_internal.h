@@ -237,6 +237,7 @@ hipError_t launch_reactor(const DevMech &m, int mixed, int64_t n, double *T, con
                           double *Y, int64_t ld, double dt, int nsub, void *work, hipStream_t st);
 hipError_t launch_reactor_static(const DevMech &m, int mixed, int64_t n, double *T, const double *p, int64_t ps,
                                  double *Y, int64_t ld, double dt, int nsub, hipStream_t st);
+hipError_t launch_peak(int kind, int64_t threads, int iters, double *out, hipStream_t st);
 hipError_t launch_jac(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
                       int64_t ps, const double *Y, int64_t ld, void *J, double *wdot, hipStream_t st);
 

@@ -1925,6 +1925,47 @@ __global__ __launch_bounds__(ROS_THREADS) void k_ros_finish(DevMech m, int64_t n
     }
 }
 
+// ------------------------------------------------------------------ peak-rate probes
+// Throughput probes for the roofline denominators: every thread runs 8 independent
+// chains of `iters` operations of one kind (0: exp_fast (FP64), 1: exp of the device
+// library (FP64), 2: __expf (v_exp_f32), 3: FP64 FMA, 4: FP32 FMA); out[thread] keeps the
+// result alive.  Operations = threads x iters x 8.
+__global__ __launch_bounds__(256) void k_peak(int kind, int iters, double *__restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    double d[8];
+    float f[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        d[c] = -1e-3 * (double)((t + c) & 1023);
+        f[c] = (float)d[c];
+    }
+    if (kind == 0) {
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) d[c] = exp_fast(d[c]) - 1.0;
+    } else if (kind == 1) {
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) d[c] = exp(d[c]) - 1.0;
+    } else if (kind == 2) {
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) f[c] = __expf(f[c]) - 1.0f;
+    } else if (kind == 3) {
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) d[c] = fma(d[c], 0.999999, 1e-9);
+    } else {
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) f[c] = fmaf(f[c], 0.999999f, 1e-9f);
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc += d[c] + (double)f[c];
+    out[t] = acc;
+}
+
 int device_cu_count() {
     static int cached[64] = {0};
     int dev = 0;
@@ -1960,6 +2001,11 @@ hipError_t lds_waves(const void *fn, size_t per_wave, int &wpb, size_t &shm) {
 }
 
 }  // namespace
+
+hipError_t launch_peak(int kind, int64_t threads, int iters, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_peak, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, kind, iters, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_thermo(const DevMech &m, int64_t n, const double *T, const double *p, int64_t ps,
                          const double *Y, int64_t ld, double *cp_k, double *h_k, double *s_k, double *g_k,

@@ -125,3 +125,32 @@ def state_c4_launch(ns, n_elements, seed=4, launch=0, p_pa=40.0 * P_ATM):
     n = n_elements * 512
     return {"T": T.reshape(n), "p": np.full(n, p_pa),
             "Y": np.ascontiguousarray(Y.reshape(n, ns).T)}
+
+
+def state_c4_launch_device(ns, n_elements, seed=4, launch=0, p_pa=40.0 * P_ATM, device="cuda"):
+    """state_c4_launch's recipe with its per-element draws taken from the same generator in
+    the same order, and the [E x 512 x Ns] fields formed on the device with torch (for
+    launches of thousands of elements; the per-point values agree with state_c4_launch to
+    the rounding of tanh).  Returns torch tensors T [n], p [n], Y [Ns, n] (FP64)."""
+    import torch
+    rng = np.random.default_rng([seed, launch])
+    x1 = gll_nodes(8)
+    zz, yy, xx = np.meshgrid(x1, x1, x1, indexing="ij")
+    X = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
+    nrm = rng.standard_normal((n_elements, 3))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    d = rng.uniform(-1.2, 1.2, size=n_elements)
+    delta = np.exp(rng.uniform(np.log(0.05), np.log(1.0), size=n_elements))
+    Yu = dirichlet_rows(rng, n_elements, ns, 0.3)
+    Yb = dirichlet_rows(rng, n_elements, ns, 0.3)
+    dev = torch.device(device)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    s_ = (t(nrm) @ t(X).T - t(d)[:, None]) / t(delta)[:, None]        # [E, 512]
+    T = 300.0 + 2100.0 * 0.5 * (1.0 + torch.tanh(s_))
+    c = ((T - 300.0) / 2100.0).reshape(-1)                             # [n]
+    n = n_elements * 512
+    Yu_d, Yb_d = t(Yu.T.copy()), t(Yb.T.copy())                        # [Ns, E]
+    Y = torch.empty((ns, n), dtype=torch.float64, device=dev)
+    for k in range(ns):                                                # [Ns, n] species-major
+        Y[k] = (1.0 - c) * Yu_d[k].repeat_interleave(512) + c * Yb_d[k].repeat_interleave(512)
+    return T.reshape(n), torch.full((n,), p_pa, dtype=torch.float64, device=dev), Y
