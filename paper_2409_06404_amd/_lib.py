@@ -2,7 +2,8 @@
 import ctypes
 import os
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcrf.so")
+# CRF_LIB names another build of the same ABI (the sanitized host-only build of the host tests)
+LIB_PATH = os.environ.get("CRF_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcrf.so")
 
 EXPORTED = (
     "crf_load_mech", "crf_free_mech", "crf_n_species", "crf_n_reactions", "crf_device", "crf_jac_plan",

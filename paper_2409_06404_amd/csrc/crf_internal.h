@@ -212,7 +212,33 @@ inline bool jac_rt_fits(int ns, int nr, bool mixed, JacRtLayout *out = nullptr) 
     return true;
 }
 
-// Kernel launchers (kernels.hip).// Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.
+// Byte layout of the workspace of crf_reactor_step for n points (offsets of its regions; all
+// regions 256-byte aligned).  FP64: the Newton matrix overwrites the Jacobian in place.
+struct RosLayout {
+    size_t J, M, wd, piv, k1, Tw, Yw, Ts, Ys, fT, fY, total;
+};
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+inline RosLayout ros_layout(int ns, int mixed, int64_t n) {
+    const size_t N = (size_t)ns + 1, nn = (size_t)n;
+    RosLayout L{};
+    size_t o = 0;
+    L.J = o; o = align256(o + nn * N * N * (mixed ? sizeof(float) : sizeof(double)));
+    if (mixed) { L.M = o; o = align256(o + nn * N * N * sizeof(double)); } else { L.M = L.J; }
+    L.wd = o; o = align256(o + nn * ns * sizeof(double));
+    L.piv = o; o = align256(o + nn * N * sizeof(int));
+    L.k1 = o; o = align256(o + nn * N * sizeof(double));
+    L.Tw = o; o = align256(o + nn * sizeof(double));
+    L.Yw = o; o = align256(o + nn * ns * sizeof(double));
+    L.Ts = o; o = align256(o + nn * sizeof(double));
+    L.Ys = o; o = align256(o + nn * ns * sizeof(double));
+    L.fT = o; o = align256(o + nn * sizeof(double));
+    L.fY = o; o = align256(o + nn * ns * sizeof(double));
+    L.total = o;
+    return L;
+}
+inline size_t reactor_work_bytes(int ns, int mixed, int64_t n) { return n > 0 ? ros_layout(ns, mixed, n).total : 0; }
+
+// Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_thermo(const DevMech &m, int64_t n, const double *T, const double *p, int64_t ps,
                          const double *Y, int64_t ld, double *cp_k, double *h_k, double *s_k,
                          double *g_k, double *cp_mass, double *h_mass, double *rho, double *Wbar,
@@ -232,7 +258,6 @@ hipError_t launch_jvp(const DevMech &m, int mixed, int64_t n, const double *T, c
 hipError_t launch_source(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
                          int64_t ps, const double *Y, int64_t ld, double dp0dt, double *dYdt,
                          double *dTdt, double *QT, double *hrr, hipStream_t st);
-size_t reactor_work_bytes(int ns, int mixed, int64_t n);
 hipError_t launch_reactor(const DevMech &m, int mixed, int64_t n, double *T, const double *p, int64_t ps,
                           double *Y, int64_t ld, double dt, int nsub, void *work, hipStream_t st);
 hipError_t launch_reactor_static(const DevMech &m, int mixed, int64_t n, double *T, const double *p, int64_t ps,

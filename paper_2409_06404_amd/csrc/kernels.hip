@@ -2222,36 +2222,6 @@ __global__ __launch_bounds__(256) void k_state_copy(int64_t n, int ns, const dou
     }
 }
 
-namespace {
-inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-}  // namespace
-
-// Byte layout of the reactor workspace for n points (offsets of its regions; all
-// regions 256-byte aligned).  FP64: the Newton matrix overwrites the Jacobian in place.
-struct RosLayout {
-    size_t J, M, wd, piv, k1, Tw, Yw, Ts, Ys, fT, fY, total;
-};
-RosLayout ros_layout(int ns, int mixed, int64_t n) {
-    const size_t N = (size_t)ns + 1, nn = (size_t)n;
-    RosLayout L{};
-    size_t o = 0;
-    L.J = o; o = align256(o + nn * N * N * (mixed ? sizeof(float) : sizeof(double)));
-    if (mixed) { L.M = o; o = align256(o + nn * N * N * sizeof(double)); } else { L.M = L.J; }
-    L.wd = o; o = align256(o + nn * ns * sizeof(double));
-    L.piv = o; o = align256(o + nn * N * sizeof(int));
-    L.k1 = o; o = align256(o + nn * N * sizeof(double));
-    L.Tw = o; o = align256(o + nn * sizeof(double));
-    L.Yw = o; o = align256(o + nn * ns * sizeof(double));
-    L.Ts = o; o = align256(o + nn * sizeof(double));
-    L.Ys = o; o = align256(o + nn * ns * sizeof(double));
-    L.fT = o; o = align256(o + nn * sizeof(double));
-    L.fY = o; o = align256(o + nn * ns * sizeof(double));
-    L.total = o;
-    return L;
-}
-
-size_t reactor_work_bytes(int ns, int mixed, int64_t n) { return n > 0 ? ros_layout(ns, mixed, n).total : 0; }
-
 hipError_t launch_reactor(const DevMech &m, int mixed, int64_t n, double *T, const double *p, int64_t ps, double *Y,
                           int64_t ld, double dt, int nsub, void *work, hipStream_t st) {
     const int ns = m.ns, N = ns + 1;

@@ -192,3 +192,51 @@ def test_jacobian_plan_selection(mech_dir):
             assert m.jac_plan.startswith(want), m.jac_plan
         finally:
             m.close()
+
+
+_GARBAGE = ("", "nan", "inf", "-inf", "-1", "0", "1e400", "-1e-400", "2147483648", "-2147483649",
+            "9223372036854775808", "x", "1:2:3", ":", "0:", ":1", "99999:1", "1:nan", "3.5", "-0")
+
+
+@pytest.fixture(scope="module")
+def variant_path(mech_dir):
+    import synth
+    return synth.write_mechanism(synth.MECH_V, str(mech_dir / "fuzz_v.mech"))
+
+
+@pytest.mark.parametrize("which", ["c0", "v"])
+def test_truncated_files_are_rejected(L, c0_path, variant_path, tmp_path, which):
+    """A file cut after any of its lines (before the last one) is refused with a status, never
+    read past its end; the variant mechanism holds the PLOG and Chebyshev blocks."""
+    lines = open(c0_path if which == "c0" else variant_path).read().splitlines()
+    last = max(i for i, ln in enumerate(lines) if ln.strip())
+    bad = tmp_path / "cut.mech"
+    for k in range(last):
+        bad.write_text("\n".join(lines[:k + 1]) + "\n")
+        s, h = _load(L, bad)
+        assert s in (2, 3, 6), (k, s, lines[k])
+        assert not h.value
+
+
+@pytest.mark.parametrize("which", ["c0", "v"])
+def test_corrupted_tokens_never_crash(L, c0_path, variant_path, tmp_path, which):
+    """Single tokens replaced by garbage (empty, non-finite, out-of-range integers, malformed
+    species:coefficient pairs): every load returns a status, and a file that still loads
+    describes a usable mechanism."""
+    import numpy as np
+    lines = open(c0_path if which == "c0" else variant_path).read().splitlines()
+    rng = np.random.default_rng(17 if which == "c0" else 18)
+    spots = [(i, j) for i, ln in enumerate(lines) for j in range(len(ln.split()))]
+    bad = tmp_path / "tok.mech"
+    for n in rng.choice(len(spots), size=min(300, len(spots)), replace=False):
+        i, j = spots[n]
+        toks = lines[i].split()
+        toks[j] = _GARBAGE[rng.integers(len(_GARBAGE))]
+        bad.write_text("\n".join(lines[:i] + [" ".join(toks)] + lines[i + 1:]) + "\n")
+        s, h = _load(L, bad)
+        assert 0 <= s <= 7
+        if s == 0:
+            assert L.crf_n_species(h) > 0 and L.crf_n_reactions(h) > 0 and L.crf_jac_plan(h)
+            L.crf_free_mech(h)
+        else:
+            assert not h.value and L.crf_last_error()
