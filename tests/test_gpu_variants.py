@@ -39,7 +39,7 @@ def _dev(st):
             torch.from_numpy(np.ascontiguousarray(st["Y"])).to(dev).t())
 
 
-def test_variant_plan_is_row_block(var):
+def test_variant_plan_is_reaction_table(var):
     crf, g, om = var
     assert g.jac_plan.startswith("reaction-table") and "PLOG" in g.jac_plan
 

@@ -73,8 +73,8 @@ def test_chebyshev_closed_forms(tmp_path):
 
 
 def test_sri_at_unit_reduced_pressure_and_scaling(tmp_path):
-    """At P_r = 1, X = 1 and F = d (a e^(-b/T) + e^(-T/c)) T^e, so k_f = kinf F / 2; F (and
-    k_f) scale with d everywhere."""
+    """At P_r = 1, X = 1 and F = d (a e^(-b/T) + e^(-T/c)) T^e, so k_f = kinf F / 2; at
+    P_r = 100, X = 1/5; F (and k_f) scale with d everywhere."""
     lnA, b, th = math.log(1e10), 0.3, 2000.0
     k0 = (math.log(1e14), -0.8, 500.0)
     sri = (0.8, 300.0, 900.0, 1.2, 0.15)
@@ -92,6 +92,11 @@ def test_sri_at_unit_reduced_pressure_and_scaling(tmp_path):
     a_, b_, c_, d_, e_ = sri
     F = d_ * (a_ * math.exp(-b_ / T) + math.exp(-T / c_)) * T ** e_
     assert r["kf"][0, 0] == pytest.approx(kinf * 0.5 * F, rel=1e-12)
+    # at P_r = 100, log10 P_r = 2 and X = 1/5: F = d S^(1/5) T^e, k_f = kinf (100/101) F
+    T_, p_, Y_ = _state(T, 100.0 * p, [0.4, 0.35, 0.25])
+    r = oracle.rates_of_progress(m, T_, p_, Y_)
+    F100 = d_ * (a_ * math.exp(-b_ / T) + math.exp(-T / c_)) ** 0.2 * T ** e_
+    assert r["kf"][0, 0] == pytest.approx(kinf * 100.0 / 101.0 * F100, rel=1e-12)
     m2 = _iso(tmp_path, [Reaction("sri", {0: 1, 1: 1}, {2: 1}, lnA, b, th,
                                   extra={"k0": k0, "sri": sri[:3] + (2 * d_, e_)})], "v2.mech")
     T2, p2, Y2 = _state(1700.0, 3 * P0, [0.2, 0.3, 0.5])
