@@ -80,6 +80,7 @@ struct DevMech {
     // pairs per round
     const int *tr_jk;         // [round][slot]: j | k << 16
     const double *tr_fit;     // [round][slot][4]: the pair's ln D fit (zeros for the dummy pair)
+    const float *tr_fit32;    // the same fits rounded to FP32 (the mixed mode)
     int tr_rounds, tr_slots;
     // reactions
     const double *lnA, *b, *theta;

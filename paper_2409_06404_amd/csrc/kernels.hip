@@ -1716,6 +1716,219 @@ __global__ __launch_bounds__(256) void k_transport(DevMech m, int64_t n, const d
     }
 }
 
+// ------------------------------------------------------------------ transport, point tiles
+// Sixteen points per workgroup of W wavefronts, one tile per workgroup.  LDS holds, per
+// species row of the tile (row stride TT_RS doubles, odd, so that the rows that one
+// instruction touches start on different banks): Xs_k = Y_k / W_k, the diffusion sums
+// IS_k = sum_j Xs_j / D_jk, b_k = W_k^(1/4) / sqrt(mu_k), a_k = 1 / b_k and mu_k.  The mole fractions are
+// X = Wbar Xs; Wbar cancels from Wilke's quotient and is applied to the conductivity and
+// diffusion sums at the end.
+//   * setup: thread = (point, species group); the 16 points of a species row are adjacent
+//     in Y, so each group of 16 lanes reads one 128-byte line;
+//   * diffusion: each wavefront owns 16/W points and runs every round of the pair schedule on
+//     them, 64 W/16 pairs per instruction.  A round touches each species once, so the LDS
+//     additions of one instruction never meet, and only the owning wavefront adds into a
+//     point's sums, in program order: the result is reproducible bit for bit;
+//   * Wilke: den_k = sum_j X_j c_jk (1 + a_k b_j)^2 with a_k = sqrt(mu_k) / W_k^(1/4) is
+//     D1_k + a_k (2 D2_k + a_k D3_k) with D1 = Xs C, D2 = (Xs b) C, D3 = (Xs b^2) C:
+//     three [16 x Ns] x [Ns x Ns] products on the matrix cores (16x16x4 MFMA, FP64, or FP32
+//     in the mixed mode), tiles of 16 species columns dealt to the wavefronts, C = wilke_c
+//     read from L2 once per tile of points.  mu = sum_k Xs_k mu_k / den~_k (Wbar cancels).
+constexpr int TT_P = 16;
+constexpr int TT_RS = 17;
+
+template <bool MIXED> struct TileMfma;
+template <> struct TileMfma<false> {
+    typedef double V __attribute__((ext_vector_type(4)));
+    __device__ static V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    // row of the product held in register r of `lane` (its column is lane % 16)
+    __device__ static int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <> struct TileMfma<true> {
+    typedef float V __attribute__((ext_vector_type(4)));
+    __device__ static V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+// Sum over the 16 lanes that share lane / 16 (butterfly, fixed order).
+__device__ inline double row16_sum(double v) {
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// LDS bytes of k_transport_tile for `rows` species rows (the species and the dummy of the pair
+// schedule) and W wavefronts.
+inline size_t tile_transport_lds(int rows, bool mixed, int W) {
+    return (size_t)rows * TT_RS * (2 * sizeof(double) + 3 * (mixed ? sizeof(float) : sizeof(double))) +
+           (size_t)(2 * TT_P + 4 * W * TT_P) * sizeof(double);
+}
+
+template <bool MIXED, int W>
+__global__ __launch_bounds__(W * WAVE) __attribute__((amdgpu_waves_per_eu(4))) void k_transport_tile(DevMech m, int64_t n, const double *__restrict__ T,
+                                                             const double *__restrict__ p, int64_t ps,
+                                                             const double *__restrict__ Y, int64_t ld,
+                                                             double *__restrict__ mu, double *__restrict__ lam,
+                                                             double *__restrict__ Dmix, int rows) {
+    using Rt = typename std::conditional<MIXED, float, double>::type;
+    using MM = TileMfma<MIXED>;
+    constexpr int NT = W * WAVE;
+    constexpr int PW = TT_P / W;                 // points per wavefront in the diffusion phase
+    constexpr int G = WAVE / PW;                 // pairs per wavefront instruction
+    constexpr int NG = NT / TT_P;                // species groups of the setup and output phases
+    extern __shared__ double lds[];
+    double *XS = lds;                            // [rows][TT_RS]
+    double *IS = XS + rows * TT_RS;              // [rows][TT_RS]
+    double *PT = IS + rows * TT_RS;              // lnT[16], ln(p0/p)[16], sums[W][16][3], num[W][16]
+    double *SUMS = PT + 2 * TT_P, *NUM = SUMS + 3 * W * TT_P;
+    Rt *BB = (Rt *)(NUM + W * TT_P);             // [rows][TT_RS]
+    Rt *AA = BB + rows * TT_RS;                  // [rows][TT_RS]
+    Rt *MU = AA + rows * TT_RS;                  // [rows][TT_RS]
+    const int tid = threadIdx.x, wave = tid / WAVE, lane = tid & (WAVE - 1);
+    const int ns = m.ns;
+    {
+        const int64_t i0 = (int64_t)blockIdx.x * TT_P;
+        {   // setup
+            const int mm = tid % TT_P, g = tid / TT_P;
+            const int64_t i = i0 + mm < n ? i0 + mm : n - 1;
+            const double L = log(T[i]);
+            const Rt Lr = (Rt)L;
+            if (g == 0) {
+                PT[mm] = L;
+                PT[TT_P + mm] = log(m.p0 / p[i * ps]);
+            }
+            double sx = 0.0, sxl = 0.0, sxil = 0.0;
+            for (int k = g; k < rows; k += NG) {
+                double x = 0.0;
+                Rt b = 0, ak = 0, muk = 0;
+                if (k < ns) {
+                    x = Y[(int64_t)k * ld + i] * m.invW[k];
+                    const double *a = m.mu_fit + 4 * k, *c = m.lam_fit + 4 * k;
+                    muk = exp_r<Rt>((Rt)a[0] + Lr * ((Rt)a[1] + Lr * ((Rt)a[2] + Lr * (Rt)a[3])));
+                    const double lk = (double)exp_r<Rt>((Rt)c[0] + Lr * ((Rt)c[1] + Lr * ((Rt)c[2] + Lr * (Rt)c[3])));
+                    const double sq = sqrt((double)muk);
+                    b = (Rt)(m.w4[k] / sq);
+                    ak = (Rt)(sq * m.iw4[k]);
+                    sx += x;
+                    sxl += x * lk;
+                    sxil += x / lk;
+                }
+                XS[k * TT_RS + mm] = x;
+                IS[k * TT_RS + mm] = 0.0;
+                BB[k * TT_RS + mm] = b;
+                AA[k * TT_RS + mm] = ak;
+                MU[k * TT_RS + mm] = muk;
+            }
+            // the wavefront's four species groups of a point: lanes mm, mm + 16, mm + 32, mm + 48
+            sx += __shfl_xor(sx, 16);
+            sx += __shfl_xor(sx, 32);
+            sxl += __shfl_xor(sxl, 16);
+            sxl += __shfl_xor(sxl, 32);
+            sxil += __shfl_xor(sxil, 16);
+            sxil += __shfl_xor(sxil, 32);
+            if (lane < TT_P) {
+                double *s = SUMS + 3 * (wave * TT_P + lane);
+                s[0] = sx;
+                s[1] = sxl;
+                s[2] = sxil;
+            }
+        }
+        __syncthreads();
+        if (Dmix) {   // binary diffusion sums of the wavefront's own points
+            const int q = lane % PW, sg = lane / PW, mm = wave * PW + q;
+            const Rt L = (Rt)PT[mm], lp = (Rt)PT[TT_P + mm];
+            double *ISm = IS + mm;
+            const double *XSm = XS + mm;
+            const int slots = m.tr_slots;
+            for (int r = 0; r < m.tr_rounds; ++r) {
+                const int e0 = r * slots;
+                for (int s = sg; s < slots; s += G) {
+                    const int e = e0 + s;
+                    const int jk = m.tr_jk[e];
+                    const int j = jk & 0xffff, k = jk >> 16;
+                    Rt c0, c1, c2, c3;
+                    if constexpr (MIXED) {
+                        const float4 c = *(const float4 *)(m.tr_fit32 + 4 * e);
+                        c0 = c.x; c1 = c.y; c2 = c.z; c3 = c.w;
+                    } else {
+                        const double2 a = *(const double2 *)(m.tr_fit + 4 * e);
+                        const double2 b = *(const double2 *)(m.tr_fit + 4 * e + 2);
+                        c0 = a.x; c1 = a.y; c2 = b.x; c3 = b.y;
+                    }
+                    const double invD = (double)exp_r<Rt>(-(c0 + L * (c1 + L * (c2 + L * c3))) - lp);
+                    const double xj = XSm[j * TT_RS], xk = XSm[k * TT_RS];
+                    atomicAdd(&ISm[k * TT_RS], xj * invD);
+                    atomicAdd(&ISm[j * TT_RS], xk * invD);
+                }
+            }
+        }
+        if (mu) {     // Wilke on the matrix cores
+            double num[4] = {0.0, 0.0, 0.0, 0.0};
+            const int ntiles = (ns + 15) / 16, ksteps = (ns + 3) / 4;
+            const int mrow = lane & 15, kin = lane >> 4;
+            for (int nt = wave; nt < ntiles; nt += W) {
+                const int kc = nt * 16 + (lane & 15);      // this lane's product column (species k)
+                typename MM::V d1 = {0, 0, 0, 0}, d2 = {0, 0, 0, 0}, d3 = {0, 0, 0, 0};
+                for (int ks = 0; ks < ksteps; ++ks) {
+                    const int j = ks * 4 + kin;
+                    Rt u1 = 0, bj = 0, c = 0;
+                    if (j < ns) {
+                        u1 = (Rt)XS[j * TT_RS + mrow];
+                        bj = BB[j * TT_RS + mrow];
+                        if (kc < ns) c = (Rt)m.wilke_c[(size_t)j * ns + kc];
+                    }
+                    const Rt u2 = u1 * bj, u3 = u2 * bj;
+                    d1 = MM::mma(u1, c, d1);
+                    d2 = MM::mma(u2, c, d2);
+                    d3 = MM::mma(u3, c, d3);
+                }
+                if (kc < ns) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int o = kc * TT_RS + MM::row(lane, r);
+                        const Rt a = AA[o];
+                        const Rt den = d1[r] + a * ((Rt)2 * d2[r] + a * d3[r]);
+                        num[r] += XS[o] * (double)MU[o] / (double)den;
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double s = row16_sum(num[r]);
+                if ((lane & 15) == 0) NUM[wave * TT_P + MM::row(lane, r)] = s;
+            }
+        }
+        __syncthreads();
+        {   // outputs
+            const int mm = tid % TT_P, g = tid / TT_P;
+            const int64_t i = i0 + mm;
+            if (i < n) {
+                double sx = 0.0, sxl = 0.0, sxil = 0.0;
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    const double *s = SUMS + 3 * (w * TT_P + mm);
+                    sx += s[0];
+                    sxl += s[1];
+                    sxil += s[2];
+                }
+                const double wbar = 1.0 / sx;
+                if (Dmix)
+                    for (int k = g; k < ns; k += NG)
+                        Dmix[(int64_t)k * ld + i] = (1.0 - Y[(int64_t)k * ld + i]) / (wbar * IS[k * TT_RS + mm]);
+                if (g == 0) {
+                    if (lam) lam[i] = 0.5 * (wbar * sxl + 1.0 / (wbar * sxil));
+                    if (mu) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int w = 0; w < W; ++w) s += NUM[w * TT_P + mm];
+                        mu[i] = s;
+                    }
+                }
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ reactor step (ROS2)
 // Constant-pressure adiabatic reactor, x = (T, Y), dx/dt = f(x) = (hrr/(rho c_p), W_k w_k/rho),
 // one two-stage Rosenbrock (ROS2) substep of size h:
@@ -2307,6 +2520,31 @@ hipError_t launch_reactor_static(const DevMech &m, int mixed, int64_t n, double 
 hipError_t launch_transport(const DevMech &m, int mixed, int64_t n, const double *T, const double *p,
                             int64_t ps, const double *Y, int64_t ld, double *mu, double *lam, double *Dmix,
                             hipStream_t st) {
+    // Point tiles while a tile's species rows fit one compute unit's LDS: 4 wavefronts per
+    // workgroup while four or more workgroups fit, else 8 (two or three) or 16 (one).
+    const int rows = m.ns + 1;
+    const int fit = (int)(CU_LDS_BYTES / tile_transport_lds(rows, mixed, 4));
+    const int W = fit >= 4 ? 4 : (fit >= 2 ? 8 : 16);
+    const size_t tshm = tile_transport_lds(rows, mixed, W);
+    if (tshm <= (size_t)CU_LDS_BYTES) {
+        const void *fn = nullptr;
+        if (W == 4) fn = mixed ? (const void *)k_transport_tile<true, 4> : (const void *)k_transport_tile<false, 4>;
+        else if (W == 8) fn = mixed ? (const void *)k_transport_tile<true, 8> : (const void *)k_transport_tile<false, 8>;
+        else fn = mixed ? (const void *)k_transport_tile<true, 16> : (const void *)k_transport_tile<false, 16>;
+        if (tshm > 64 * 1024) {
+            const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tshm);
+            if (e != hipSuccess) return e;
+        }
+        const int64_t tiles = (n + TT_P - 1) / TT_P;
+        const dim3 grid((unsigned)tiles), block(W * WAVE);
+#define CRF_TT_LAUNCH(MX, WW) hipLaunchKernelGGL((k_transport_tile<MX, WW>), grid, block, tshm, st, m, n, T, p, ps, Y, ld, mu, lam, Dmix, rows)
+        if (W == 4) { if (mixed) CRF_TT_LAUNCH(true, 4); else CRF_TT_LAUNCH(false, 4); }
+        else if (W == 8) { if (mixed) CRF_TT_LAUNCH(true, 8); else CRF_TT_LAUNCH(false, 8); }
+        else { if (mixed) CRF_TT_LAUNCH(true, 16); else CRF_TT_LAUNCH(false, 16); }
+#undef CRF_TT_LAUNCH
+        return hipGetLastError();
+    }
+    // larger mechanisms: two points per wavefront, per-point species arrays in LDS
     constexpr int PPW = 2;
     const int nsp = pad_odd(m.ns + 1);   // room for the dummy species of the pair schedule
     const void *fn = mixed ? (const void *)k_transport<true, PPW> : (const void *)k_transport<false, PPW>;

@@ -894,7 +894,7 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
            oLnA = P.add(h.lnA), oB = P.add(h.b), oTh = P.add(h.theta), oInfo = P.add(h.info),
            oDs = P.add(h.dnu_sum), oRi = P.add(h.ri), oTroe = P.add(h.troe), oEs = P.add(h.eff_sp),
            oEm = P.add(h.eff_m1), oJt = P.add(h.jp_thr), oJr = P.add(h.jp_recs), oJp = P.add(h.jp_prog), oJm = P.add(h.jp_mrx),
-           oTj = P.add(tr_jk), oTf = P.add(tr_fit), oRo = P.add(rxn_order), oVar = P.add(h.var),
+           oTj = P.add(tr_jk), oTf = P.add(tr_fit), oTf32 = P.add(std::vector<float>(tr_fit.begin(), tr_fit.end())), oRo = P.add(rxn_order), oVar = P.add(h.var),
            oVt = P.add(vtab);
     int prev = -1;
     if (hipGetDevice(&prev) != hipSuccess) return fail(CRF_E_DEVICE, "hipGetDevice failed (no HIP device?)");
@@ -913,7 +913,7 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
     m.W = (const double *)at(oW); m.invW = (const double *)at(oInvW); m.nasa = (const double *)at(oNasa);
     m.mu_fit = (const double *)at(oMu); m.lam_fit = (const double *)at(oLam); m.w4 = (const double *)at(oW4);
     m.iw4 = (const double *)at(oIw4); m.wilke_c = (const double *)at(oWc);
-    m.tr_jk = (const int *)at(oTj); m.tr_fit = (const double *)at(oTf);
+    m.tr_jk = (const int *)at(oTj); m.tr_fit = (const double *)at(oTf); m.tr_fit32 = (const float *)at(oTf32);
     m.tr_rounds = tr_rounds; m.tr_slots = tr_slots;
     m.lnA = (const double *)at(oLnA); m.b = (const double *)at(oB);
     m.theta = (const double *)at(oTh); m.info = (const int *)at(oInfo); m.rxn_order = (const int *)at(oRo); m.dnu_sum = (const int *)at(oDs);

@@ -313,8 +313,11 @@ def test_bitwise_reproducible(crf, mechs):
     b = crf.wdot(g, T, p, Y)[0].clone()
     Ja = crf.wdot_jac(g, T[:200], p[:200], Y[:200])[0].clone()
     Jb = crf.wdot_jac(g, T[:200], p[:200], Y[:200])[0].clone()
+    ta = [x.clone() for x in crf.transport(g, T, p, Y)]
+    tb = [x.clone() for x in crf.transport(g, T, p, Y)]
     torch.cuda.synchronize()
     assert torch.equal(a, b) and torch.equal(Ja, Jb)
+    assert all(torch.equal(x, y) for x, y in zip(ta, tb))
 
 
 def test_invalid_arguments_raise(crf, mechs):
@@ -325,6 +328,46 @@ def test_invalid_arguments_raise(crf, mechs):
         crf.wdot(g, T, p, Y.contiguous())                 # point-major layout is rejected
     with pytest.raises(ValueError):
         crf.wdot(g, T, p, Y, precision="bf16")
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_transport_ragged_tiles_and_partial_outputs(crf, mechs, prec, tol):
+    """Transport works on tiles of 16 points: point counts around the tile size, a padded
+    leading dimension, one pressure for all points, and each output requested alone."""
+    g, om = mechs["c1"]
+    dev = torch.device("cuda", 0)
+    st = state("c1", 77)
+    st["Y"][11, :] = 0.0
+    ref = oracle.transport_properties(om, st["T"], np.full(77, 3e5), st["Y"].T)
+    for n in (1, 15, 16, 17, 33, 77):
+        sub = {"T": st["T"][:n], "p": np.full(n, 3e5), "Y": np.ascontiguousarray(st["Y"][:, :n])}
+        T, _, Y = to_dev(sub, ld=n + 3)
+        log(f"transport ragged {prec} n={n}")
+        mu, lam, D = crf.transport(g, T, 3e5, Y, prec)
+        torch.cuda.synchronize()
+        assert np.max(np.abs(mu.cpu().numpy() / ref["mu"][:n] - 1)) <= tol
+        assert np.max(np.abs(lam.cpu().numpy() / ref["lambda"][:n] - 1)) <= tol
+        assert np.max(np.abs(D.cpu().numpy() / ref["Dmix"][:n] - 1)) <= tol
+    T, _, Y = to_dev({"T": st["T"], "p": st["p"], "Y": st["Y"]})
+    from paper_2409_06404_amd import _lib
+    import ctypes
+    L = _lib.lib()
+    out = torch.full((77,), -1.0, dtype=torch.float64, device=dev)
+    Dm = torch.full((53, 77), -1.0, dtype=torch.float64, device=dev)
+    P = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    pr = torch.full((77,), 3e5, dtype=torch.float64, device=dev)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    prec_id = 0 if prec == "fp64" else 1
+    for which in ("mu", "lambda", "Dmix"):
+        out.fill_(-1.0)
+        Dm.fill_(-1.0)
+        args = {"mu": None, "lambda": None, "Dmix": None}
+        args[which] = Dm if which == "Dmix" else out
+        _lib.check(L.crf_transport(g.handle, prec_id, 77, P(T), P(pr), 1, P(Y), Y.stride(1), P(args["mu"]),
+                                   P(args["lambda"]), P(args["Dmix"]), stream))
+        torch.cuda.synchronize()
+        got = (Dm.t() if which == "Dmix" else out).cpu().numpy()
+        assert np.max(np.abs(got / ref[which] - 1)) <= tol, which
 
 
 # ------------------------------------------------------------------ full sizes (sampled)
@@ -349,6 +392,24 @@ def test_full_size_wdot_sampled(crf, mechs, c1_full, prec, tol):
     log(f"  E_norm max {en[sig].max():.2e}")
     assert en[sig].max() <= tol
     assert torch.isfinite(w).all() and torch.isfinite(h).all()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_full_size_transport_sampled(crf, mechs, c1_full, prec, tol):
+    g, om = mechs["c1"]
+    T, p, Y = to_dev(c1_full)
+    log(f"full-size transport {prec} n=2^20")
+    mu, lam, D = crf.transport(g, T, p, Y, prec)
+    torch.cuda.synchronize()
+    idx = np.concatenate([np.random.default_rng(2).choice(1 << 20, size=400, replace=False), [0, (1 << 20) - 1]])
+    ref = oracle.transport_properties(om, c1_full["T"][idx], c1_full["p"][idx], c1_full["Y"][:, idx].T)
+    ii = torch.from_numpy(idx).cuda()
+    e = [np.max(np.abs(mu[ii].cpu().numpy() / ref["mu"] - 1)), np.max(np.abs(lam[ii].cpu().numpy() / ref["lambda"] - 1)),
+         np.max(np.abs(D[ii].cpu().numpy() / ref["Dmix"] - 1))]
+    log(f"  mu {e[0]:.2e} lambda {e[1]:.2e} Dmix {e[2]:.2e}")
+    assert max(e) <= tol
+    del mu, lam, D
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
