@@ -187,7 +187,7 @@ def c0_latency(crf, steps, stream):
 def supporting_c4(crf, stream, budget_gb=12.0):
     """The 200-species / 1500-reaction mechanism (300 third-body, 150 Troe) at 40 atm over
     its 8 launches of U{1000..8000} spectral elements of 8^3 points (the same element-count
-    draw as the parity state): production rates and VJP over whole launches in both modes,
+    draw as the parity state): production rates, transport and VJP over whole launches in both modes,
     and the mixed-mode Jacobian (201 x 201 FP32 per point) in chunks of whole elements
     that fit `budget_gb` GB, every chunk of every launch computed; aggregate rates."""
     import numpy as np
@@ -203,7 +203,8 @@ def supporting_c4(crf, stream, budget_gb=12.0):
         n1 = ns + 1
         chunk = int(budget_gb * 1e9 / (n1 * n1 * 4)) // 512 * 512
         J = torch.empty((chunk, n1, n1), dtype=torch.float32, device=dev)
-        tot = {"points": 0, "fp64": {"wdot": 0.0, "vjp": 0.0}, "mixed": {"wdot": 0.0, "vjp": 0.0, "jac": 0.0}}
+        tot = {"points": 0, "fp64": {"wdot": 0.0, "vjp": 0.0, "transport": 0.0},
+               "mixed": {"wdot": 0.0, "vjp": 0.0, "transport": 0.0, "jac": 0.0}}
         per_launch = []
         for li, E in enumerate(counts):
             T, p, Ysm = synth.state_c4_launch_device(ns, E, seed=4, launch=li, device="cuda")
@@ -213,7 +214,8 @@ def supporting_c4(crf, stream, budget_gb=12.0):
             rec = {"elements": E, "points": n}
             for prec in ("fp64", "mixed"):
                 for name, fn in (("wdot", lambda: crf.wdot(m, T, p, Y, prec, hrr=True)),
-                                 ("vjp", lambda: crf.wdot_vjp(m, T, p, Y, u, None, prec))):
+                                 ("vjp", lambda: crf.wdot_vjp(m, T, p, Y, u, None, prec)),
+                                 ("transport", lambda: crf.transport(m, T, p, Y, prec))):
                     ms = timed(fn, 1, 1 if li == 0 else 0, stream)
                     tot[prec][name] += ms
                     rec[f"{prec}_{name}_ms"] = ms
@@ -240,6 +242,66 @@ def supporting_c4(crf, stream, budget_gb=12.0):
             "jac_roofline": {"bound": "hbm", "bytes_per_point": jb,
                              "frac": agg["mixed"]["jac"] * 1e6 * jb / (HBM_PEAK_GBS * 1e9)},
             "per_launch": per_launch}
+
+
+def reactor_figures(crf, m, full, stream, n=1 << 14, nsub=4, dt=1e-6):
+    """crf_reactor_step on the first n points of the 2^20-point state (53 species): nsub ROS2
+    substeps of dt/nsub per call, each a fused w + Jacobian evaluation, the Newton matrix and
+    its LU factorisation per point, and the stage source terms; the state advances in place."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda", 0)
+    out = {"workload": f"53 species, {n} points, {nsub} ROS2 substeps of {dt / nsub:g} s per call", "points": n,
+           "substeps": nsub}
+    for prec in ("fp64", "mixed"):
+        T = torch.from_numpy(full["T"][:n].copy()).to(dev)
+        p = torch.from_numpy(full["p"][:n].copy()).to(dev)
+        Y = torch.from_numpy(np.ascontiguousarray(full["Y"][:, :n])).to(dev).t()
+        work = crf.reactor_workspace(m, n, prec)
+        ms = timed(lambda: crf.reactor_step(m, T, p, Y, dt, nsub, prec, work=work), 5, 1, stream)
+        out[prec] = {"ms_per_call": ms, "mpoint_substeps_per_s": n * nsub / (ms * 1e-3) / 1e6,
+                     "workspace_bytes": int(work.numel())}
+        del T, p, Y, work
+        torch.cuda.empty_cache()
+    return out
+
+
+def variant_figures(crf, stream, n=1 << 18, steps=5):
+    """The mechanism with every optional rate form (32 species; PLOG, Chebyshev, Lindemann,
+    SRI, explicit reverse, irreversible and forward-order reactions) on n points of the
+    9-species state's distributions with pressures over 0.05-60 atm: every per-point call."""
+    import numpy as np
+    import torch
+
+    import synth
+    dev = torch.device("cuda", 0)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "v.mech")
+        with open(path, "w") as fh:
+            fh.write(synth.mechanism_text(synth.generate_variant_mechanism()))
+        m = crf.Mechanism(path, device=0)
+        ns = m.n_species
+        st = synth.state_c0(ns, n=n, seed=7)
+        st["p"] = st["p"] * np.geomspace(0.05, 60.0, n)[np.random.default_rng(7).permutation(n)]
+        T = torch.from_numpy(st["T"]).to(dev)
+        p = torch.from_numpy(st["p"]).to(dev)
+        Y = torch.from_numpy(np.ascontiguousarray(st["Y"])).to(dev).t()
+        u = torch.randn((ns, n), dtype=torch.float64, device=dev).t()
+        out = {"workload": f"{ns} species / {m.n_reactions} reactions with every optional rate form, {n} points",
+               "jac_plan": m.jac_plan}
+        for prec in ("fp64", "mixed"):
+            J = torch.empty((n, ns + 1, ns + 1), dtype=torch.float64 if prec == "fp64" else torch.float32, device=dev)
+            calls = {"wdot": lambda: crf.wdot(m, T, p, Y, prec, hrr=True),
+                     "transport": lambda: crf.transport(m, T, p, Y, prec),
+                     "vjp": lambda: crf.wdot_vjp(m, T, p, Y, u, None, prec),
+                     "jvp": lambda: crf.wdot_jvp(m, T, p, Y, u, T, prec),
+                     "jac": lambda: crf.wdot_jac(m, T, p, Y, prec, out=J)}
+            out[prec] = {k: n / (timed(fn, steps, 1, stream) * 1e-3) / 1e6 for k, fn in calls.items()}
+            del J
+            torch.cuda.empty_cache()
+        m.close()
+    out["unit"] = "Mpoints/s"
+    return out
 
 
 def cpu_baseline(mech_path, st, n_sample):
@@ -335,7 +397,7 @@ def main():
                                       "bytes_per_point": bpp, "kernel": kname}}
             del J
             torch.cuda.empty_cache()
-        path, peaks, c0 = {}, None, None
+        path, peaks, c0, reactor, variants = {}, None, None, None, None
         if not args.no_path:
             peaks = measure_peaks(crf, stream)
             npath = args.path_points
@@ -349,9 +411,12 @@ def main():
             del Tf, pf, Yf, uf
             torch.cuda.empty_cache()
             c0 = c0_latency(crf, args.steps, stream)
+            reactor = reactor_figures(crf, m, full, stream)
+            variants = variant_figures(crf, stream)
         m.close()
         if args.no_jac:
-            print(json.dumps({"path": path, "peaks_measured": peaks, "c0": c0}), flush=True)
+            print(json.dumps({"path": path, "peaks_measured": peaks, "c0": c0, "reactor": reactor,
+                              "variants": variants}), flush=True)
             return
         head = "fp64" if "fp64" in res else precs[0]
         out = {
@@ -371,6 +436,8 @@ def main():
             out["peaks_measured"] = peaks
             out["path"] = path
             out["c0"] = c0
+            out["reactor"] = reactor
+            out["variants"] = variants
         if not (args.no_path or args.no_c4):
             out["c4"] = supporting_c4(crf, stream)
         if not args.no_cpu_baseline:
