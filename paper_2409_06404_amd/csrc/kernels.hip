@@ -2138,6 +2138,202 @@ __global__ __launch_bounds__(ROS_THREADS) void k_ros_finish(DevMech m, int64_t n
     }
 }
 
+// Wave-per-point forms of the two reactor kernels for N = Ns + 1 <= NM (NM = 16, 40 or 56): lane r
+// holds row r of the Newton matrix in registers, so the factorisation needs no barrier and
+// moves no rows.  Partial pivoting by selection: at step k the not yet selected row with the
+// largest |M_rk| (lowest lane on ties) is selected, its entries are broadcast through scalar
+// registers (readlane), and every other unselected row takes l = M_rk / M_pk and
+// M_rj -= l M_pj (the same operations as a factorisation with row exchanges).  Lane r keeps
+// its multipliers for the steps before its own selection step s_r and the U row of step s_r
+// after it; the factors and s_r go to the workspace for the second stage.  The solution of
+// step k's unknown (column k) is formed on the lane selected at step k.  Every loop over the
+// row is expanded at compile time (static_for), so that each element of the row array has a
+// constant index from the start and is kept in a register.
+template <int I, int E, class F>
+__device__ __attribute__((always_inline)) inline void static_for(F &&f) {
+    if constexpr (I < E) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, E>(f);
+    }
+}
+
+__device__ inline double lane_bcast(double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
+// The lane selected at step k (the step indices of the lanes are a permutation of 0..N-1).
+__device__ inline int lane_of_step(int step, int k) {
+    return __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(__ballot(step == k)));
+}
+
+// Solves with the factors held in a[] (see above): b is row r's right-hand side on entry,
+// and on return lane s^-1(k) holds unknown k.
+template <int NM>
+__device__ __attribute__((always_inline)) inline double ros_solve_w(const double (&a)[NM], int step, int N,
+                                                                   double b) {
+    static_for<0, NM>([&](auto kc) __attribute__((always_inline)) {   // forward: unit lower factor
+        constexpr int k = decltype(kc)::value;
+        if (k < N) {
+            const double yk = lane_bcast(b, lane_of_step(step, k));
+            if (step > k) b = fma(-a[k], yk, b);
+        }
+    });
+    static_for<0, NM>([&](auto ic) __attribute__((always_inline)) {   // backward: upper factor
+        constexpr int k = NM - 1 - decltype(ic)::value;
+        if (k < N) {
+            const int pv = lane_of_step(step, k);
+            const double xk = lane_bcast(b, pv) / lane_bcast(a[k], pv);
+            if (step == k) b = xk;
+            else if (step < k) b = fma(-a[k], xk, b);
+        }
+    });
+    return b;
+}
+
+template <bool JF32, int NM>
+__global__ __launch_bounds__(256) void k_ros_lu_w(DevMech m, int64_t n, const double *__restrict__ T,
+                                                  const double *__restrict__ p, int64_t ps,
+                                                  const double *__restrict__ Y, int64_t ld,
+                                                  const void *__restrict__ Jv, const double *__restrict__ wd,
+                                                  double h, double *__restrict__ Mbuf, int *__restrict__ stepg,
+                                                  double *__restrict__ k1g, double *__restrict__ Ts,
+                                                  double *__restrict__ Ys) {
+    using Jt = typename std::conditional<JF32, float, double>::type;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    if (i >= n) return;                    // whole wavefronts
+    const int ns = m.ns, N = ns + 1;
+    const double t = T[i], pp = p[i * ps], invT = 1.0 / t;
+    // mixture (lane c = 1 + species k): Wbar, rho, c_p, dc_p/dT, hrr = -R T sum_k (h_k/RT) w_k
+    const int k = lane - 1;
+    const bool sp = lane >= 1 && lane < N;
+    double yw = 0.0, cpy = 0.0, dcpy = 0.0, hw = 0.0, w = 0.0, cpw = 0.0;
+    if (sp) {
+        const double *c16 = m.nasa + 16 * k;
+        const double *ca = (t <= c16[0]) ? c16 + 1 : c16 + 8;
+        const double cpR = ca[0] + t * (ca[1] + t * (ca[2] + t * (ca[3] + t * ca[4])));
+        const double dcpR = ca[1] + t * (2.0 * ca[2] + t * (3.0 * ca[3] + t * 4.0 * ca[4]));
+        const double hRT = ca[0] + t * (ca[1] * 0.5 + t * (ca[2] * (1.0 / 3.0) + t * (ca[3] * 0.25 + t * (ca[4] * 0.2)))) +
+                           ca[5] * invT;
+        yw = Y[(int64_t)k * ld + i] * m.invW[k];
+        w = wd[(int64_t)k * n + i];
+        cpy = yw * cpR;
+        dcpy = yw * dcpR;
+        hw = hRT * w;
+        cpw = cpR * m.invW[k];
+    }
+    const double syw = wave_sum(yw), scp = wave_sum(cpy), sdcp = wave_sum(dcpy), shw = wave_sum(hw);
+    const double wbar = 1.0 / syw, rho = pp * wbar / (m.R * t);
+    const double cp = m.R * scp, hrr = -m.R * t * shw;
+    const double fT = hrr / (rho * cp);
+    // per column c (lane c): (d rho/dx_c)/rho and (d c_p/dx_c)/c_p; per row r (lane r): f_r,
+    // the row scale and w_r
+    double F = 0.0, DR = 0.0, DC = 0.0, RS = 0.0, WV = 0.0;
+    if (lane == 0) {
+        F = fT; DR = -invT; DC = sdcp / scp; RS = 1.0 / (rho * cp);
+    } else if (sp) {
+        F = m.W[k] * w / rho; DR = -wbar * m.invW[k]; DC = cpw / scp; RS = m.W[k] / rho; WV = w;
+    }
+    const double DRC = DR + DC;
+    // row `lane` of M = I - gamma h A (identity rows and columns beyond N)
+    const double gh = ROS_GAMMA * h;
+    const Jt *Jr = (const Jt *)Jv + (size_t)i * N * N + (size_t)(lane < N ? lane : 0) * N;
+    double a[NM];
+    static_for<0, NM>([&](auto cc) __attribute__((always_inline)) {
+        constexpr int c = decltype(cc)::value;
+        double v = lane == c ? 1.0 : 0.0;
+        if (c < N) {
+            const double dr = lane_bcast(DR, c), drc = lane_bcast(DRC, c);
+            if (lane < N) {
+                const double j = (double)Jr[c];
+                const double ar = lane == 0 ? RS * j - fT * drc : RS * (j - WV * dr);
+                v -= gh * ar;
+            }
+        }
+        a[c] = v;
+        if constexpr ((c & 7) == 7) __builtin_amdgcn_sched_barrier(0);   // bounds the loads in flight
+    });
+    // factorisation
+    int step = NM;
+    bool live = lane < N;
+    static_for<0, NM>([&](auto kc) __attribute__((always_inline)) {
+        constexpr int kk = decltype(kc)::value;
+        if (kk < N) {
+            double best = live ? fabs(a[kk]) : -1.0;
+            int bl = lane;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double ob = __shfl_xor(best, off);
+                const int ol = __shfl_xor(bl, off);
+                if (ob > best || (ob == best && ol < bl)) { best = ob; bl = ol; }
+            }
+            const int pv = __builtin_amdgcn_readfirstlane(bl);
+            const double inv = 1.0 / lane_bcast(a[kk], pv);
+            if (lane == pv) { step = kk; live = false; }
+            if (live) {   // the padding columns of real rows are zero, so they stay unchanged
+                const double l = a[kk] * inv;
+                a[kk] = l;
+                static_for<kk + 1, NM>([&](auto jc) __attribute__((always_inline)) {
+                    constexpr int j = decltype(jc)::value;
+                    a[j] = fma(-l, lane_bcast(a[j], pv), a[j]);
+                });
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);   // one step at a time: bounds the live registers
+    });
+    // stage 1: k1 = M^-1 f; the lane selected at step c holds component c
+    const double x = ros_solve_w<NM>(a, step, N, F);
+    if (lane < N) {
+        const int c = step;
+        k1g[(size_t)i * N + c] = x;
+        if (c == 0) Ts[i] = t + h * x;
+        else Ys[(int64_t)(c - 1) * n + i] = Y[(int64_t)(c - 1) * ld + i] + h * x;
+        double *Mr = Mbuf + (size_t)i * N * N + (size_t)lane * N;
+        static_for<0, NM>([&](auto cc) __attribute__((always_inline)) {
+            constexpr int c2 = decltype(cc)::value;
+            if (c2 < N) Mr[c2] = a[c2];
+        });
+        stepg[(size_t)i * N + lane] = step;
+    }
+}
+
+// Second stage, wave per point: k2 = M^-1 (f(x_s) - 2 k1), x <- x + 3/2 h k1 + 1/2 h k2.
+template <int NM>
+__global__ __launch_bounds__(256) void k_ros_finish_w(DevMech m, int64_t n, double *__restrict__ T,
+                                                      double *__restrict__ Y, int64_t ld,
+                                                      const double *__restrict__ Mbuf,
+                                                      const int *__restrict__ stepg,
+                                                      const double *__restrict__ k1g,
+                                                      const double *__restrict__ fTs,
+                                                      const double *__restrict__ fYs, double h) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    if (i >= n) return;
+    const int N = m.ns + 1;
+    double a[NM];
+    int step = NM;
+    double b = 0.0;
+    const double *Mr = Mbuf + (size_t)i * N * N + (size_t)(lane < N ? lane : 0) * N;
+    static_for<0, NM>([&](auto cc) __attribute__((always_inline)) {
+        constexpr int c = decltype(cc)::value;
+        a[c] = (c < N && lane < N) ? Mr[c] : 0.0;
+    });
+    if (lane < N) {
+        step = stepg[(size_t)i * N + lane];
+        const double f = lane == 0 ? fTs[i] : fYs[(int64_t)(lane - 1) * n + i];
+        b = f - 2.0 * k1g[(size_t)i * N + lane];
+    }
+    const double x = ros_solve_w<NM>(a, step, N, b);
+    if (lane < N) {
+        const int c = step;
+        const double dx = 1.5 * h * k1g[(size_t)i * N + c] + 0.5 * h * x;
+        if (c == 0) T[i] += dx;
+        else Y[(int64_t)(c - 1) * ld + i] += dx;
+    }
+}
+
 // ------------------------------------------------------------------ peak-rate probes
 // Throughput probes for the roofline denominators: every thread runs 8 independent
 // chains of `iters` operations of one kind (0: exp_fast (FP64), 1: exp of the device
@@ -2462,9 +2658,35 @@ hipError_t launch_reactor(const DevMech &m, int mixed, int64_t n, double *T, con
     const dim3 grid(grid_for(n, 1, 8)), block(ROS_THREADS);
     const size_t fshm = (size_t)N * sizeof(double) + (size_t)N * sizeof(int);
     const double h = dt / nsub;
+    // up to 56 unknowns: a wavefront per point with the matrix in registers
+    const dim3 wgrid((unsigned)((n + 3) / 4)), wblock(4 * WAVE);
     for (int s = 0; s < nsub; ++s) {
         e = launch_jac(m, mixed, n, Tw, p, ps, Yw, n, Jb, wd, st);
         if (e != hipSuccess) return e;
+        if (N <= 56) {
+#define CRF_ROS_W(NMX)                                                                                              \
+    do {                                                                                                            \
+        if (mixed)                                                                                                  \
+            hipLaunchKernelGGL((k_ros_lu_w<true, NMX>), wgrid, wblock, 0, st, m, n, Tw, p, ps, Yw, (int64_t)n, Jb, wd, \
+                               h, Mb, piv, k1, Ts, Ys);                                                             \
+        else                                                                                                        \
+            hipLaunchKernelGGL((k_ros_lu_w<false, NMX>), wgrid, wblock, 0, st, m, n, Tw, p, ps, Yw, (int64_t)n, Jb,    \
+                               wd, h, Mb, piv, k1, Ts, Ys);                                                         \
+        e = hipGetLastError();                                                                                      \
+        if (e != hipSuccess) return e;                                                                              \
+        e = launch_source(m, mixed, n, Ts, p, ps, Ys, n, 0.0, fY, fT, nullptr, nullptr, st);                        \
+        if (e != hipSuccess) return e;                                                                              \
+        hipLaunchKernelGGL((k_ros_finish_w<NMX>), wgrid, wblock, 0, st, m, n, Tw, Yw, (int64_t)n, Mb, piv, k1, fT,    \
+                           fY, h);                                                                                  \
+    } while (0)
+            if (N <= 16) CRF_ROS_W(16);
+            else if (N <= 40) CRF_ROS_W(40);
+            else CRF_ROS_W(56);
+#undef CRF_ROS_W
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            continue;
+        }
         if (mixed)
             hipLaunchKernelGGL((k_ros_lu<true>), grid, block, shm, st, m, n, Tw, p, ps, Yw, (int64_t)n, Jb, wd, h, Mb,
                                piv, k1, Ts, Ys, in_lds);
