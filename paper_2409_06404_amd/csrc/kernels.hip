@@ -63,6 +63,20 @@ __device__ inline double wave_sum(double v) {
     return __hiloint2double(hi, lo);
 }
 
+// Largest value over the 64 lanes (IEEE maxNum: NaN entries are passed over), in every
+// lane; the same DPP pattern as wave_sum, so the reduction stays in the VALU.
+__device__ inline double wave_max(double v) {
+    v = fmax(v, dpp_f64<0x111, 0xf>(v));
+    v = fmax(v, dpp_f64<0x112, 0xf>(v));
+    v = fmax(v, dpp_f64<0x114, 0xf>(v));
+    v = fmax(v, dpp_f64<0x118, 0xf>(v));
+    v = fmax(v, dpp_f64<0x142, 0xa>(v));
+    v = fmax(v, dpp_f64<0x143, 0xc>(v));
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
 // Makes LDS writes of all lanes of this wave visible to all its lanes.
 __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -2145,7 +2159,8 @@ __global__ __launch_bounds__(ROS_THREADS) void k_ros_finish(DevMech m, int64_t n
 // registers (readlane), and every other unselected row takes l = M_rk / M_pk and
 // M_rj -= l M_pj (the same operations as a factorisation with row exchanges).  Lane r keeps
 // its multipliers for the steps before its own selection step s_r and the U row of step s_r
-// after it; the factors and s_r go to the workspace for the second stage.  The solution of
+// after it (with 1/U_kk stored on the diagonal); the factors and s_r go to the workspace for
+// the second stage.  The solution of
 // step k's unknown (column k) is formed on the lane selected at step k.  Every loop over the
 // row is expanded at compile time (static_for), so that each element of the row array has a
 // constant index from the start and is kept in a register.
@@ -2184,7 +2199,7 @@ __device__ __attribute__((always_inline)) inline double ros_solve_w(const double
         constexpr int k = NM - 1 - decltype(ic)::value;
         if (k < N) {
             const int pv = lane_of_step(step, k);
-            const double xk = lane_bcast(b, pv) / lane_bcast(a[k], pv);
+            const double xk = lane_bcast(b, pv) * lane_bcast(a[k], pv);   // 1/U_kk is stored
             if (step == k) b = xk;
             else if (step < k) b = fma(-a[k], xk, b);
         }
@@ -2196,8 +2211,8 @@ template <bool JF32, int NM>
 __global__ __launch_bounds__(256) void k_ros_lu_w(DevMech m, int64_t n, const double *__restrict__ T,
                                                   const double *__restrict__ p, int64_t ps,
                                                   const double *__restrict__ Y, int64_t ld,
-                                                  const void *__restrict__ Jv, const double *__restrict__ wd,
-                                                  double h, double *__restrict__ Mbuf, int *__restrict__ stepg,
+                                                  const void *Jv, const double *__restrict__ wd,
+                                                  double h, double *Mbuf, int *__restrict__ stepg,
                                                   double *__restrict__ k1g, double *__restrict__ Ts,
                                                   double *__restrict__ Ys) {
     using Jt = typename std::conditional<JF32, float, double>::type;
@@ -2261,17 +2276,19 @@ __global__ __launch_bounds__(256) void k_ros_lu_w(DevMech m, int64_t n, const do
     static_for<0, NM>([&](auto kc) __attribute__((always_inline)) {
         constexpr int kk = decltype(kc)::value;
         if (kk < N) {
-            double best = live ? fabs(a[kk]) : -1.0;
-            int bl = lane;
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                const double ob = __shfl_xor(best, off);
-                const int ol = __shfl_xor(bl, off);
-                if (ob > best || (ob == best && ol < bl)) { best = ob; bl = ol; }
-            }
-            const int pv = __builtin_amdgcn_readfirstlane(bl);
+            // pivot: the largest |M_rk| (DPP reduction), the lowest such lane (ballot); a column
+            // of NaNs selects the lowest unselected lane
+            const double key = live ? fabs(a[kk]) : -1.0;
+            const double mx = wave_max(key);
+            unsigned long long sel = __ballot(live && key == mx);
+            if (sel == 0) sel = __ballot(live);
+            const int pv = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(sel));
             const double inv = 1.0 / lane_bcast(a[kk], pv);
-            if (lane == pv) { step = kk; live = false; }
+            if (lane == pv) {   // the selected row keeps 1/U_kk in place of U_kk
+                step = kk;
+                live = false;
+                a[kk] = inv;
+            }
             if (live) {   // the padding columns of real rows are zero, so they stay unchanged
                 const double l = a[kk] * inv;
                 a[kk] = l;
@@ -2290,10 +2307,12 @@ __global__ __launch_bounds__(256) void k_ros_lu_w(DevMech m, int64_t n, const do
         k1g[(size_t)i * N + c] = x;
         if (c == 0) Ts[i] = t + h * x;
         else Ys[(int64_t)(c - 1) * n + i] = Y[(int64_t)(c - 1) * ld + i] + h * x;
-        double *Mr = Mbuf + (size_t)i * N * N + (size_t)lane * N;
+        // column-major (lane-contiguous) factors; in FP64 Mbuf is the Jacobian's storage, whose
+        // rows this wavefront read above
+        double *Mc = Mbuf + (size_t)i * N * N + lane;
         static_for<0, NM>([&](auto cc) __attribute__((always_inline)) {
             constexpr int c2 = decltype(cc)::value;
-            if (c2 < N) Mr[c2] = a[c2];
+            if (c2 < N) Mc[(size_t)c2 * N] = a[c2];
         });
         stepg[(size_t)i * N + lane] = step;
     }
@@ -2315,10 +2334,10 @@ __global__ __launch_bounds__(256) void k_ros_finish_w(DevMech m, int64_t n, doub
     double a[NM];
     int step = NM;
     double b = 0.0;
-    const double *Mr = Mbuf + (size_t)i * N * N + (size_t)(lane < N ? lane : 0) * N;
+    const double *Mc = Mbuf + (size_t)i * N * N + (lane < N ? lane : 0);   // column-major factors
     static_for<0, NM>([&](auto cc) __attribute__((always_inline)) {
         constexpr int c = decltype(cc)::value;
-        a[c] = (c < N && lane < N) ? Mr[c] : 0.0;
+        a[c] = (c < N && lane < N) ? Mc[(size_t)c * N] : 0.0;
     });
     if (lane < N) {
         step = stepg[(size_t)i * N + lane];
