@@ -79,6 +79,8 @@ struct DevMech {
     // perfect matching of the species (plus the dummy species ns when ns is odd), tr_slots
     // pairs per round
     const int *tr_jk;         // [round][slot]: j | k << 16
+    const unsigned *tr_off;   // [round][slot]: the pair's byte offsets in a point tile's species rows,
+                              // 8 TT_RS j | 8 TT_RS k << 16 (transport on point tiles)
     const double *tr_fit;     // [round][slot][4]: the pair's ln D fit (zeros for the dummy pair)
     const float *tr_fit32;    // the same fits rounded to FP32 (the mixed mode)
     int tr_rounds, tr_slots;
@@ -238,6 +240,11 @@ inline RosLayout ros_layout(int ns, int mixed, int64_t n) {
     return L;
 }
 inline size_t reactor_work_bytes(int ns, int mixed, int64_t n) { return n > 0 ? ros_layout(ns, mixed, n).total : 0; }
+
+// Transport on point tiles: points per tile, and the row stride (doubles, odd) of its
+// [species][point] arrays in LDS.
+constexpr int TT_P = 16;
+constexpr int TT_RS = 17;
 
 // Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_thermo(const DevMech &m, int64_t n, const double *T, const double *p, int64_t ps,

@@ -1748,8 +1748,40 @@ __global__ __launch_bounds__(256) void k_transport(DevMech m, int64_t n, const d
 //     three [16 x Ns] x [Ns x Ns] products on the matrix cores (16x16x4 MFMA, FP64, or FP32
 //     in the mixed mode), tiles of 16 species columns dealt to the wavefronts, C = wilke_c
 //     read from L2 once per tile of points.  mu = sum_k Xs_k mu_k / den~_k (Wbar cancels).
-constexpr int TT_P = 16;
-constexpr int TT_RS = 17;
+// 2^(j/64), j = 0..63, each the double nearest to its exact value.
+__constant__ double EXP2_J64[64] = {
+    0x1.0000000000000p+0, 0x1.02c9a3e778061p+0, 0x1.059b0d3158574p+0, 0x1.0874518759bc8p+0,
+    0x1.0b5586cf9890fp+0, 0x1.0e3ec32d3d1a2p+0, 0x1.11301d0125b51p+0, 0x1.1429aaea92de0p+0,
+    0x1.172b83c7d517bp+0, 0x1.1a35beb6fcb75p+0, 0x1.1d4873168b9aap+0, 0x1.2063b88628cd6p+0,
+    0x1.2387a6e756238p+0, 0x1.26b4565e27cddp+0, 0x1.29e9df51fdee1p+0, 0x1.2d285a6e4030bp+0,
+    0x1.306fe0a31b715p+0, 0x1.33c08b26416ffp+0, 0x1.371a7373aa9cbp+0, 0x1.3a7db34e59ff7p+0,
+    0x1.3dea64c123422p+0, 0x1.4160a21f72e2ap+0, 0x1.44e086061892dp+0, 0x1.486a2b5c13cd0p+0,
+    0x1.4bfdad5362a27p+0, 0x1.4f9b2769d2ca7p+0, 0x1.5342b569d4f82p+0, 0x1.56f4736b527dap+0,
+    0x1.5ab07dd485429p+0, 0x1.5e76f15ad2148p+0, 0x1.6247eb03a5585p+0, 0x1.6623882552225p+0,
+    0x1.6a09e667f3bcdp+0, 0x1.6dfb23c651a2fp+0, 0x1.71f75e8ec5f74p+0, 0x1.75feb564267c9p+0,
+    0x1.7a11473eb0187p+0, 0x1.7e2f336cf4e62p+0, 0x1.82589994cce13p+0, 0x1.868d99b4492edp+0,
+    0x1.8ace5422aa0dbp+0, 0x1.8f1ae99157736p+0, 0x1.93737b0cdc5e5p+0, 0x1.97d829fde4e50p+0,
+    0x1.9c49182a3f090p+0, 0x1.a0c667b5de565p+0, 0x1.a5503b23e255dp+0, 0x1.a9e6b5579fdbfp+0,
+    0x1.ae89f995ad3adp+0, 0x1.b33a2b84f15fbp+0, 0x1.b7f76f2fb5e47p+0, 0x1.bcc1e904bc1d2p+0,
+    0x1.c199bdd85529cp+0, 0x1.c67f12e57d14bp+0, 0x1.cb720dcef9069p+0, 0x1.d072d4a07897cp+0,
+    0x1.d5818dcfba487p+0, 0x1.da9e603db3285p+0, 0x1.dfc97337b9b5fp+0, 0x1.e502ee78b3ff6p+0,
+    0x1.ea4afa2a490dap+0, 0x1.efa1bee615a27p+0, 0x1.f50765b6e4540p+0, 0x1.fa7c1819e90d8p+0
+};
+
+// e^x in FP64 by the table-driven method of Tang (ACM TOMS 15, 1989): x = (64 m + j) ln2/64 + r,
+// |r| <= ln2/128 (ln2/64 split as in exp_fast, so kf ln2_hi/64 is exact), then
+// e^x = 2^m 2^(j/64) e^r with e^r from its degree-5 Taylor polynomial (truncation below 4e-17
+// relative) and 2^(j/64) from `tab` (EXP2_J64 staged in LDS).  About 1.5 ulp; fewer
+// instructions than exp_fast, whose eleven polynomial coefficients the fused multiply-adds
+// consume one register copy each.
+__device__ inline double exp_tab(double x, const double *tab) {
+    const double kf = fmin(fmax(rint(x * 92.332482616893657), -140000.0), 140000.0);
+    double r = fma(-kf, 6.93147180369123816490e-01 / 64.0, x);
+    r = fma(-kf, 1.90821492927058770002e-10 / 64.0, r);
+    const int k = (int)kf;
+    const double q = fma(r, fma(r, fma(r, fma(r, fma(r, 1.0 / 120.0, 1.0 / 24.0), 1.0 / 6.0), 0.5), 1.0), 1.0);
+    return ldexp(tab[k & 63] * q, k >> 6);
+}
 
 template <bool MIXED> struct TileMfma;
 template <> struct TileMfma<false> {
@@ -1775,7 +1807,7 @@ __device__ inline double row16_sum(double v) {
 // schedule) and W wavefronts.
 inline size_t tile_transport_lds(int rows, bool mixed, int W) {
     return (size_t)rows * TT_RS * (2 * sizeof(double) + 3 * (mixed ? sizeof(float) : sizeof(double))) +
-           (size_t)(2 * TT_P + 4 * W * TT_P) * sizeof(double);
+           (size_t)(64 + 2 * TT_P + 4 * W * TT_P) * sizeof(double);
 }
 
 template <bool MIXED, int W>
@@ -1793,13 +1825,15 @@ __global__ __launch_bounds__(W * WAVE) __attribute__((amdgpu_waves_per_eu(4))) v
     extern __shared__ double lds[];
     double *XS = lds;                            // [rows][TT_RS]
     double *IS = XS + rows * TT_RS;              // [rows][TT_RS]
-    double *PT = IS + rows * TT_RS;              // lnT[16], ln(p0/p)[16], sums[W][16][3], num[W][16]
+    double *E2 = IS + rows * TT_RS;              // 2^(j/64) for exp_tab
+    double *PT = E2 + 64;                        // lnT[16], ln(p0/p)[16], sums[W][16][3], num[W][16]
     double *SUMS = PT + 2 * TT_P, *NUM = SUMS + 3 * W * TT_P;
     Rt *BB = (Rt *)(NUM + W * TT_P);             // [rows][TT_RS]
     Rt *AA = BB + rows * TT_RS;                  // [rows][TT_RS]
     Rt *MU = AA + rows * TT_RS;                  // [rows][TT_RS]
     const int tid = threadIdx.x, wave = tid / WAVE, lane = tid & (WAVE - 1);
     const int ns = m.ns;
+    if (!MIXED && tid < 64) E2[tid] = EXP2_J64[tid];
     {
         const int64_t i0 = (int64_t)blockIdx.x * TT_P;
         {   // setup
@@ -1851,28 +1885,49 @@ __global__ __launch_bounds__(W * WAVE) __attribute__((amdgpu_waves_per_eu(4))) v
         if (Dmix) {   // binary diffusion sums of the wavefront's own points
             const int q = lane % PW, sg = lane / PW, mm = wave * PW + q;
             const Rt L = (Rt)PT[mm], lp = (Rt)PT[TT_P + mm];
-            double *ISm = IS + mm;
-            const double *XSm = XS + mm;
-            const int slots = m.tr_slots;
-            for (int r = 0; r < m.tr_rounds; ++r) {
-                const int e0 = r * slots;
-                for (int s = sg; s < slots; s += G) {
-                    const int e = e0 + s;
-                    const int jk = m.tr_jk[e];
-                    const int j = jk & 0xffff, k = jk >> 16;
-                    Rt c0, c1, c2, c3;
-                    if constexpr (MIXED) {
-                        const float4 c = *(const float4 *)(m.tr_fit32 + 4 * e);
-                        c0 = c.x; c1 = c.y; c2 = c.z; c3 = c.w;
-                    } else {
-                        const double2 a = *(const double2 *)(m.tr_fit + 4 * e);
-                        const double2 b = *(const double2 *)(m.tr_fit + 4 * e + 2);
-                        c0 = a.x; c1 = a.y; c2 = b.x; c3 = b.y;
-                    }
-                    const double invD = (double)exp_r<Rt>(-(c0 + L * (c1 + L * (c2 + L * c3))) - lp);
-                    const double xj = XSm[j * TT_RS], xk = XSm[k * TT_RS];
-                    atomicAdd(&ISm[k * TT_RS], xj * invD);
-                    atomicAdd(&ISm[j * TT_RS], xk * invD);
+            // byte addresses of this point's column in the species rows (pair offsets add to them)
+            const unsigned xs_b = (unsigned)((const char *)(XS + mm) - (const char *)lds);
+            const unsigned is_b = (unsigned)((const char *)(IS + mm) - (const char *)lds);
+            const int slots = m.tr_slots, passes = (slots + G - 1) / G, total = m.tr_rounds * passes;
+            // one pass = G pairs of one round (lanes past the round's end idle); the next pass's
+            // pair offsets and fit coefficients are loaded while this pass computes
+            int r = 0, t = 0;
+            bool ok_n = sg < slots;
+            int e_n = ok_n ? sg : 0;
+            unsigned off_n = m.tr_off[e_n];
+            Rt cn[4];
+            auto load_fit = [&](int e) {
+                if constexpr (MIXED) {
+                    const float4 c = *(const float4 *)(m.tr_fit32 + 4 * e);
+                    cn[0] = c.x; cn[1] = c.y; cn[2] = c.z; cn[3] = c.w;
+                } else {
+                    const double2 a = *(const double2 *)(m.tr_fit + 4 * e);
+                    const double2 b = *(const double2 *)(m.tr_fit + 4 * e + 2);
+                    cn[0] = a.x; cn[1] = a.y; cn[2] = b.x; cn[3] = b.y;
+                }
+            };
+            load_fit(e_n);
+            for (int it = 0; it < total; ++it) {
+                const bool ok = ok_n;
+                const unsigned off = off_n;
+                const Rt c0 = cn[0], c1 = cn[1], c2 = cn[2], c3 = cn[3];
+                if (++t == passes) { t = 0; ++r; }
+                if (it + 1 < total) {
+                    const int s = sg + t * G;
+                    ok_n = s < slots;
+                    e_n = r * slots + (ok_n ? s : 0);
+                    off_n = m.tr_off[e_n];
+                    load_fit(e_n);
+                }
+                if (ok) {
+                    const unsigned oj = off & 0xffffu, ok16 = off >> 16;
+                    const Rt arg = -(c0 + L * (c1 + L * (c2 + L * c3))) - lp;
+                    double invD;
+                    if constexpr (MIXED) invD = (double)exp_r<Rt>(arg);
+                    else invD = exp_tab(arg, E2);
+                    const double xj = lds_ld(xs_b + oj), xk = lds_ld(xs_b + ok16);
+                    atomicAdd((double *)((char *)lds + is_b + ok16), xj * invD);
+                    atomicAdd((double *)((char *)lds + is_b + oj), xk * invD);
                 }
             }
         }
@@ -1883,14 +1938,20 @@ __global__ __launch_bounds__(W * WAVE) __attribute__((amdgpu_waves_per_eu(4))) v
             for (int nt = wave; nt < ntiles; nt += W) {
                 const int kc = nt * 16 + (lane & 15);      // this lane's product column (species k)
                 typename MM::V d1 = {0, 0, 0, 0}, d2 = {0, 0, 0, 0}, d3 = {0, 0, 0, 0};
-                for (int ks = 0; ks < ksteps; ++ks) {
+                Rt u1n = 0, bjn = 0, cn = 0;     // operands of the next K step, loaded a step ahead
+                auto load_k = [&](int ks) {
                     const int j = ks * 4 + kin;
-                    Rt u1 = 0, bj = 0, c = 0;
+                    u1n = 0; bjn = 0; cn = 0;
                     if (j < ns) {
-                        u1 = (Rt)XS[j * TT_RS + mrow];
-                        bj = BB[j * TT_RS + mrow];
-                        if (kc < ns) c = (Rt)m.wilke_c[(size_t)j * ns + kc];
+                        u1n = (Rt)XS[j * TT_RS + mrow];
+                        bjn = BB[j * TT_RS + mrow];
+                        if (kc < ns) cn = (Rt)m.wilke_c[(size_t)j * ns + kc];
                     }
+                };
+                load_k(0);
+                for (int ks = 0; ks < ksteps; ++ks) {
+                    const Rt u1 = u1n, bj = bjn, c = cn;
+                    if (ks + 1 < ksteps) load_k(ks + 1);
                     const Rt u2 = u1 * bj, u3 = u2 * bj;
                     d1 = MM::mma(u1, c, d1);
                     d2 = MM::mma(u2, c, d2);

@@ -866,6 +866,7 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
     // positions of a circle of n2 (even) entries, fixed entry 0, the others rotated
     const int n2 = ns + (ns & 1), tr_slots = n2 / 2, tr_rounds = n2 - 1;
     std::vector<int> tr_jk;
+    std::vector<unsigned> tr_off;
     std::vector<double> tr_fit;
     for (int r = 0; r < tr_rounds; ++r) {
         std::vector<int> circ(n2);
@@ -875,6 +876,7 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
             int j = circ[q], k = circ[n2 - 1 - q];
             if (j > k) std::swap(j, k);
             tr_jk.push_back(j | k << 16);
+            tr_off.push_back((unsigned)(8 * TT_RS * j) | (unsigned)(8 * TT_RS * k) << 16);
             for (int c = 0; c < 4; ++c) tr_fit.push_back(k < ns ? h.dif_full[((size_t)j * ns + k) * 4 + c] : 0.0);
         }
     }
@@ -894,7 +896,7 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
            oLnA = P.add(h.lnA), oB = P.add(h.b), oTh = P.add(h.theta), oInfo = P.add(h.info),
            oDs = P.add(h.dnu_sum), oRi = P.add(h.ri), oTroe = P.add(h.troe), oEs = P.add(h.eff_sp),
            oEm = P.add(h.eff_m1), oJt = P.add(h.jp_thr), oJr = P.add(h.jp_recs), oJp = P.add(h.jp_prog), oJm = P.add(h.jp_mrx),
-           oTj = P.add(tr_jk), oTf = P.add(tr_fit), oTf32 = P.add(std::vector<float>(tr_fit.begin(), tr_fit.end())), oRo = P.add(rxn_order), oVar = P.add(h.var),
+           oTj = P.add(tr_jk), oTo = P.add(tr_off), oTf = P.add(tr_fit), oTf32 = P.add(std::vector<float>(tr_fit.begin(), tr_fit.end())), oRo = P.add(rxn_order), oVar = P.add(h.var),
            oVt = P.add(vtab);
     int prev = -1;
     if (hipGetDevice(&prev) != hipSuccess) return fail(CRF_E_DEVICE, "hipGetDevice failed (no HIP device?)");
@@ -913,7 +915,7 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
     m.W = (const double *)at(oW); m.invW = (const double *)at(oInvW); m.nasa = (const double *)at(oNasa);
     m.mu_fit = (const double *)at(oMu); m.lam_fit = (const double *)at(oLam); m.w4 = (const double *)at(oW4);
     m.iw4 = (const double *)at(oIw4); m.wilke_c = (const double *)at(oWc);
-    m.tr_jk = (const int *)at(oTj); m.tr_fit = (const double *)at(oTf); m.tr_fit32 = (const float *)at(oTf32);
+    m.tr_jk = (const int *)at(oTj); m.tr_off = (const unsigned *)at(oTo); m.tr_fit = (const double *)at(oTf); m.tr_fit32 = (const float *)at(oTf32);
     m.tr_rounds = tr_rounds; m.tr_slots = tr_slots;
     m.lnA = (const double *)at(oLnA); m.b = (const double *)at(oB);
     m.theta = (const double *)at(oTh); m.info = (const int *)at(oInfo); m.rxn_order = (const int *)at(oRo); m.dnu_sum = (const int *)at(oDs);
