@@ -1329,9 +1329,8 @@ __device__ inline void jac_seg_state(int ns, double R, double lnp0R, int wave, i
         // both ranges' coefficients are requested at once, then one is selected
         double c15[15];
         if (lane < ns) {
-            const double *c16 = NS + 16 * lane;
 #pragma unroll
-            for (int q = 0; q < 15; ++q) c15[q] = c16[q];
+            for (int q = 0; q < 15; ++q) c15[q] = NS[q * ns + lane];   // coefficient-major: no bank conflicts
         }
         const double lnT = log(Tt), invT = 1.0 / Tt;
         if (lane < ns) {
@@ -1400,7 +1399,7 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
         EXm[e] = m.eff_m1[e];
         EXs[e] = m.eff_sp[e];
     }
-    for (int e = tid; e < 16 * ns; e += JS_THREADS) NS[e] = m.nasa[e];
+    for (int e = tid; e < 16 * ns; e += JS_THREADS) NS[(e & 15) * ns + (e >> 4)] = m.nasa[e];   // [q][k]
     for (int e = tid; e < ns; e += JS_THREADS) IW[e] = m.invW[e];
     for (int e = tid; e < 2 * n_m; e += JS_THREADS) MX[e] = m.jp_mrx[e];
     const double lnp0R = log(m.p0 / m.R);
