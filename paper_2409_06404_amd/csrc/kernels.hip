@@ -1136,8 +1136,9 @@ __global__ __launch_bounds__(KR_WAVES * 64) void k_jac_rt(DevMech m, int64_t n, 
 template <bool MIXED>
 __device__ inline void jac_seg_reaction(int r, unsigned sp03, unsigned sp45, int dpos, int xpos, int n_exc,
                                         int exc0, int troe, int dnu, double lnA, double bb, double th,
-                                        const double *SP, const double *SC, const double *TQ, const double *MQ,
-                                        const double *EXm, typename GatherT<MIXED>::type *RDd, int qb) {
+                                        const double *SP, const double *SC, const double *TQ, int nt,
+                                        const double *MQ, const double *EXm, typename GatherT<MIXED>::type *RDd,
+                                        int qb) {
     using Rt = typename std::conditional<MIXED, float, double>::type;
     const int nfm = (sp45 >> 16) & 7, nrm = (sp45 >> 19) & 7, kind = (sp45 >> 22) & 3;
     const double lnT = SC[5], invT = SC[6], lnp0RT = SC[7];
@@ -1157,8 +1158,8 @@ __device__ inline void jac_seg_reaction(int r, unsigned sp03, unsigned sp45, int
     const Rt dlnkinf = ((Rt)bb + (Rt)th * rinvT) * rinvT;
     Rt kf = kinf, dkf_dT = kinf * dlnkinf, dkf_dM = 0;
     if (kind == RXN_TROE) {
-        const double *tq = TQ + JS_TQ * troe;
-        const Rt lFc = (Rt)tq[0], dlFc = (Rt)tq[1], lnkr = (Rt)tq[2], dlnPr = (Rt)tq[3], k0 = (Rt)tq[4];
+        const double *tq = TQ + troe;   // [term][falloff reaction]
+        const Rt lFc = (Rt)tq[0], dlFc = (Rt)tq[nt], lnkr = (Rt)tq[2 * nt], dlnPr = (Rt)tq[3 * nt], k0 = (Rt)tq[4 * nt];
         const Rt lnPr = lnkr + (Rt)lnMd;
         const Rt Pr = exp_r<Rt>(lnPr);
         const Rt cc = (Rt)-0.4 - (Rt)0.67 * lFc;
@@ -1234,16 +1235,16 @@ template <bool MIXED>
 __device__ inline void jac_seg_troe_fc(int lane, int n_troe, double Tt, const double *TP, double *TQ) {
     using Rt = typename std::conditional<MIXED, float, double>::type;
     for (int j = lane; j < n_troe; j += WAVE) {
-        const double *tp = TP + JS_TP * j;
+        const double *tp = TP + j;      // [constant][falloff reaction]: lanes read adjacent words
         const Rt T = (Rt)Tt, invT = (Rt)1 / T;
-        const Rt alpha = (Rt)tp[3], iT3 = (Rt)tp[4], iT1 = (Rt)tp[5], T2 = (Rt)tp[6];
+        const Rt alpha = (Rt)tp[3 * n_troe], iT3 = (Rt)tp[4 * n_troe], iT1 = (Rt)tp[5 * n_troe], T2 = (Rt)tp[6 * n_troe];
         const Rt e3 = exp_r<Rt>(-T * iT3), e1 = exp_r<Rt>(-T * iT1), e2 = exp_r<Rt>(-T2 * invT);
         const Rt Fc = ((Rt)1 - alpha) * e3 + alpha * e1 + e2;
         const Rt tiny = MIXED ? (Rt)1e-37 : (Rt)1e-300;
         const Rt dFc = -((Rt)1 - alpha) * iT3 * e3 - alpha * iT1 * e1 + T2 * invT * invT * e2;
-        double *tq = TQ + JS_TQ * j;
+        double *tq = TQ + j;
         tq[0] = (double)(log_r<Rt>(Fc > tiny ? Fc : tiny) * (Rt)INV_LN10);
-        tq[1] = (double)(dFc / (Fc * (Rt)LN10));
+        tq[n_troe] = (double)(dFc / (Fc * (Rt)LN10));
     }
 }
 
@@ -1251,16 +1252,16 @@ template <bool MIXED>
 __device__ inline void jac_seg_troe_k(int lane, int n_troe, double lnT_, double invT_, const double *TP, double *TQ) {
     using Rt = typename std::conditional<MIXED, float, double>::type;
     for (int j = lane; j < n_troe; j += WAVE) {
-        const double *tp = TP + JS_TP * j;
+        const double *tp = TP + j;
         const Rt lnT = (Rt)lnT_, invT = (Rt)invT_;
-        const Rt lnA0 = (Rt)tp[0], b0 = (Rt)tp[1], th0 = (Rt)tp[2];
-        const Rt lnA = (Rt)tp[8], bb = (Rt)tp[9], th = (Rt)tp[10];
+        const Rt lnA0 = (Rt)tp[0], b0 = (Rt)tp[n_troe], th0 = (Rt)tp[2 * n_troe];
+        const Rt lnA = (Rt)tp[8 * n_troe], bb = (Rt)tp[9 * n_troe], th = (Rt)tp[10 * n_troe];
         const Rt lnk0 = lnA0 + b0 * lnT - th0 * invT;
         const Rt lnkinf = lnA + bb * lnT - th * invT;
-        double *tq = TQ + JS_TQ * j;
-        tq[2] = (double)(lnk0 - lnkinf);
-        tq[3] = (double)((b0 + th0 * invT) * invT - (bb + th * invT) * invT);
-        tq[4] = (double)exp_r<Rt>(lnk0);
+        double *tq = TQ + j;
+        tq[2 * n_troe] = (double)(lnk0 - lnkinf);
+        tq[3 * n_troe] = (double)((b0 + th0 * invT) * invT - (bb + th * invT) * invT);
+        tq[4 * n_troe] = (double)exp_r<Rt>(lnk0);
     }
 }
 
@@ -1394,7 +1395,7 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
         SP0[4 * ns + tid] = tid == 0 ? 1.0 : 0.0;
         SP0[4 * (ns + 1) + 4 * ns + tid] = tid == 0 ? 1.0 : 0.0;
     }
-    for (int e = tid; e < 8 * n_troe; e += JS_THREADS) TP[JS_TP * (e / 8) + e % 8] = m.troe[e];
+    for (int e = tid; e < 8 * n_troe; e += JS_THREADS) TP[(e % 8) * n_troe + e / 8] = m.troe[e];   // [q][j]
     for (int e = tid; e < m.n_exc; e += JS_THREADS) {
         EXm[e] = m.eff_m1[e];
         EXs[e] = m.eff_sp[e];
@@ -1415,9 +1416,9 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
         th = m.theta[r];
         const int ti = troe & 0xffff;
         if (ti != 0xffff) {   // the high-pressure Arrhenius constants beside the Troe constants
-            TP[JS_TP * ti + 8] = lnA;
-            TP[JS_TP * ti + 9] = bb;
-            TP[JS_TP * ti + 10] = th;
+            TP[8 * n_troe + ti] = lnA;
+            TP[9 * n_troe + ti] = bb;
+            TP[10 * n_troe + ti] = th;
         }
     }
     // gather program of this wavefront (uniform)
@@ -1461,7 +1462,7 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
         // ---- B
         if (r >= 0)
             jac_seg_reaction<MIXED>(r, sp03, sp45, dpos, xpos, n_exc, exc0, troe, dnu, lnA, bb, th, SP, SC,
-                                    TQ0, MQ0, EXm, RDd, qb);
+                                    TQ0, n_troe, MQ0, EXm, RDd, qb);
         const double Tt = SC[0], rho = SC[2], wbar = SC[3], invT = SC[6];
         // this wavefront's gather records (the same for every point; L1/L2 resident); every
         // wavefront runs DMAX rounds (the plan pads with no-op rounds), so the gather
