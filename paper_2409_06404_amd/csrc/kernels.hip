@@ -1133,13 +1133,17 @@ __global__ __launch_bounds__(KR_WAVES * 64) void k_jac_rt(DevMech m, int64_t n, 
 //        J[row][Y_j] = (rho A[row][5 + j] + alpha_row) / W_j
 // No LDS atomics: every LDS word has one writer per phase, and every sum is taken in
 // an order fixed by the plan, so results are bitwise reproducible.
-template <bool MIXED>
+// VAR: the reaction may carry an optional form (RxnVar var; tables in vtab, SRI constants in
+// TP): a PLOG or Chebyshev rate, Lindemann or SRI broadening, an explicit reverse rate or
+// none (irreversible).  Non-integer orders are not taken (the plan refuses them).
+template <bool MIXED, bool VAR>
 __device__ inline void jac_seg_reaction(int r, unsigned sp03, unsigned sp45, int dpos, int xpos, int n_exc,
                                         int exc0, int troe, int dnu, double lnA, double bb, double th,
                                         const double *SP, const double *SC, const double *TQ, int nt,
                                         const double *MQ, const double *EXm, typename GatherT<MIXED>::type *RDd,
-                                        int qb) {
+                                        int qb, const RxnVar &var, const double *vtab, const double *TP) {
     using Rt = typename std::conditional<MIXED, float, double>::type;
+    const int vf = VAR ? var.flags : 0;
     const int nfm = (sp45 >> 16) & 7, nrm = (sp45 >> 19) & 7, kind = (sp45 >> 22) & 3;
     const double lnT = SC[5], invT = SC[6], lnp0RT = SC[7];
     // third-body concentration [M] and its logarithm (formed with the state)
@@ -1153,11 +1157,42 @@ __device__ inline void jac_seg_reaction(int r, unsigned sp03, unsigned sp45, int
     // forward rate constant (Arrhenius; Lindemann-Troe blending for falloff reactions,
     // whose temperature-only terms come from jac_seg_troe_t)
     const Rt rlnT = (Rt)lnT, rinvT = (Rt)invT;
-    const Rt lnkinf = (Rt)lnA + (Rt)bb * rlnT - (Rt)th * rinvT;
+    Rt lnkinf = (Rt)lnA + (Rt)bb * rlnT - (Rt)th * rinvT;
+    Rt dlnkinf = ((Rt)bb + (Rt)th * rinvT) * rinvT;
+    if constexpr (VAR) {
+        if (vf & VAR_PLOG) plog_rate<Rt>(vtab + var.rate_off, log(SC[1]), rlnT, rinvT, lnkinf, dlnkinf);
+        else if (vf & VAR_CHEB) cheb_rate<Rt>(vtab + var.rate_off, log10(SC[1]), rinvT, lnkinf, dlnkinf);
+    }
     const Rt kinf = exp_r<Rt>(lnkinf);
-    const Rt dlnkinf = ((Rt)bb + (Rt)th * rinvT) * rinvT;
     Rt kf = kinf, dkf_dT = kinf * dlnkinf, dkf_dM = 0;
-    if (kind == RXN_TROE) {
+    if (VAR && kind == RXN_TROE && (vf & (VAR_LINDEMANN | VAR_SRI))) {
+        // Lindemann (F = 1) or SRI broadening, with the temperature terms of k0/kinf from TQ
+        const double *tq = TQ + troe;
+        const Rt lnkr = (Rt)tq[2 * nt], dlnPr = (Rt)tq[3 * nt], k0 = (Rt)tq[4 * nt];
+        const Rt lnPr = lnkr + (Rt)lnMd;
+        const Rt Pr = exp_r<Rt>(lnPr);
+        Rt F = 1, dlogF_dell = 0, dlnF = 0;
+        if (vf & VAR_SRI) {
+            const double *tp = TP + troe;   // a, b, c, d, e at constants 3..7
+            const Rt a = (Rt)tp[3 * nt], b = (Rt)tp[4 * nt], c = (Rt)tp[5 * nt], d = (Rt)tp[6 * nt], e = (Rt)tp[7 * nt];
+            const Rt T = (Rt)SC[0];
+            const Rt lnfloor = MIXED ? (Rt)-85.19 : (Rt)-690.7755278982137;
+            const Rt ell = (lnPr > lnfloor ? lnPr : lnfloor) * (Rt)INV_LN10;
+            const Rt X = (Rt)1 / ((Rt)1 + ell * ell);
+            const Rt ea = exp_r<Rt>(-b * rinvT), ec = exp_r<Rt>(-T / c);
+            const Rt S = a * ea + ec;
+            const Rt lnS = log_r<Rt>(S);
+            F = d * exp_r<Rt>(X * lnS + e * rlnT);
+            dlogF_dell = (Rt)-2 * ell * X * X * lnS * (Rt)INV_LN10;
+            const Rt dS = a * b * rinvT * rinvT * ea - ec / c;
+            dlnF = dlogF_dell * dlnPr + X * dS / S + e * rinvT;   // LN10 d log10 F / dT at fixed P_r
+        }
+        const Rt Prp = (Rt)1 / ((Rt)1 + (Rt)1 / Pr);
+        kf = kinf * Prp * F;
+        const Rt ip1 = (Rt)1 / ((Rt)1 + Pr);
+        dkf_dT = kf * (dlnkinf + dlnPr * ip1 + dlnF);
+        dkf_dM = k0 * F * ip1 * (ip1 + dlogF_dell);
+    } else if (kind == RXN_TROE) {
         const double *tq = TQ + troe;   // [term][falloff reaction]
         const Rt lFc = (Rt)tq[0], dlFc = (Rt)tq[nt], lnkr = (Rt)tq[2 * nt], dlnPr = (Rt)tq[3 * nt], k0 = (Rt)tq[4 * nt];
         const Rt lnPr = lnkr + (Rt)lnMd;
@@ -1196,15 +1231,31 @@ __device__ inline void jac_seg_reaction(int r, unsigned sp03, unsigned sp45, int
     // equilibrium constant and rates of progress (FP64)
     const double lnKc = (double)dnu * lnp0RT - ((g[3] + g[4] + g[5]) - (g[0] + g[1] + g[2]));
     const double dlnKc = ((h[3] + h[4] + h[5]) - (h[0] + h[1] + h[2]) - (double)dnu) * invT;
-    const double invKc = exp_fast(-lnKc);   // FP64 in both modes (it decides q near equilibrium)
     const double kfd = (double)kf;
     const double fac = kind == RXN_THREEBODY ? M : 1.0;
-    const double fk = fac * kfd, fr = fk * invKc;
     const double pf = c[0] * c[1] * c[2], pr = c[3] * c[4] * c[5];
+    double fk, fr, t, mf;
+    if (VAR && (vf & (VAR_REVERSE | VAR_IRREV))) {
+        // explicit reverse Arrhenius expression (independent of [M]) or no reverse reaction
+        double kr = 0.0, dkrT = 0.0;
+        if (vf & VAR_REVERSE) {
+            const double *rv = vtab + var.rev_off;
+            kr = exp_fast(rv[0] + rv[1] * lnT - rv[2] * invT);
+            dkrT = kr * (rv[1] + rv[2] * invT) * invT;
+        }
+        fk = fac * kfd;
+        fr = fac * kr;
+        t = fac * ((double)dkf_dT * pf - dkrT * pr);
+        mf = kind == RXN_THREEBODY ? kfd * pf - kr * pr : kind == RXN_TROE ? (double)dkf_dM * pf : 0.0;
+    } else {
+        const double invKc = exp_fast(-lnKc);   // FP64 in both modes (it decides q near equilibrium)
+        fk = fac * kfd;
+        fr = fk * invKc;
+        const double bracket = pf - invKc * pr;
+        t = fac * (double)dkf_dT * bracket + fr * pr * dlnKc;
+        mf = kind == RXN_THREEBODY ? kfd * bracket : kind == RXN_TROE ? (double)dkf_dM * bracket : 0.0;
+    }
     const double qf = fk * pf, qr = fr * pr;
-    const double bracket = pf - invKc * pr;
-    const double t = fac * (double)dkf_dT * bracket + fr * pr * dlnKc;
-    const double mf = kind == RXN_THREEBODY ? kfd * bracket : kind == RXN_TROE ? (double)dkf_dM * bracket : 0.0;
     const double sig = (double)nfm * qf - (double)nrm * qr + mf * M;
     if constexpr (MIXED) {   // 16-byte aligned (qb a multiple of 4)
         typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -1357,7 +1408,7 @@ __device__ inline void jac_seg_state(int ns, double R, double lnp0R, int wave, i
     }
 }
 
-template <bool MIXED, int DMAX>
+template <bool MIXED, int DMAX, bool VAR>
 __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n, const double *__restrict__ T,
                                                           const double *__restrict__ p, int64_t ps,
                                                           const double *__restrict__ Y, int64_t ld,
@@ -1410,6 +1461,7 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
     const unsigned sp03 = (unsigned)ta.y, sp45 = (unsigned)ta.z;
     const int dpos = ta.w, xpos = tb.x & 0xffff, n_exc = (tb.x >> 16) & 0xffff, exc0 = tb.y, troe = tb.z, dnu = tb.w;
     double lnA = 0.0, bb = 0.0, th = 0.0;
+    const RxnVar var = (VAR && r >= 0) ? m.var[r] : RxnVar{0, 0, 0, 0};
     if (r >= 0) {
         lnA = m.lnA[r];
         bb = m.b[r];
@@ -1461,8 +1513,8 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
         double *SC = SC0 + buf * 16;
         // ---- B
         if (r >= 0)
-            jac_seg_reaction<MIXED>(r, sp03, sp45, dpos, xpos, n_exc, exc0, troe, dnu, lnA, bb, th, SP, SC,
-                                    TQ0, n_troe, MQ0, EXm, RDd, qb);
+            jac_seg_reaction<MIXED, VAR>(r, sp03, sp45, dpos, xpos, n_exc, exc0, troe, dnu, lnA, bb, th, SP, SC,
+                                         TQ0, n_troe, MQ0, EXm, RDd, qb, var, m.vtab, TP);
         const double Tt = SC[0], rho = SC[2], wbar = SC[3], invT = SC[6];
         // this wavefront's gather records (the same for every point; L1/L2 resident); every
         // wavefront runs DMAX rounds (the plan pads with no-op rounds), so the gather
@@ -2617,18 +2669,18 @@ hipError_t launch_jvp(const DevMech &m, int mixed, int64_t n, const double *T, c
                    : launch_jvp_v<false>(m, mixed, n, T, p, ps, Y, ld, vT, vY, jh, jw, wdot, st);
 }
 
-template <int DMAX>
+template <int DMAX, bool VAR>
 hipError_t launch_jac_seg(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
                           const double *Y, int64_t ld, void *J, double *wdot, hipStream_t st) {
     const dim3 grid(grid_for(n, 1, 2)), block(JS_THREADS);
-    const void *fn = mixed ? (const void *)k_jac_seg<true, DMAX> : (const void *)k_jac_seg<false, DMAX>;
+    const void *fn = mixed ? (const void *)k_jac_seg<true, DMAX, VAR> : (const void *)k_jac_seg<false, DMAX, VAR>;
     // more than 64 KB of dynamic LDS per workgroup has to be allowed explicitly
     const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, m.jp_lds);
     if (e != hipSuccess) return e;
     if (mixed)
-        hipLaunchKernelGGL((k_jac_seg<true, DMAX>), grid, block, m.jp_lds, st, m, n, T, p, ps, Y, ld, J, wdot);
+        hipLaunchKernelGGL((k_jac_seg<true, DMAX, VAR>), grid, block, m.jp_lds, st, m, n, T, p, ps, Y, ld, J, wdot);
     else
-        hipLaunchKernelGGL((k_jac_seg<false, DMAX>), grid, block, m.jp_lds, st, m, n, T, p, ps, Y, ld, J, wdot);
+        hipLaunchKernelGGL((k_jac_seg<false, DMAX, VAR>), grid, block, m.jp_lds, st, m, n, T, p, ps, Y, ld, J, wdot);
     return hipGetLastError();
 }
 
@@ -2681,19 +2733,25 @@ hipError_t launch_jac(const DevMech &m, int mixed, int64_t n, const double *T, c
         // the instance with the fewest gather rounds that covers the plan (every wavefront
         // runs that many rounds in straight-line code; the plan pads with no-op rounds)
         const int r = m.jp_rmax;
-        if (r <= 6) return launch_jac_seg<6>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
-        if (r <= 8) return launch_jac_seg<8>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
-        if (r <= 10) return launch_jac_seg<10>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
-        if (r <= 11) return launch_jac_seg<11>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
-        if (r <= 12) return launch_jac_seg<12>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
-        if (r <= 13) return launch_jac_seg<13>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
-        if (r <= 14) return launch_jac_seg<14>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
-        if (r <= 15) return launch_jac_seg<15>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
-        if (r <= 16) return launch_jac_seg<16>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
-        if (r <= 18) return launch_jac_seg<18>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
-        if (r <= 20) return launch_jac_seg<20>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
-        if (r <= 22) return launch_jac_seg<22>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
-        return launch_jac_seg<JS_DMAX>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (m.n_var) {   // mechanisms with optional rate forms: fewer instances
+            if (r <= 8) return launch_jac_seg<8, true>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+            if (r <= 12) return launch_jac_seg<12, true>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+            if (r <= 16) return launch_jac_seg<16, true>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+            return launch_jac_seg<JS_DMAX, true>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        }
+        if (r <= 6) return launch_jac_seg<6, false>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 8) return launch_jac_seg<8, false>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 10) return launch_jac_seg<10, false>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 11) return launch_jac_seg<11, false>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 12) return launch_jac_seg<12, false>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 13) return launch_jac_seg<13, false>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 14) return launch_jac_seg<14, false>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 15) return launch_jac_seg<15, false>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 16) return launch_jac_seg<16, false>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 18) return launch_jac_seg<18, false>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 20) return launch_jac_seg<20, false>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        if (r <= 22) return launch_jac_seg<22, false>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
+        return launch_jac_seg<JS_DMAX, false>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);
     }
     return m.n_var ? launch_jac_general<true>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st)
                    : launch_jac_general<false>(m, mixed, n, T, p, ps, Y, ld, J, wdot, st);

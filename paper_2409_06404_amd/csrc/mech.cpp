@@ -417,7 +417,8 @@ void build_jac_plan(HostMech &h) {
         h.jp_mrx.clear();
     };
     if (ns < 1 || nr < 1) return no("empty mechanism");
-    if (h.n_var > 0) return no("PLOG, Chebyshev, Lindemann, SRI, explicit-reverse, irreversible or order reactions");
+    for (int i = 0; i < nr; ++i)   // the rate phase forms products of whole molecules
+        if (h.var[i].flags & VAR_ORDERS) return no("reactions with non-integer forward orders");
     if (ns > 64) return no("more than 64 species (the state phase is one species per lane)");
     if (nr > JS_THREADS) return no("more reactions than threads per workgroup");
     {   // emission: column pairs x row phases over JS_EWAVES wavefronts, at most JS_EROWS rows each

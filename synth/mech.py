@@ -443,12 +443,13 @@ def mechanism_text(m: Mechanism) -> str:
 MECH_V = MechSpec("v", ("C", "H", "O", "N"), 32, 6, 50, 6, 12, 11)
 
 
-def generate_variant_mechanism(spec: MechSpec = MECH_V) -> Mechanism:
+def generate_variant_mechanism(spec: MechSpec = MECH_V, orders: bool = True) -> Mechanism:
     """generate_mechanism(spec) with reactions converted to the optional forms:
     of the 12 falloff reactions, 4 Lindemann and 5 SRI (the rest Troe); of the elementary
     ones, 6 PLOG (3-4 pressures, 1e4-1e7 Pa, each Arrhenius perturbed from the reaction's),
     5 Chebyshev (4 x 3 coefficients around the reaction's Arrhenius at 1 atm), 6 with an
-    explicit reverse expression, 6 irreversible of which 4 have non-integer orders."""
+    explicit reverse expression, 6 irreversible of which 4 have non-integer orders (none
+    with orders=False; the draws are the same either way)."""
     m = generate_mechanism(spec)
     rng = np.random.default_rng(spec.seed + 1000)
     fall = [i for i, r in enumerate(m.reactions) if r.kind == "troe"]
@@ -498,7 +499,9 @@ def generate_variant_mechanism(spec: MechSpec = MECH_V) -> Mechanism:
         r = m.reactions[i]
         r.extra = {"irreversible": True}
         if j < 4:
-            r.extra["orders"] = {s_: round(float(n_) * rng.uniform(0.5, 1.5), 2) for s_, n_ in r.reactants.items()}
+            o = {s_: round(float(n_) * rng.uniform(0.5, 1.5), 2) for s_, n_ in r.reactants.items()}
+            if orders:
+                r.extra["orders"] = o
     return m
 
 

@@ -182,11 +182,21 @@ def test_compute_calls_validate_before_launch(L, c0_path):
 
 def test_jacobian_plan_selection(mech_dir):
     """The segmented Jacobian kernel takes the 9- and 53-species mechanisms (its plan
-    passes the builder's replay check); the 200-species one goes to the reaction-table kernel."""
+    passes the builder's replay check) and the variant mechanism without non-integer orders;
+    the 200-species one and the variant mechanism with orders go to the reaction-table kernel."""
     import synth
     import paper_2409_06404_amd as crf
     for spec, want in ((synth.MECH_C0, "segmented"), (synth.MECH_C1, "segmented"), (synth.MECH_C4, "reaction-table")):
         path = synth.write_mechanism(spec, str(mech_dir / f"plan_{spec.n_species}.mech"))
+        m = crf.Mechanism(path, device=-1)
+        try:
+            assert m.jac_plan.startswith(want), m.jac_plan
+        finally:
+            m.close()
+    # optional rate forms take the segmented plan, non-integer forward orders do not
+    for orders, want in ((False, "segmented"), (True, "reaction-table")):
+        path = str(mech_dir / f"plan_var_{orders}.mech")
+        open(path, "w").write(synth.mechanism_text(synth.generate_variant_mechanism(orders=orders)))
         m = crf.Mechanism(path, device=-1)
         try:
             assert m.jac_plan.startswith(want), m.jac_plan

@@ -40,8 +40,9 @@ def _dev(st):
 
 
 def test_variant_plan_is_reaction_table(var):
+    """Non-integer forward orders keep a mechanism out of the segmented plan."""
     crf, g, om = var
-    assert g.jac_plan.startswith("reaction-table") and "PLOG" in g.jac_plan
+    assert g.jac_plan.startswith("reaction-table") and "orders" in g.jac_plan
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
@@ -107,6 +108,49 @@ def test_variant_stored_vjp_and_source(var):
     pr = oracle.production_rates(om, st["T"], st["p"], st["Y"].T)
     S = pr["turnover"] + np.abs(pr["wdot"])
     assert np.max(np.abs(out["dYdt"].cpu().numpy() - ref["dYdt"]) / (S * om.W[None, :] / ref["rho"][:, None])) <= 1e-12
+
+
+@pytest.fixture(scope="module")
+def var_seg(mech_dir):
+    """The same mechanism without the non-integer orders: the segmented Jacobian kernel with
+    its optional-form rate phase."""
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2409_06404_amd as crf
+    path = str(mech_dir / "variants_no_orders.mech")
+    open(path, "w").write(synth.mechanism_text(synth.generate_variant_mechanism(orders=False)))
+    g = crf.Mechanism(path, device=0)
+    yield crf, g, oracle.read_mechanism(path)
+    g.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_variant_segmented_jacobian(var_seg, prec, tol):
+    """PLOG, Chebyshev, Lindemann, SRI, explicit-reverse and irreversible reactions in the
+    segmented kernel: J and the fused w against the oracle (ragged point count, pressures
+    over 0.05-60 atm), and two runs bitwise equal."""
+    crf, g, om = var_seg
+    assert g.jac_plan == "segmented", g.jac_plan
+    n = 83
+    st = _state(om.n_species, n, 67)
+    T, p, Y = _dev(st)
+    print(f"variant segmented {prec}", flush=True)
+    J, w = crf.wdot_jac(g, T, p, Y, prec)
+    J2, w2 = crf.wdot_jac(g, T, p, Y, prec)
+    torch.cuda.synchronize()
+    assert torch.equal(J, J2) and torch.equal(w, w2)
+    Jr, G = oracle.jacobian(om, st["T"], st["p"], st["Y"].T, return_gross=True)
+    floor = 1e-10 if prec == "mixed" else 0.0
+    ej = jac_scaled_error(J.double().cpu().numpy(), Jr, G, st["T"], st["Y"].T, floor=floor).max()
+    ref = oracle.production_rates(om, st["T"], st["p"], st["Y"].T)
+    got = w.cpu().numpy()
+    if prec == "fp64":
+        ew = e_turn(got, ref["wdot"], ref["turnover"]).max()
+    else:
+        sig = significant_species(ref["wdot"], om.W)
+        ew = e_norm(got, ref["wdot"])[sig].max()
+    print(f"  J {ej:.2e} w {ew:.2e}", flush=True)
+    assert ej <= tol and ew <= tol
 
 
 def test_variant_reactor_step(var, mech_dir):
