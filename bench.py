@@ -269,7 +269,9 @@ def reactor_figures(crf, m, full, stream, n=1 << 14, nsub=4, dt=1e-6):
 def variant_figures(crf, stream, n=1 << 18, steps=5):
     """The mechanism with every optional rate form (32 species; PLOG, Chebyshev, Lindemann,
     SRI, explicit reverse, irreversible and forward-order reactions) on n points of the
-    9-species state's distributions with pressures over 0.05-60 atm: every per-point call."""
+    9-species state's distributions with pressures over 0.05-60 atm: every per-point call
+    (its Jacobian in the reaction-table kernel), and the Jacobian of the same mechanism
+    without the non-integer orders (the segmented kernel)."""
     import numpy as np
     import torch
 
@@ -300,6 +302,19 @@ def variant_figures(crf, stream, n=1 << 18, steps=5):
             del J
             torch.cuda.empty_cache()
         m.close()
+        # the same mechanism without its non-integer forward orders: the segmented Jacobian kernel
+        path2 = os.path.join(d, "v_no_orders.mech")
+        with open(path2, "w") as fh:
+            fh.write(synth.mechanism_text(synth.generate_variant_mechanism(orders=False)))
+        m2 = crf.Mechanism(path2, device=0)
+        out["no_orders_jac_plan"] = m2.jac_plan
+        for prec in ("fp64", "mixed"):
+            J = torch.empty((n, ns + 1, ns + 1), dtype=torch.float64 if prec == "fp64" else torch.float32, device=dev)
+            out[prec]["jac_no_orders"] = n / (timed(lambda: crf.wdot_jac(m2, T, p, Y, prec, out=J), steps, 1, stream)
+                                              * 1e-3) / 1e6
+            del J
+            torch.cuda.empty_cache()
+        m2.close()
     out["unit"] = "Mpoints/s"
     return out
 
