@@ -946,7 +946,7 @@ __global__ __launch_bounds__(KJ_WAVES * 64) void k_jac(DevMech m, int64_t n, con
 
 // ------------------------------------------------------------------ Jacobian (reaction table)
 // For mechanisms the segmented kernel does not take (more than 64 species or 384
-// reactions, optional rate forms): one workgroup of KR_WAVES wavefronts per point.  Each
+// reactions, optional rate forms): one workgroup of WAVES wavefronts per point.  Each
 // reaction is evaluated once per point; its derivative data (dq/dC of its slots and
 // dq/d[M], FP64, or FP32 in the mixed mode) go to a table in LDS, its reaction enthalpy
 // sum_k dnu_k h_k beside them, and the row scalars (tau, J_T at fixed C, R, w) are summed
@@ -955,10 +955,10 @@ __global__ __launch_bounds__(KJ_WAVES * 64) void k_jac(DevMech m, int64_t n, con
 // are FP64 LDS atomics, so results are reproducible to rounding (not bitwise).
 // LDS: {C, g/RT, h/RT, cp/R} x nsp and {tau, jtc, R, w} x (nsp+1) doubles, the enthalpy of
 // every reaction (nrp doubles), the table (7 x nrp values), rb x sr FP64 accumulators and
-// two per-row scalars of the block.
-constexpr int KR_WAVES = 8;
-template <bool MIXED, bool VAR>
-__global__ __launch_bounds__(KR_WAVES * 64) void k_jac_rt(DevMech m, int64_t n, const double *__restrict__ T,
+// two per-row scalars of the block.  WAVES is 16 for mechanisms with more reactions than
+// 8 wavefronts have lanes, else 8 (two workgroups per compute unit).
+template <bool MIXED, bool VAR, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_jac_rt(DevMech m, int64_t n, const double *__restrict__ T,
                                                           const double *__restrict__ p, int64_t ps,
                                                           const double *__restrict__ Y, int64_t ld,
                                                           void *__restrict__ Jv, double *__restrict__ wdot, int nsp,
@@ -968,7 +968,7 @@ __global__ __launch_bounds__(KR_WAVES * 64) void k_jac_rt(DevMech m, int64_t n, 
     extern __shared__ double lds[];
     const int tid = threadIdx.x, lane = tid & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
-    constexpr int NT = KR_WAVES * WAVE;
+    constexpr int NT = WAVES * WAVE;
     const int ns = m.ns, n1 = ns + 1, nr = m.nr;
     double *C = lds, *G = C + nsp, *H = G + nsp, *CP = H + nsp;
     double *TAU = CP + nsp, *JTC = TAU + (nsp + 1), *RC = JTC + (nsp + 1), *Wd = RC + (nsp + 1);
@@ -2684,6 +2684,28 @@ hipError_t launch_jac_seg(const DevMech &m, int mixed, int64_t n, const double *
     return hipGetLastError();
 }
 
+// The reaction-table kernel with WAVES wavefronts per workgroup: as many resident
+// workgroups per compute unit as its registers and LDS allow, each persistent over points.
+template <bool VAR, int WAVES>
+hipError_t launch_jac_rt(const DevMech &m, int mixed, int64_t n, const double *T, const double *p, int64_t ps,
+                         const double *Y, int64_t ld, void *J, double *wdot, int nsp, int sr, const JacRtLayout &lay,
+                         int nrp, hipStream_t st) {
+    const void *fn = mixed ? (const void *)k_jac_rt<true, VAR, WAVES> : (const void *)k_jac_rt<false, VAR, WAVES>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lay.total);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, WAVES * WAVE, lay.total);
+    if (e != hipSuccess) return e;
+    const dim3 grid(grid_for(n, 1, per_cu > 1 ? per_cu : 1)), block(WAVES * WAVE);
+    if (mixed)
+        hipLaunchKernelGGL((k_jac_rt<true, VAR, WAVES>), grid, block, lay.total, st, m, n, T, p, ps, Y, ld, J, wdot, nsp,
+                           sr, lay.rows, nrp);
+    else
+        hipLaunchKernelGGL((k_jac_rt<false, VAR, WAVES>), grid, block, lay.total, st, m, n, T, p, ps, Y, ld, J, wdot, nsp,
+                           sr, lay.rows, nrp);
+    return hipGetLastError();
+}
+
 // The kernels for mechanisms the segmented plan does not take: the reaction table when it
 // fits the LDS, else the row blocks that re-evaluate the reactions per block.
 template <bool VAR>
@@ -2697,17 +2719,8 @@ hipError_t launch_jac_general(const DevMech &m, int mixed, int64_t n, const doub
     if (jac_rt_fits(m.ns, m.nr, mixed != 0, &lay)) {
         // reaction table in LDS: each reaction evaluated once per point
         const int nrp = (m.nr + 1) & ~1;
-        const void *fn = mixed ? (const void *)k_jac_rt<true, VAR> : (const void *)k_jac_rt<false, VAR>;
-        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lay.total);
-        if (e != hipSuccess) return e;
-        const dim3 grid(grid_for(n, 1, 1)), block(KR_WAVES * WAVE);
-        if (mixed)
-            hipLaunchKernelGGL((k_jac_rt<true, VAR>), grid, block, lay.total, st, m, n, T, p, ps, Y, ld, J, wdot, nsp, sr,
-                               lay.rows, nrp);
-        else
-            hipLaunchKernelGGL((k_jac_rt<false, VAR>), grid, block, lay.total, st, m, n, T, p, ps, Y, ld, J, wdot, nsp, sr,
-                               lay.rows, nrp);
-        return hipGetLastError();
+        return m.nr > 8 * WAVE ? launch_jac_rt<VAR, 16>(m, mixed, n, T, p, ps, Y, ld, J, wdot, nsp, sr, lay, nrp, st)
+                               : launch_jac_rt<VAR, 8>(m, mixed, n, T, p, ps, Y, ld, J, wdot, nsp, sr, lay, nrp, st);
     }
     const size_t fixed = (size_t)(4 * nsp + 4 * (nsp + 1)) * sizeof(double);
     // rows per block: as many as fit one compute unit's LDS (one workgroup per point)
