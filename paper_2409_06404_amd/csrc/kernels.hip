@@ -1195,7 +1195,10 @@ __device__ inline void jac_seg_reaction(int r, unsigned sp03, unsigned sp45, int
     } else if (kind == RXN_TROE) {
         const double *tq = TQ + troe;   // [term][falloff reaction]
         const Rt lFc = (Rt)tq[0], dlFc = (Rt)tq[nt], lnkr = (Rt)tq[2 * nt], dlnPr = (Rt)tq[3 * nt], k0 = (Rt)tq[4 * nt];
-        const Rt lnPr = lnkr + (Rt)lnMd;
+        // ln P_r capped where P_r / (1 + P_r) = 1 to the working precision (P_r stays finite)
+        const Rt lnceil = MIXED ? (Rt)80 : (Rt)700;
+        const Rt lnPr0 = lnkr + (Rt)lnMd;
+        const Rt lnPr = lnPr0 < lnceil ? lnPr0 : lnceil;
         const Rt Pr = exp_r<Rt>(lnPr);
         const Rt cc = (Rt)-0.4 - (Rt)0.67 * lFc;
         const Rt nn = (Rt)0.75 - (Rt)1.27 * lFc;
@@ -1203,18 +1206,22 @@ __device__ inline void jac_seg_reaction(int r, unsigned sp03, unsigned sp45, int
         const Rt ell = (lnPr > lnfloor ? lnPr : lnfloor) * (Rt)INV_LN10;
         const Rt u = ell + cc;
         const Rt den = nn - (Rt)0.14 * u;
-        const Rt f1 = u / den;
-        const Rt gg = (Rt)1 / ((Rt)1 + f1 * f1);
+        // one reciprocal for 1/den, f1 = u/den and 1/(1 + f1^2) = den^2/(den^2 + u^2)
+        const Rt d2 = den * den, s2 = d2 + u * u;
+        const Rt rr = (Rt)1 / (den * s2);
+        const Rt iden = s2 * rr;
+        const Rt f1 = u * iden;
+        const Rt gg = d2 * den * rr;
         const Rt F = exp_r<Rt>(lFc * gg * (Rt)LN10);
-        const Rt Prp = (Rt)1 / ((Rt)1 + (Rt)1 / Pr);
+        const Rt ip1 = (Rt)1 / ((Rt)1 + Pr);
+        const Rt Prp = Pr * ip1;
         kf = kinf * Prp * F;
-        const Rt idd = (Rt)1 / (den * den);
+        const Rt idd = iden * iden;
         const Rt df1_dell = nn * idd;
         const Rt df1_dlFc = ((Rt)-0.67 * den - u * ((Rt)-1.27 + (Rt)0.67 * (Rt)0.14)) * idd;
         const Rt dlogF_dell = -lFc * (Rt)2 * f1 * df1_dell * gg * gg;
         const Rt dlogF_dlFc = gg - lFc * (Rt)2 * f1 * df1_dlFc * gg * gg;
         const Rt dlnF = dlogF_dell * dlnPr + (Rt)LN10 * dlogF_dlFc * dlFc;
-        const Rt ip1 = (Rt)1 / ((Rt)1 + Pr);
         dkf_dT = kf * (dlnkinf + dlnPr * ip1 + dlnF);
         dkf_dM = k0 * F * ip1 * (ip1 + dlogF_dell);
     }
@@ -1483,7 +1490,10 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
     const int npair = (n1 + 1) / 2;
     const int rphase = JS_EWAVES * WAVE / npair;
     const int pc0 = 2 * (tid % npair), pr0 = tid / npair;
-    const bool pon = tid < JS_EWAVES * WAVE && pr0 < rphase;
+    const bool pon = tid < JS_EWAVES * WAVE && pr0 < rphase && pr0 < n1;
+    // with an even row length and a J aligned to a pair, every emitted pair is one aligned
+    // vector store (point-major rows of n1 values)
+    const bool evec = n1 % 2 == 0 && (((uintptr_t)Jv) & (2 * sizeof(Out) - 1)) == 0;
     // this workgroup's points: i = slot, slot + G, ... (G = gridDim.x).  Workgroups are
     // dispatched round-robin over the 8 XCDs, so the slots of one XCD's workgroups are a
     // contiguous run of G/8 points: the 16 points of a 128-byte line of the species-major Y
@@ -1644,14 +1654,42 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
                 }
                 emit(0, a0, a1, rho * tau0 - wbar * R0, t0 - cw - R0 * invT);
             }
+            typedef Acc Acc2 __attribute__((ext_vector_type(2)));
+            if (evec) {
+                // every pair whole and aligned, and no branch in the loop: a row outside
+                // 1 .. n1 - 1 is clamped onto a row whose owner (same column pair) stores the
+                // identical value, so every iteration is two LDS reads and one vector store
+                typedef Out Out2 __attribute__((ext_vector_type(2)));
+                const int nq = (n1 + rphase - 1) / rphase;
+                constexpr int EB = 3;   // rows whose reads are issued together
+                for (int q = 0; q < nq; q += EB) {
+                    int row[EB];
+                    Acc2 av[EB];
+                    f64x2 rw[EB];
+#pragma unroll
+                    for (int b = 0; b < EB; ++b) {
+                        const int rr = pr0 + (q + b) * rphase;
+                        row[b] = rr < 1 ? 1 : (rr < n1 ? rr : n1 - 1);
+                        av[b] = *(const Acc2 *)(A + (row[b] - 1) * sr + 4 + pc0);
+                        rw[b] = *(const f64x2 *)(ROW + 2 * (row[b] - 1));
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int b = 0; b < EB; ++b) {
+                        const Out v0 = (Out)(pc0 == 0 ? rw[b].y : (rho * (double)av[b].x + rw[b].x) * iw0);
+                        const Out v1 = (Out)((rho * (double)av[b].y + rw[b].x) * iw1);
+                        *(Out2 *)(Jp + row[b] * n1 + pc0) = Out2{v0, v1};
+                    }
+                }
+            } else {
 #pragma unroll 2
-            for (int q = 0; q < JS_EROWS; ++q) {
-                const int row = pr0 + q * rphase;
-                if (row >= 1 && row < n1) {
-                    typedef Acc Acc2 __attribute__((ext_vector_type(2)));
-                    const Acc2 av = *(const Acc2 *)(A + (row - 1) * sr + 4 + pc0);   // aligned pair
-                    const f64x2 rw = *(const f64x2 *)(ROW + 2 * (row - 1));
-                    emit(row, av.x, av.y, rw.x, rw.y);
+                for (int q = 0; q < JS_EROWS; ++q) {
+                    const int row = pr0 + q * rphase;
+                    if (row >= 1 && row < n1) {
+                        const Acc2 av = *(const Acc2 *)(A + (row - 1) * sr + 4 + pc0);   // aligned pair
+                        const f64x2 rw = *(const f64x2 *)(ROW + 2 * (row - 1));
+                        emit(row, av.x, av.y, rw.x, rw.y);
+                    }
                 }
             }
         }
