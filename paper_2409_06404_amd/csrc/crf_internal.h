@@ -78,11 +78,13 @@ struct DevMech {
     // binary-diffusion pairs as a round-robin schedule: each of tr_rounds rounds is a
     // perfect matching of the species (plus the dummy species ns when ns is odd), tr_slots
     // pairs per round
-    const int *tr_jk;         // [round][slot]: j | k << 16
-    const unsigned *tr_off;   // [round][slot]: the pair's byte offsets in a point tile's species rows,
-                              // 8 TT_RS j | 8 TT_RS k << 16 (transport on point tiles)
+    const int *tr_jk;         // [round][slot]: j | k << 16 (the FP64 tables' pair order)
+    const unsigned *tr_off;   // [prec][round][slot]: byte offsets of rows j and k in a point tile,
+                              // 8 tt_rs(W) j | 8 tt_rs(W) k << 16, W the tile width of the FP64
+                              // (prec 0) or mixed (prec 1) transport
     const double *tr_fit;     // [round][slot][4]: the pair's ln D fit (zeros for the dummy pair)
-    const float *tr_fit32;    // the same fits rounded to FP32 (the mixed mode)
+    const float *tr_fit32;    // the fits rounded to FP32 in the mixed tables' pair order (the
+                              // mixed tile; the same order as tr_fit when both widths agree)
     int tr_rounds, tr_slots;
     // reactions
     const double *lnA, *b, *theta;
@@ -241,10 +243,26 @@ inline RosLayout ros_layout(int ns, int mixed, int64_t n) {
 }
 inline size_t reactor_work_bytes(int ns, int mixed, int64_t n) { return n > 0 ? ros_layout(ns, mixed, n).total : 0; }
 
-// Transport on point tiles: points per tile, and the row stride (doubles, odd) of its
-// [species][point] arrays in LDS.
+// Transport on point tiles of TT_P points, W wavefronts per workgroup, each wavefront
+// owning TT_P / W points of the diffusion sums.  The row stride (doubles) of the tile's
+// [species][point] arrays in LDS is TT_P + TT_P / W, so that the TT_P / W points of row j
+// start at bank slot j mod W (32 banks of 4 bytes); the host orders the pairs of the
+// schedule so that W consecutive pairs have distinct first and distinct second members mod W.
 constexpr int TT_P = 16;
-constexpr int TT_RS = 17;
+constexpr int tt_rs(int W) { return TT_P + TT_P / W; }
+// LDS bytes of the tile kernel for `rows` species rows (species and the schedule's dummy).
+inline size_t tile_transport_lds(int rows, bool mixed, int W) {
+    return (size_t)rows * tt_rs(W) * (2 * sizeof(double) + (mixed ? sizeof(float) : sizeof(double))) +
+           (size_t)(64 + 2 * TT_P + 4 * W * TT_P) * sizeof(double);
+}
+// Wavefronts per tile workgroup: 4 while four or more workgroups fit a compute unit's LDS,
+// else 8 (two or three) or 16 (one); 0 if the tile does not fit (the species-per-lane kernel).
+inline int tile_transport_waves(int rows, bool mixed) {
+    const int fit = (int)(CU_LDS_BYTES / tile_transport_lds(rows, mixed, 4));
+    const int W = fit >= 4 ? 4 : (fit >= 2 ? 8 : 16);
+    const bool fits = tile_transport_lds(rows, mixed, W) <= (size_t)CU_LDS_BYTES;
+    return fits && 8 * tt_rs(W) * rows <= 0xffff ? W : 0;   // 16-bit row offsets
+}
 
 // Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_thermo(const DevMech &m, int64_t n, const double *T, const double *p, int64_t ps,

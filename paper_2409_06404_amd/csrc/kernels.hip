@@ -1822,9 +1822,11 @@ __global__ __launch_bounds__(256) void k_transport(DevMech m, int64_t n, const d
 
 // ------------------------------------------------------------------ transport, point tiles
 // Sixteen points per workgroup of W wavefronts, one tile per workgroup.  LDS holds, per
-// species row of the tile (row stride TT_RS doubles, odd, so that the rows that one
-// instruction touches start on different banks): Xs_k = Y_k / W_k, the diffusion sums
-// IS_k = sum_j Xs_j / D_jk, b_k = W_k^(1/4) / sqrt(mu_k), a_k = 1 / b_k and mu_k.  The mole fractions are
+// species row of the tile (row stride tt_rs(W) doubles; the host orders the pairs of a round so
+// that the rows one part of an instruction touches fall on different banks): Xs_k = Y_k / W_k, the diffusion sums
+// IS_k = sum_j Xs_j / D_jk and a_k = sqrt(mu_k) / W_k^(1/4); b_k = 1 / a_k and
+// mu_k = (a_k W_k^(1/4))^2 are formed where they are used, which keeps the tile small enough
+// for six workgroups per compute unit (53 species, FP64).  The mole fractions are
 // X = Wbar Xs; Wbar cancels from Wilke's quotient and is applied to the conductivity and
 // diffusion sums at the end.
 //   * setup: thread = (point, species group); the 16 points of a species row are adjacent
@@ -1893,13 +1895,6 @@ __device__ inline double row16_sum(double v) {
     return v;
 }
 
-// LDS bytes of k_transport_tile for `rows` species rows (the species and the dummy of the pair
-// schedule) and W wavefronts.
-inline size_t tile_transport_lds(int rows, bool mixed, int W) {
-    return (size_t)rows * TT_RS * (2 * sizeof(double) + 3 * (mixed ? sizeof(float) : sizeof(double))) +
-           (size_t)(64 + 2 * TT_P + 4 * W * TT_P) * sizeof(double);
-}
-
 template <bool MIXED, int W>
 __global__ __launch_bounds__(W * WAVE) __attribute__((amdgpu_waves_per_eu(4))) void k_transport_tile(DevMech m, int64_t n, const double *__restrict__ T,
                                                              const double *__restrict__ p, int64_t ps,
@@ -1912,15 +1907,14 @@ __global__ __launch_bounds__(W * WAVE) __attribute__((amdgpu_waves_per_eu(4))) v
     constexpr int PW = TT_P / W;                 // points per wavefront in the diffusion phase
     constexpr int G = WAVE / PW;                 // pairs per wavefront instruction
     constexpr int NG = NT / TT_P;                // species groups of the setup and output phases
+    constexpr int RS = tt_rs(W);                 // row stride of the species rows
     extern __shared__ double lds[];
-    double *XS = lds;                            // [rows][TT_RS]
-    double *IS = XS + rows * TT_RS;              // [rows][TT_RS]
-    double *E2 = IS + rows * TT_RS;              // 2^(j/64) for exp_tab
+    double *XS = lds;                            // [rows][RS]
+    double *IS = XS + rows * RS;              // [rows][RS]
+    double *E2 = IS + rows * RS;              // 2^(j/64) for exp_tab
     double *PT = E2 + 64;                        // lnT[16], ln(p0/p)[16], sums[W][16][3], num[W][16]
     double *SUMS = PT + 2 * TT_P, *NUM = SUMS + 3 * W * TT_P;
-    Rt *BB = (Rt *)(NUM + W * TT_P);             // [rows][TT_RS]
-    Rt *AA = BB + rows * TT_RS;                  // [rows][TT_RS]
-    Rt *MU = AA + rows * TT_RS;                  // [rows][TT_RS]
+    Rt *AA = (Rt *)(NUM + W * TT_P);             // [rows][RS]
     const int tid = threadIdx.x, wave = tid / WAVE, lane = tid & (WAVE - 1);
     const int ns = m.ns;
     if (!MIXED && tid < 64) E2[tid] = EXP2_J64[tid];
@@ -1938,24 +1932,20 @@ __global__ __launch_bounds__(W * WAVE) __attribute__((amdgpu_waves_per_eu(4))) v
             double sx = 0.0, sxl = 0.0, sxil = 0.0;
             for (int k = g; k < rows; k += NG) {
                 double x = 0.0;
-                Rt b = 0, ak = 0, muk = 0;
+                Rt ak = 0;
                 if (k < ns) {
                     x = Y[(int64_t)k * ld + i] * m.invW[k];
                     const double *a = m.mu_fit + 4 * k, *c = m.lam_fit + 4 * k;
-                    muk = exp_r<Rt>((Rt)a[0] + Lr * ((Rt)a[1] + Lr * ((Rt)a[2] + Lr * (Rt)a[3])));
+                    const Rt muk = exp_r<Rt>((Rt)a[0] + Lr * ((Rt)a[1] + Lr * ((Rt)a[2] + Lr * (Rt)a[3])));
                     const double lk = (double)exp_r<Rt>((Rt)c[0] + Lr * ((Rt)c[1] + Lr * ((Rt)c[2] + Lr * (Rt)c[3])));
-                    const double sq = sqrt((double)muk);
-                    b = (Rt)(m.w4[k] / sq);
-                    ak = (Rt)(sq * m.iw4[k]);
+                    ak = (Rt)(sqrt((double)muk) * m.iw4[k]);
                     sx += x;
                     sxl += x * lk;
                     sxil += x / lk;
                 }
-                XS[k * TT_RS + mm] = x;
-                IS[k * TT_RS + mm] = 0.0;
-                BB[k * TT_RS + mm] = b;
-                AA[k * TT_RS + mm] = ak;
-                MU[k * TT_RS + mm] = muk;
+                XS[k * RS + mm] = x;
+                IS[k * RS + mm] = 0.0;
+                AA[k * RS + mm] = ak;
             }
             // the wavefront's four species groups of a point: lanes mm, mm + 16, mm + 32, mm + 48
             sx += __shfl_xor(sx, 16);
@@ -1984,7 +1974,8 @@ __global__ __launch_bounds__(W * WAVE) __attribute__((amdgpu_waves_per_eu(4))) v
             int r = 0, t = 0;
             bool ok_n = sg < slots;
             int e_n = ok_n ? sg : 0;
-            unsigned off_n = m.tr_off[e_n];
+            const unsigned *offs = m.tr_off + (MIXED ? m.tr_rounds * m.tr_slots : 0);
+            unsigned off_n = offs[e_n];
             Rt cn[4];
             auto load_fit = [&](int e) {
                 if constexpr (MIXED) {
@@ -2006,7 +1997,7 @@ __global__ __launch_bounds__(W * WAVE) __attribute__((amdgpu_waves_per_eu(4))) v
                     const int s = sg + t * G;
                     ok_n = s < slots;
                     e_n = r * slots + (ok_n ? s : 0);
-                    off_n = m.tr_off[e_n];
+                    off_n = offs[e_n];
                     load_fit(e_n);
                 }
                 if (ok) {
@@ -2033,8 +2024,8 @@ __global__ __launch_bounds__(W * WAVE) __attribute__((amdgpu_waves_per_eu(4))) v
                     const int j = ks * 4 + kin;
                     u1n = 0; bjn = 0; cn = 0;
                     if (j < ns) {
-                        u1n = (Rt)XS[j * TT_RS + mrow];
-                        bjn = BB[j * TT_RS + mrow];
+                        u1n = (Rt)XS[j * RS + mrow];
+                        bjn = (Rt)1 / AA[j * RS + mrow];
                         if (kc < ns) cn = (Rt)m.wilke_c[(size_t)j * ns + kc];
                     }
                 };
@@ -2048,12 +2039,14 @@ __global__ __launch_bounds__(W * WAVE) __attribute__((amdgpu_waves_per_eu(4))) v
                     d3 = MM::mma(u3, c, d3);
                 }
                 if (kc < ns) {
+                    const Rt w4k = (Rt)m.w4[kc];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int o = kc * TT_RS + MM::row(lane, r);
+                        const int o = kc * RS + MM::row(lane, r);
                         const Rt a = AA[o];
                         const Rt den = d1[r] + a * ((Rt)2 * d2[r] + a * d3[r]);
-                        num[r] += XS[o] * (double)MU[o] / (double)den;
+                        const Rt sq = a * w4k;   // sqrt(mu_k)
+                        num[r] += XS[o] * (double)(sq * sq) / (double)den;
                     }
                 }
             }
@@ -2079,7 +2072,7 @@ __global__ __launch_bounds__(W * WAVE) __attribute__((amdgpu_waves_per_eu(4))) v
                 const double wbar = 1.0 / sx;
                 if (Dmix)
                     for (int k = g; k < ns; k += NG)
-                        Dmix[(int64_t)k * ld + i] = (1.0 - Y[(int64_t)k * ld + i]) / (wbar * IS[k * TT_RS + mm]);
+                        Dmix[(int64_t)k * ld + i] = (1.0 - Y[(int64_t)k * ld + i]) / (wbar * IS[k * RS + mm]);
                 if (g == 0) {
                     if (lam) lam[i] = 0.5 * (wbar * sxl + 1.0 / (wbar * sxil));
                     if (mu) {
@@ -2934,10 +2927,9 @@ hipError_t launch_transport(const DevMech &m, int mixed, int64_t n, const double
     // Point tiles while a tile's species rows fit one compute unit's LDS: 4 wavefronts per
     // workgroup while four or more workgroups fit, else 8 (two or three) or 16 (one).
     const int rows = m.ns + 1;
-    const int fit = (int)(CU_LDS_BYTES / tile_transport_lds(rows, mixed, 4));
-    const int W = fit >= 4 ? 4 : (fit >= 2 ? 8 : 16);
-    const size_t tshm = tile_transport_lds(rows, mixed, W);
-    if (tshm <= (size_t)CU_LDS_BYTES) {
+    const int W = tile_transport_waves(rows, mixed != 0);
+    if (W) {
+        const size_t tshm = tile_transport_lds(rows, mixed, W);
         const void *fn = nullptr;
         if (W == 4) fn = mixed ? (const void *)k_transport_tile<true, 4> : (const void *)k_transport_tile<false, 4>;
         else if (W == 8) fn = mixed ? (const void *)k_transport_tile<true, 8> : (const void *)k_transport_tile<false, 8>;

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <sstream>
 
@@ -400,6 +401,82 @@ void build_tree(PlanTree &t, std::vector<unsigned> recs, int L, int &n_partial) 
 int coef_of(unsigned rec) { return ((int)(rec & 7u) ^ 4) - 4; }
 
 }  // namespace
+
+template <class T> static std::vector<T> cat(std::vector<T> a, const std::vector<T> &b) {
+    a.insert(a.end(), b.begin(), b.end());
+    return a;
+}
+
+// Order and orientation of the pairs of one round of the transport pair schedule.  Any
+// order gives the same sums (a round adds into each species once).  The tile kernel with W
+// wavefronts puts W consecutive pairs of a round into one 16-lane part of an LDS instruction,
+// and row j of the wavefront's points starts at bank slot j mod W (tt_rs), so W consecutive
+// pairs whose first members are distinct mod W, and whose second members are too, touch
+// every bank once.  Each group of W pairs is filled greedily (a pair and orientation adding
+// no repeated residue on either side, else the fewest), restarted from other positions
+// (a fixed pseudo-random sequence) until a group without repeats is found or 32 attempts
+// are made; a group is then sorted by its first members' residues.
+static std::vector<std::pair<int, int>> order_round_pairs(std::vector<std::pair<int, int>> rest, int W) {
+    std::vector<std::pair<int, int>> out;
+    unsigned long long seed = 0x9e3779b97f4a7c15ull;
+    auto rnd = [&]() {
+        seed ^= seed << 13;
+        seed ^= seed >> 7;
+        seed ^= seed << 17;
+        return seed;
+    };
+    while (!rest.empty()) {
+        const int g = std::min<int>(W, (int)rest.size());
+        std::vector<int> bidx;
+        std::vector<std::pair<int, int>> bgrp;
+        int best_cost = 1 << 30;
+        for (int attempt = 0; attempt < 32 && best_cost > 0; ++attempt) {
+            const size_t s0 = attempt == 0 ? 0 : (size_t)(rnd() % rest.size());
+            std::vector<char> used(rest.size(), 0);
+            std::vector<int> idx;
+            std::vector<std::pair<int, int>> grp;
+            unsigned lmask = 0, rmask = 0;
+            int cost = 0;
+            for (int t = 0; t < g; ++t) {
+                int bi = -1, bf = 0, bc = 3;
+                for (size_t u = 0; u < rest.size() && bc > 0; ++u) {
+                    const size_t i = (s0 + u) % rest.size();
+                    if (used[i]) continue;
+                    for (int f = 0; f < 2; ++f) {
+                        const int a = f ? rest[i].second : rest[i].first, b = f ? rest[i].first : rest[i].second;
+                        const int c = (int)((lmask >> (a % W)) & 1u) + (int)((rmask >> (b % W)) & 1u);
+                        if (c < bc) {
+                            bc = c;
+                            bi = (int)i;
+                            bf = f;
+                            if (c == 0) break;
+                        }
+                    }
+                }
+                if (bi < 0) break;   // not reached: g never exceeds the pairs left
+                used[bi] = 1;
+                const int a = bf ? rest[bi].second : rest[bi].first, b = bf ? rest[bi].first : rest[bi].second;
+                lmask |= 1u << (a % W);
+                rmask |= 1u << (b % W);
+                cost += bc;
+                idx.push_back(bi);
+                grp.emplace_back(a, b);
+            }
+            if ((int)idx.size() == g && cost < best_cost) {
+                best_cost = cost;
+                bidx = idx;
+                bgrp = grp;
+            }
+        }
+        std::stable_sort(bgrp.begin(), bgrp.end(), [W](const std::pair<int, int> &x, const std::pair<int, int> &y) {
+            return x.first % W < y.first % W;
+        });
+        out.insert(out.end(), bgrp.begin(), bgrp.end());
+        std::sort(bidx.begin(), bidx.end());
+        for (int t = g - 1; t >= 0; --t) rest.erase(rest.begin() + bidx[t]);
+    }
+    return out;
+}
 
 void build_jac_plan(HostMech &h) {
     h.jp_ok = 0;
@@ -866,19 +943,39 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
     // round-robin schedule of the species pairs (circle method): round r pairs the
     // positions of a circle of n2 (even) entries, fixed entry 0, the others rotated
     const int n2 = ns + (ns & 1), tr_slots = n2 / 2, tr_rounds = n2 - 1;
+    // pair order of the FP64 tables (tr_jk, tr_off FP64 part, tr_fit: the FP64 tile and the
+    // species-per-lane kernel) and of the mixed ones (tr_off mixed part, tr_fit32), each for
+    // its precision's tile width; byte offsets of the pair's rows fit 16 bits while the tile fits
+    const int tw64 = tile_transport_waves(ns + 1, false), tw32 = tile_transport_waves(ns + 1, true);
+    const int wa = tw64 ? tw64 : 4, wb = tw32 ? tw32 : 4;
     std::vector<int> tr_jk;
-    std::vector<unsigned> tr_off;
     std::vector<double> tr_fit;
+    std::vector<float> tr_fit32;
+    std::vector<unsigned> tr_off64, tr_off32;
+    auto fit = [&](int j, int k, int c) {
+        const int lo = std::min(j, k), hi = std::max(j, k);
+        return hi < ns ? h.dif_full[((size_t)lo * ns + hi) * 4 + c] : 0.0;
+    };
     for (int r = 0; r < tr_rounds; ++r) {
         std::vector<int> circ(n2);
         circ[0] = 0;
         for (int q = 1; q < n2; ++q) circ[q] = 1 + (q - 1 + r) % (n2 - 1);
-        for (int q = 0; q < tr_slots; ++q) {
-            int j = circ[q], k = circ[n2 - 1 - q];
-            if (j > k) std::swap(j, k);
+        std::vector<std::pair<int, int>> pr;
+        for (int q = 0; q < tr_slots; ++q) pr.emplace_back(circ[q], circ[n2 - 1 - q]);
+        const auto oa = order_round_pairs(pr, wa);
+        const auto ob = wb == wa ? oa : order_round_pairs(pr, wb);
+        for (const auto &jk : oa) {
+            const int j = jk.first, k = jk.second;
             tr_jk.push_back(j | k << 16);
-            tr_off.push_back((unsigned)(8 * TT_RS * j) | (unsigned)(8 * TT_RS * k) << 16);
-            for (int c = 0; c < 4; ++c) tr_fit.push_back(k < ns ? h.dif_full[((size_t)j * ns + k) * 4 + c] : 0.0);
+            const unsigned rs = 8u * tt_rs(wa);
+            tr_off64.push_back(rs * j | (rs * k) << 16);
+            for (int c = 0; c < 4; ++c) tr_fit.push_back(fit(j, k, c));
+        }
+        for (const auto &jk : ob) {
+            const int j = jk.first, k = jk.second;
+            const unsigned rs = 8u * tt_rs(wb);
+            tr_off32.push_back(rs * j | (rs * k) << 16);
+            for (int c = 0; c < 4; ++c) tr_fit32.push_back((float)fit(j, k, c));
         }
     }
     // the lane-per-reaction kernels take 64 reactions at a time, and a wavefront pays for a
@@ -897,7 +994,7 @@ crf_status upload_mechanism(crf_mech *mm, int device) {
            oLnA = P.add(h.lnA), oB = P.add(h.b), oTh = P.add(h.theta), oInfo = P.add(h.info),
            oDs = P.add(h.dnu_sum), oRi = P.add(h.ri), oTroe = P.add(h.troe), oEs = P.add(h.eff_sp),
            oEm = P.add(h.eff_m1), oJt = P.add(h.jp_thr), oJr = P.add(h.jp_recs), oJp = P.add(h.jp_prog), oJm = P.add(h.jp_mrx),
-           oTj = P.add(tr_jk), oTo = P.add(tr_off), oTf = P.add(tr_fit), oTf32 = P.add(std::vector<float>(tr_fit.begin(), tr_fit.end())), oRo = P.add(rxn_order), oVar = P.add(h.var),
+           oTj = P.add(tr_jk), oTo = P.add(cat(tr_off64, tr_off32)), oTf = P.add(tr_fit), oTf32 = P.add(tr_fit32), oRo = P.add(rxn_order), oVar = P.add(h.var),
            oVt = P.add(vtab);
     int prev = -1;
     if (hipGetDevice(&prev) != hipSuccess) return fail(CRF_E_DEVICE, "hipGetDevice failed (no HIP device?)");
