@@ -1195,11 +1195,19 @@ __device__ inline void jac_seg_reaction(int r, unsigned sp03, unsigned sp45, int
     } else if (kind == RXN_TROE) {
         const double *tq = TQ + troe;   // [term][falloff reaction]
         const Rt lFc = (Rt)tq[0], dlFc = (Rt)tq[nt], lnkr = (Rt)tq[2 * nt], dlnPr = (Rt)tq[3 * nt], k0 = (Rt)tq[4 * nt];
-        // ln P_r capped where P_r / (1 + P_r) = 1 to the working precision (P_r stays finite)
+        // P_r capped where P_r / (1 + P_r) = 1 to the working precision (P_r stays finite):
+        // in FP64 (k0/kinf) [M] with k0/kinf formed with the point's state (an FP64
+        // exponential fewer on the falloff wavefront), in FP32 e^(ln P_r)
         const Rt lnceil = MIXED ? (Rt)80 : (Rt)700;
         const Rt lnPr0 = lnkr + (Rt)lnMd;
         const Rt lnPr = lnPr0 < lnceil ? lnPr0 : lnceil;
-        const Rt Pr = exp_r<Rt>(lnPr);
+        Rt Pr;
+        if constexpr (MIXED) {
+            Pr = exp_r<Rt>(lnPr);
+        } else {
+            const Rt Pr0 = (Rt)tq[5 * nt] * (Rt)M;
+            Pr = Pr0 < (Rt)1.0e304 ? Pr0 : (Rt)1.0e304;   // about e^700
+        }
         const Rt cc = (Rt)-0.4 - (Rt)0.67 * lFc;
         const Rt nn = (Rt)0.75 - (Rt)1.27 * lFc;
         const Rt lnfloor = MIXED ? (Rt)-85.19 : (Rt)-690.7755278982137;
@@ -1288,7 +1296,7 @@ __device__ inline void jac_seg_reaction(int r, unsigned sp03, unsigned sp45, int
 // Temperature-only terms of the falloff reactions at temperature Tt (lane j = falloff
 // reaction j), in two halves that run on different wavefronts:
 //   jac_seg_troe_fc: log10 Fcent and its T-derivative (TQ[0], TQ[1]);
-//   jac_seg_troe_k:  ln(k0/kinf), its T-derivative and k0 (TQ[2..4]).
+//   jac_seg_troe_k:  ln(k0/kinf), its T-derivative, k0 and, in FP64, k0/kinf (TQ[2..5]).
 template <bool MIXED>
 __device__ inline void jac_seg_troe_fc(int lane, int n_troe, double Tt, const double *TP, double *TQ) {
     using Rt = typename std::conditional<MIXED, float, double>::type;
@@ -1320,6 +1328,7 @@ __device__ inline void jac_seg_troe_k(int lane, int n_troe, double lnT_, double 
         tq[2 * n_troe] = (double)(lnk0 - lnkinf);
         tq[3 * n_troe] = (double)((b0 + th0 * invT) * invT - (bb + th * invT) * invT);
         tq[4 * n_troe] = (double)exp_r<Rt>(lnk0);
+        if constexpr (!MIXED) tq[5 * n_troe] = exp_r<Rt>(lnk0 - lnkinf);
     }
 }
 
