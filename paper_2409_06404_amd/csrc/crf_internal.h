@@ -203,7 +203,8 @@ struct JacRtLayout { size_t total; int rows; };
 inline bool jac_rt_fits(int ns, int nr, bool mixed, JacRtLayout *out = nullptr) {
     const int nsp = ns | 1, n1 = ns + 1, sr = n1 | 1, nrp = (nr + 1) & ~1;
     const size_t fixed = (size_t)(4 * nsp + 4 * (nsp + 1) + nrp) * sizeof(double) +
-                         (size_t)7 * nrp * (mixed ? sizeof(float) : sizeof(double)) + 16;
+                         (size_t)7 * nrp * (mixed ? sizeof(float) : sizeof(double)) + 16 +
+                         16 * sizeof(double);   // per-wavefront partial sums of the state
     const size_t budget = CU_LDS_BYTES - 256, row_bytes = (size_t)(sr + 2) * sizeof(double);
     if (n1 > 512 || fixed + (size_t)16 * row_bytes > budget) return false;
     if (out) {

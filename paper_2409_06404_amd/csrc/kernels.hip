@@ -954,8 +954,8 @@ __global__ __launch_bounds__(KJ_WAVES * 64) void k_jac(DevMech m, int64_t n, con
 // (as in k_jac, without re-evaluating the reactions), and emitted.  The row accumulators
 // are FP64 LDS atomics, so results are reproducible to rounding (not bitwise).
 // LDS: {C, g/RT, h/RT, cp/R} x nsp and {tau, jtc, R, w} x (nsp+1) doubles, the enthalpy of
-// every reaction (nrp doubles), the table (7 x nrp values), rb x sr FP64 accumulators and
-// two per-row scalars of the block.  WAVES is 16 for mechanisms with more reactions than
+// every reaction (nrp doubles), the table (7 x nrp values), rb x sr FP64 accumulators, two
+// per-row scalars of the block and one partial sum per wavefront.  WAVES is 16 for mechanisms with more reactions than
 // 8 wavefronts have lanes, else 8 (two workgroups per compute unit).
 template <bool MIXED, bool VAR, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_jac_rt(DevMech m, int64_t n, const double *__restrict__ T,
@@ -977,10 +977,48 @@ __global__ __launch_bounds__(WAVES * 64) void k_jac_rt(DevMech m, int64_t n, con
     double *S = (double *)(TB + 7 * (size_t)nrp + (MIXED ? (7 * nrp) & 1 : 0));
     Out *J = (Out *)Jv;
     double *AL = S + (size_t)rb * sr, *JT = AL + rb;    // per-row scalars of the current block
+    double *RED = JT + rb;                              // per-wavefront partial sums of Y_k / W_k
+    // the next point's T, p and Y_k (thread k), requested while the current point is computed
+    double nT = 0.0, np = 0.0, ny = 0.0;
+    auto prefetch = [&](int64_t j) {
+        const int64_t jj = j < n ? j : n - 1;
+        nT = T[jj];
+        np = p[jj * ps];
+        ny = tid < ns ? Y[(int64_t)tid * ld + jj] : 0.0;
+    };
+    if ((int64_t)blockIdx.x < n) prefetch(blockIdx.x);
+    for (int e = tid; e < rb * sr; e += NT) S[e] = 0.0;   // the emission zeroes what it reads
     for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
         __syncthreads();
-        const PointState st = load_point<true, true>(m, i, n, T, p, ps, Y, ld, C, G, H, CP, wave == 0);
+        // state, one species per thread: sum Y_k / W_k over the workgroup (wavefront sums added
+        // in a fixed order), then W, rho, C_k = rho Y_k / W_k, Ctot = rho sum Y_k / W_k and NASA-7
+        PointState st;
+        st.valid = true;
+        st.T = nT;
+        st.p = np;
+        const double yw = tid < ns ? ny * m.invW[tid] : 0.0;
+        prefetch(i + gridDim.x);
+        st.lnT = log(st.T);
+        st.invT = 1.0 / st.T;
+        st.lnp0RT = log(m.p0 / (m.R * st.T));
+        const double ws = wave_sum(yw);
+        if (lane == 0) RED[wave] = ws;
         for (int k = tid; k <= ns; k += NT) { TAU[k] = 0.0; JTC[k] = 0.0; RC[k] = 0.0; Wd[k] = 0.0; }
+        __syncthreads();
+        double sy = 0.0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) sy += RED[w];
+        st.Wbar = 1.0 / sy;
+        st.rho = st.p * st.Wbar / (m.R * st.T);
+        st.Ctot = st.rho * sy;
+        if (tid < ns) {
+            double cp, h, sr_;
+            nasa7(m.nasa + 16 * tid, st.T, st.lnT, st.invT, cp, h, sr_);
+            C[tid] = st.rho * yw;
+            G[tid] = h - sr_;
+            H[tid] = h;
+            CP[tid] = cp;
+        }
         const double RT = m.R * st.T;
         __syncthreads();
         // every reaction once: table entries and the row scalars
@@ -1026,8 +1064,6 @@ __global__ __launch_bounds__(WAVES * 64) void k_jac_rt(DevMech m, int64_t n, con
         for (int r0 = 0; r0 < n1; r0 += rb) {
             const int r1 = r0 + rb < n1 ? r0 + rb : n1;
             const bool first = r0 == 0;
-            for (int e = tid; e < (r1 - r0) * sr; e += NT) S[e] = 0.0;
-            __syncthreads();
             for (int x = tid; x < nr; x += NT) {
                 const int r = m.rxn_order[x];
                 const int info = m.info[r];
@@ -1097,10 +1133,30 @@ __global__ __launch_bounds__(WAVES * 64) void k_jac_rt(DevMech m, int64_t n, con
                 if (ph < nph) {
                     const double iw = c > 0 ? m.invW[c - 1] : 0.0;
                     const double rho = st.rho;
-                    for (int row = r0 + ph; row < r1; row += nph) {
-                        const double v = c == 0 ? JT[row - r0]
-                                                : (rho * S[(size_t)(row - r0) * sr + c - 1] + AL[row - r0]) * iw;
-                        Jp[(size_t)row * n1 + c] = (Out)v;
+                    // rows in batches whose LDS reads are issued together (a row past the block's
+                    // end reads its last row and stores nothing); each accumulator is read once,
+                    // by its owner, which zeroes it for the next block
+                    const int nq = (r1 - r0 + nph - 1) / nph;
+                    constexpr int EB = 4;
+                    for (int q0 = 0; q0 < nq; q0 += EB) {
+                        int rr[EB];
+                        double sv[EB], al[EB], jt[EB];
+#pragma unroll
+                        for (int b = 0; b < EB; ++b) {
+                            const int row = r0 + ph + (q0 + b) * nph;
+                            rr[b] = (row < r1 ? row : r1 - 1) - r0;
+                            sv[b] = S[(size_t)rr[b] * sr + (c > 0 ? c - 1 : 0)];
+                            al[b] = AL[rr[b]];
+                            jt[b] = JT[rr[b]];
+                        }
+#pragma unroll
+                        for (int b = 0; b < EB; ++b) {
+                            const double v = c == 0 ? jt[b] : (rho * sv[b] + al[b]) * iw;
+                            if (r0 + ph + (q0 + b) * nph < r1) {
+                                Jp[(size_t)(r0 + rr[b]) * n1 + c] = (Out)v;
+                                if (c > 0) S[(size_t)rr[b] * sr + c - 1] = 0.0;
+                            }
+                        }
                     }
                 }
             }
