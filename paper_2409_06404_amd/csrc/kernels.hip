@@ -1532,6 +1532,10 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
     const int r = ta.x;
     const unsigned sp03 = (unsigned)ta.y, sp45 = (unsigned)ta.z;
     const int dpos = ta.w, xpos = tb.x & 0xffff, n_exc = (tb.x >> 16) & 0xffff, exc0 = tb.y, troe = tb.z, dnu = tb.w;
+    // in the mixed mode, wavefronts holding falloff reactions have the longest rate phase (it
+    // bounds the rate + emission phase): they issue first on their SIMD while it runs (in
+    // FP64 the emitting wavefronts are as long, and the priority gains nothing)
+    const bool falloff_wave = MIXED && __builtin_amdgcn_ballot_w64(r >= 0 && (troe & 0xffff) != 0xffff) != 0;
     double lnA = 0.0, bb = 0.0, th = 0.0;
     const RxnVar var = (VAR && r >= 0) ? m.var[r] : RxnVar{0, 0, 0, 0};
     if (r >= 0) {
@@ -1587,9 +1591,11 @@ __global__ __launch_bounds__(JS_THREADS, 3) void k_jac_seg(DevMech m, int64_t n,
         const double *SP = SP0 + buf * 4 * (ns + 1);
         double *SC = SC0 + buf * 16;
         // ---- B
+        if (falloff_wave) __builtin_amdgcn_s_setprio(2);
         if (r >= 0)
             jac_seg_reaction<MIXED, VAR>(r, sp03, sp45, dpos, xpos, n_exc, exc0, troe, dnu, lnA, bb, th, SP, SC,
                                          TQ0, n_troe, MQ0, EXm, RDd, qb, var, m.vtab, TP);
+        if (falloff_wave) __builtin_amdgcn_s_setprio(0);
         const double Tt = SC[0], rho = SC[2], wbar = SC[3], invT = SC[6];
         // this wavefront's gather records (the same for every point; L1/L2 resident); every
         // wavefront runs DMAX rounds (the plan pads with no-op rounds), so the gather
