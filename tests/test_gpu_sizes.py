@@ -4,7 +4,9 @@
   factorisation (up to 56), so the workgroup-per-point LU runs;
 * 100 species: transport on point tiles with 8 wavefronts per workgroup (two or three
   workgroups fit a compute unit's LDS), the Jacobian's reaction-table kernel;
-* 240 species: in FP64 a point tile's species rows exceed one compute unit's LDS and the
+* 240 species: transport on point tiles with 16 wavefronts per workgroup (one workgroup per
+  compute unit) in both modes;
+* 400 species: in FP64 a point tile's species rows exceed one compute unit's LDS and the
   two-points-per-wavefront transport kernel runs; the mixed mode still uses tiles.
 Point counts are not multiples of the tile size (16)."""
 import numpy as np
@@ -22,6 +24,7 @@ SPECS = {
     60: synth.MechSpec("s60", ("C", "H", "O", "N"), 60, 6, 180, 20, 10, 21),
     100: synth.MechSpec("s100", ("C", "H", "O", "N"), 100, 7, 300, 30, 20, 22),
     240: synth.MechSpec("s240", ("C", "H", "O", "N"), 240, 9, 400, 40, 20, 23),
+    400: synth.MechSpec("s400", ("C", "H", "O", "N"), 400, 10, 600, 40, 20, 24),
 }
 
 
@@ -50,7 +53,7 @@ def _dev(st):
             torch.from_numpy(np.ascontiguousarray(st["Y"])).to(dev).t())
 
 
-@pytest.mark.parametrize("ns", [60, 100, 240])
+@pytest.mark.parametrize("ns", [60, 100, 240, 400])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
 def test_transport_sizes(crf, mechs, ns, prec, tol):
     g, om, _ = mechs[ns]
