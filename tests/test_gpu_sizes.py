@@ -7,7 +7,10 @@
 * 240 species: transport on point tiles with 16 wavefronts per workgroup (one workgroup per
   compute unit) in both modes;
 * 400 species: in FP64 a point tile's species rows exceed one compute unit's LDS and the
-  two-points-per-wavefront transport kernel runs; the mixed mode still uses tiles.
+  two-points-per-wavefront transport kernel runs; the mixed mode still uses tiles;
+* 120 species with about 2 500 and 5 000 reactions: the reaction table exceeds the LDS, and
+  the Jacobian's row-block kernel runs (in FP64 only for the first, whose FP32 table still
+  fits in the mixed mode).
 Point counts are not multiples of the tile size (16)."""
 import numpy as np
 import pytest
@@ -85,6 +88,40 @@ def test_jacobian_sizes(crf, mechs, ns, prec, tol):
     err = jac_scaled_error(Jg, Jr, G, st["T"], st["Y"].T, floor=1e-10 if prec == "mixed" else 0.0)
     print(f"  scaled error {err.max():.2e}", flush=True)
     assert err.max() <= tol
+
+
+ROW_BLOCK = {
+    "rb2500": synth.MechSpec("rb2500", ("C", "H", "O", "N"), 120, 8, 2400, 60, 30, 31),
+    "rb5000": synth.MechSpec("rb5000", ("C", "H", "O", "N"), 120, 8, 5000, 60, 30, 31),
+}
+
+
+@pytest.mark.parametrize("name", ["rb2500", "rb5000"])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_jacobian_row_blocks(crf, mech_dir, name, prec, tol):
+    """Mechanisms whose reaction table does not fit: J and the fused w against the oracle on a
+    ragged point count."""
+    path = synth.write_mechanism(ROW_BLOCK[name], str(mech_dir / f"{name}.mech"))
+    g = crf.Mechanism(path, device=0)
+    om = oracle.read_mechanism(path)
+    plan = g.jac_plan
+    row_block = plan.startswith("row-block") or (prec == "fp64" and "row-block in FP64" in plan)
+    assert row_block or (name == "rb2500" and prec == "mixed"), plan
+    st = synth.state_c0(om.n_species, n=13, seed=33)
+    T, p, Y = _dev(st)
+    print(f"jacobian {name} ({om.n_reactions} reactions) {prec}: plan {plan}", flush=True)
+    J, w = crf.wdot_jac(g, T, p, Y, prec)
+    torch.cuda.synchronize()
+    Jr, G = oracle.jacobian(om, st["T"], st["p"], st["Y"].T, return_gross=True)
+    Jg = J.double().cpu().numpy()
+    if prec == "mixed":
+        Jg, Jr = fp32_range_split(Jg, Jr)
+    err = jac_scaled_error(Jg, Jr, G, st["T"], st["Y"].T, floor=1e-10 if prec == "mixed" else 0.0)
+    ref = oracle.production_rates(om, st["T"], st["p"], st["Y"].T)
+    ew = np.max(np.abs(w.cpu().numpy() - ref["wdot"]) / (ref["turnover"] + np.abs(ref["wdot"])))
+    print(f"  scaled error {err.max():.2e}, w {ew:.2e}", flush=True)
+    g.close()
+    assert err.max() <= tol and ew <= tol
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
