@@ -256,11 +256,12 @@ inline size_t tile_transport_lds(int rows, bool mixed, int W) {
     return (size_t)rows * tt_rs(W) * (2 * sizeof(double) + (mixed ? sizeof(float) : sizeof(double))) +
            (size_t)(64 + 2 * TT_P + 4 * W * TT_P) * sizeof(double);
 }
-// Wavefronts per tile workgroup: 4 while four or more workgroups fit a compute unit's LDS,
-// else 8 (two or three) or 16 (one); 0 if the tile does not fit (the species-per-lane kernel).
+// Wavefronts per tile workgroup: 4 while four or more such workgroups fit a compute unit's
+// LDS, else 8 while two or three do, else 16 (one); each width judged with its own row
+// stride; 0 if the tile does not fit (the species-per-lane kernel).
 inline int tile_transport_waves(int rows, bool mixed) {
-    const int fit = (int)(CU_LDS_BYTES / tile_transport_lds(rows, mixed, 4));
-    const int W = fit >= 4 ? 4 : (fit >= 2 ? 8 : 16);
+    auto fit = [&](int W) { return (int)(CU_LDS_BYTES / tile_transport_lds(rows, mixed, W)); };
+    const int W = fit(4) >= 4 ? 4 : (fit(8) >= 2 ? 8 : 16);
     const bool fits = tile_transport_lds(rows, mixed, W) <= (size_t)CU_LDS_BYTES;
     return fits && 8 * tt_rs(W) * rows <= 0xffff ? W : 0;   // 16-bit row offsets
 }
